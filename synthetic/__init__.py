@@ -1,0 +1,91 @@
+"""Seeded synthetic inputs shared by the CPU oracle, the tests and the bench.
+
+This module holds no arithmetic of the method itself: it only draws the
+random numbers the workloads are made of, so that the oracle and the HIP path
+see bit-identical inputs.
+
+Workload recipe (paper, Sec. 5 "Results"): the auxiliary field sigma is drawn
+iid uniform on [-pi, pi] per space-time site; right-hand sides are complex
+Gaussian vectors (Re and Im iid N(0, 1/2), the heat-bath law exp(-eta^H eta)).
+All generators use numpy's PCG64 (``numpy.random.default_rng``).
+
+Array layouts (C order):
+  sigma : float64 [ntau][nx][nx][nx]
+  rhs   : complex128 [nrhs][ntau][nx][nx][nx]
+"""
+from __future__ import annotations
+
+import numpy as np
+
+__all__ = [
+    "sigma_field",
+    "gaussian_rhs",
+    "gaussian_momenta",
+    "batched_problem_shapes",
+    "sample_sites",
+    "WORKLOADS",
+]
+
+
+def sigma_field(nx: int, ntau: int, seed: int) -> np.ndarray:
+    """Auxiliary field, iid uniform on [-pi, pi] per site (paper, Sec. 5)."""
+    rng = np.random.default_rng(seed)
+    return rng.uniform(-np.pi, np.pi, size=(ntau, nx, nx, nx))
+
+
+def gaussian_rhs(nx: int, ntau: int, seeds) -> np.ndarray:
+    """Complex Gaussian right-hand sides, one seed per RHS.
+
+    Re and Im are iid N(0, 1/2) so that the density is proportional to
+    exp(-|eta|^2), the pseudofermion heat-bath law (paper, Sec. 1).
+    """
+    seeds = list(seeds)
+    out = np.empty((len(seeds), ntau, nx, nx, nx), dtype=np.complex128)
+    for i, s in enumerate(seeds):
+        rng = np.random.default_rng(s)
+        re = rng.standard_normal((ntau, nx, nx, nx))
+        im = rng.standard_normal((ntau, nx, nx, nx))
+        out[i] = (re + 1j * im) / np.sqrt(2.0)
+    return out
+
+
+def gaussian_momenta(nx: int, ntau: int, seed: int) -> np.ndarray:
+    """MD momenta pi ~ N(0, 1) per site (paper, Sec. 1, MD Hamiltonian)."""
+    rng = np.random.default_rng(seed)
+    return rng.standard_normal((ntau, nx, nx, nx))
+
+
+def batched_problem_shapes(count: int = 64, seed: int = 4000):
+    """Uneven lattice shapes for the batched workload.
+
+    Nx drawn from {6, 8, 10, 12}, Ntau from {80, 120, ..., 320}.
+    Returns a list of (nx, ntau) tuples.
+    """
+    rng = np.random.default_rng(seed)
+    nxs = rng.choice([6, 8, 10, 12], size=count)
+    nts = rng.choice(np.arange(80, 321, 40), size=count)
+    return [(int(a), int(b)) for a, b in zip(nxs, nts)]
+
+
+def sample_sites(n_sites: int, count: int, seed: int) -> np.ndarray:
+    """Distinct flat site indices drawn without replacement."""
+    rng = np.random.default_rng(seed)
+    return np.sort(rng.choice(n_sites, size=count, replace=False))
+
+
+# Named workloads (seeds and shapes); physics tau = 0.05, g = 5.0 throughout.
+WORKLOADS = {
+    # plain FP64 method, dense-LU checkable
+    "lattice_4x40": dict(nx=4, ntau=40, sigma_seed=1001, rhs_seeds=[1002]),
+    # preconditioner grid, 4 RHS
+    "lattice_8x160": dict(nx=8, ntau=160, sigma_seed=2001,
+                          rhs_seeds=[2002, 2003, 2004, 2005]),
+    # precision comparison at Nx=16, Ntau=400, 8 RHS
+    "lattice_16x400": dict(nx=16, ntau=400, sigma_seed=3001,
+                           rhs_seeds=list(range(3002, 3010))),
+    # force / molecular dynamics at Nx=12, Ntau=200
+    "lattice_12x200": dict(nx=12, ntau=200, sigma_seed=5001, eta_seed=5002,
+                           site_seed=5003, momentum_seed=5004),
+}
+TAU = 0.05
+G_COUPLING = 5.0
