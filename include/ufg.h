@@ -1,0 +1,230 @@
+/*
+ * ufg.h -- C ABI of the MI355X (gfx950) library for the unitary-Fermi-gas
+ * fermion matrix of Ten, Drut and Laehde, "Preconditioning the
+ * non-relativistic many-fermion problem" (arXiv:1008.3647).
+ *
+ * The operator (paper, Sec. 1, Eq. MatrixM): M[sigma] is block cyclic over
+ * Ntau time slices with unit diagonal blocks, -B_j on the block sub-diagonal
+ * and +B_{Ntau} in the top-right corner, B_j = exp(-tau K)(1 + A sin sigma_j),
+ * A = sqrt(2) sqrt(exp(tau g) - 1), E(k) = k^2/2 (hbar = m = 1) on the momenta
+ * k_i = 2 pi n_i / Nx. M is real, so M^dagger = M^T.
+ *
+ * Conventions shared by every entry point
+ *   - Vectors are complex, interleaved (re, im), C order [nrhs][Ntau][Nx][Nx][Nx]
+ *     (x fastest). Element type is complex64 (float2) or complex128 (double2)
+ *     as fixed by the lattice's dtype; "mixed" solves take complex128.
+ *   - Every vector and field pointer is a DEVICE pointer owned by the caller;
+ *     it must stay valid until the call's work has completed on the stream.
+ *   - Work is enqueued on the lattice's HIP stream. apply_* and
+ *     force_dS_dsigma are asynchronous; set_aux_field and solve_* return after
+ *     their work has completed.
+ *   - Return value: 0 = success; negative = caller or system error
+ *     (UFG_EINVAL, UFG_ENOMEM, UFG_EHIP); positive = numerical outcome of a
+ *     solve (UFG_NOT_CONVERGED, UFG_BREAKDOWN), in which case x holds the last
+ *     iterate and the stats are filled. ufg_last_error() describes the last
+ *     failure of the calling thread.
+ */
+#ifndef UFG_H
+#define UFG_H
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct ufg_lattice_s* ufg_lattice; /* opaque, owned by the library */
+
+enum { UFG_C64 = 0, UFG_C128 = 1 };
+
+enum {
+  UFG_OK = 0,
+  UFG_EINVAL = -1,
+  UFG_ENOMEM = -2,
+  UFG_EHIP = -3,
+  UFG_NOT_CONVERGED = 1,
+  UFG_BREAKDOWN = 2
+};
+
+/* Operators a solve or preconditioner refers to. */
+enum {
+  UFG_OP_M = 0,        /* M x = b                                           */
+  UFG_OP_MDAG = 1,     /* M^dagger x = b                                    */
+  UFG_OP_TWO_STEP = 2, /* M^dagger y = b then M x = y (paper, Eq. 2)        */
+  UFG_OP_Q = 3         /* Q = M^dagger M (paper, Eq. 1)                     */
+};
+
+/* Preconditioner kinds (paper, Secs. 2-4). */
+enum { UFG_PC_NONE = 0, UFG_PC_CHEB = 1, UFG_PC_SCA = 2, UFG_PC_WCE = 3 };
+
+/*
+ * Preconditioner description.
+ *   CHEB (Sec. 2): P(Q^) = c prod_k (Q^ - z_k), Q^ = Q / lam_max, degree 2n =
+ *        `degree` (a power of two: the factors are applied in bit-reversal
+ *        order), spectrum assumed in [eps, 1]. lam_max > 0: used as given;
+ *        lam_max == 0: the bound (1 + max|1 + A sin sigma|)^2 >= ||Q||;
+ *        lam_max < 0: 30 power iterations on Q, times 1.05.
+ *   SCA  (Sec. 4): (L^dagger D L)^{-1}, shift `alpha` (> 0).
+ *   WCE  (Sec. 3): W_d = sum_{m<=d} w_m (-A M0^{-1} M1)^m M0^{-1}, d =
+ *        `wce_order` (0..8); w_m = 1, or the Euler weights of Sec. 3.1 with
+ *        parameter `euler_p` when `euler` != 0 (estimate S_{d,0}).
+ * How a kind acts for each operator (apply_precond's `op`):
+ *   op = UFG_OP_Q   : CHEB P(Q^), SCA (L^dagger D L)^{-1}, WCE W_d W_d^dagger
+ *   op = UFG_OP_M   : WCE W_d;          CHEB/SCA  P M^dagger  (extension)
+ *   op = UFG_OP_MDAG: WCE W_d^dagger;   CHEB/SCA  M P         (extension)
+ */
+typedef struct {
+  int kind;
+  int degree;
+  double eps;
+  double lam_max;
+  double alpha;
+  int wce_order;
+  int euler;
+  double euler_p;
+} ufg_precond;
+
+/*
+ * Solve options.
+ *   tol        stop when every RHS has ||b - A x|| <= tol ||b|| (true residual,
+ *              recomputed in FP64 at the end); x_0 = 0 unless use_x0.
+ *   maxit      iteration cap per solve step (paper: 10,000).
+ *   mixed      0: every vector in the lattice dtype. 1: complex64 inner Krylov
+ *              iteration with FP64 reliable updates of x and r = b - A x and
+ *              FP64 reductions; b and x are complex128 (lattice dtype C128).
+ *   delta      reliable-update trigger: update when the inner residual has
+ *              fallen below delta times its maximum since the last update.
+ *   check_every  iterations between host convergence checks (>= 1).
+ */
+typedef struct {
+  double tol;
+  int maxit;
+  int mixed;
+  double delta;
+  int check_every;
+  int use_x0;
+} ufg_solve_opts;
+
+/* Solve statistics (worst case over the right-hand sides). */
+typedef struct {
+  int iters[2];              /* iterations of step 1 / step 2 (CG: [0] only)  */
+  long long mv;              /* applications of M or M^dagger (any precision) */
+  long long m0inv;           /* applications of M0^{-1} or its adjoint        */
+  long long sca_sweeps;      /* SCA forward+backward sweeps                   */
+  long long reliable_updates;
+  double relres[2];          /* true ||b - A x|| / ||b|| per step             */
+  double relres_normal;      /* ||b - M^dagger M x|| / ||b|| (two-step, CG)   */
+  double seconds;            /* wall time of the call                         */
+  double paper_mv;           /* MV count under the paper's cost model         */
+  int status;
+} ufg_solve_stats;
+
+/*
+ * create_lattice -- allocate a lattice handle for an Nx^3 x Ntau lattice.
+ *   nx: even, 2 <= nx <= 16. ntau >= 2. tau > 0, g >= 0 (A from Sec. 1).
+ *   dtype: UFG_C64 or UFG_C128. hip_stream: a hipStream_t (NULL = default).
+ *   out: receives the handle. The field is zero (sigma = 0) until
+ *   set_aux_field. Errors: UFG_EINVAL (bad size, dtype or pointer),
+ *   UFG_ENOMEM, UFG_EHIP.
+ */
+int create_lattice(int nx, int ntau, double tau, double g, int dtype,
+                   void* hip_stream, ufg_lattice* out);
+
+/* destroy_lattice -- free the handle and all library-owned device memory. */
+int destroy_lattice(ufg_lattice L);
+
+/* set_lattice_stream -- change the stream later work is enqueued on. */
+int set_lattice_stream(ufg_lattice L, void* hip_stream);
+
+/*
+ * set_aux_field -- install sigma (paper, Sec. 1: one real per space-time site).
+ *   sigma_dev: device float64 [Ntau][Nx][Nx][Nx]; copied, so the caller may
+ *   free it afterwards. Derives 1 + A sin sigma, sin sigma, cos sigma in FP64
+ *   and FP32 and the strong-coupling blocks (alpha = 1). Synchronous.
+ */
+int set_aux_field(ufg_lattice L, const double* sigma_dev);
+
+/*
+ * apply_M -- y = M x for nrhs vectors (Eq. MatrixM):
+ *   y_{t+1} = x_{t+1} + s_t e^{-tau K}((1 + A sin sigma_t) x_t),
+ *   s_t = -1 (t < Ntau-1), +1 (t = Ntau-1; antiperiodic corner).
+ *   x, y: device, lattice dtype, must not alias. Asynchronous.
+ */
+int apply_M(ufg_lattice L, const void* x, void* y, int nrhs);
+
+/*
+ * apply_Mdag -- y = M^dagger x = M^T x (Sec. 1: M is real):
+ *   y_t = x_t + s_t (1 + A sin sigma_t) e^{-tau K} x_{t+1}.  Asynchronous.
+ */
+int apply_Mdag(ufg_lattice L, const void* x, void* y, int nrhs);
+
+/*
+ * apply_precond -- y = K^{-1} x for the preconditioner `p` acting on operator
+ *   `op` (table at ufg_precond). x, y: device, lattice dtype, no aliasing.
+ *   Synchronous only when a Chebyshev lam_max has to be estimated first.
+ */
+int apply_precond(ufg_lattice L, const ufg_precond* p, int op, const void* x,
+                  void* y, int nrhs);
+
+/*
+ * solve_cg_normal -- x = (M^dagger M)^{-1} b by (preconditioned) CG
+ *   (paper, Eqs. 1 and 3). p may be NULL (no preconditioner); p->kind is any
+ *   kind (WCE acts as W_d W_d^dagger). b, x: device, nrhs vectors; with
+ *   o->mixed, complex128. st may be NULL.
+ */
+int solve_cg_normal(ufg_lattice L, const ufg_precond* p, const void* b,
+                    void* x, int nrhs, const ufg_solve_opts* o,
+                    ufg_solve_stats* st);
+
+/*
+ * solve_bicgstab -- BiCGStab (van der Vorst, right preconditioned) for
+ *   op = UFG_OP_M (M x = b), UFG_OP_MDAG (M^dagger x = b) or UFG_OP_TWO_STEP
+ *   (M^dagger y = b, then M x = y; paper, Eq. 2). Iterations of the two steps
+ *   are reported separately in st->iters.
+ */
+int solve_bicgstab(ufg_lattice L, const ufg_precond* p, int op, const void* b,
+                   void* x, int nrhs, const ufg_solve_opts* o,
+                   ufg_solve_stats* st);
+
+/*
+ * solve_batched -- nprob independent two-step BiCGStab solves, one lattice
+ *   each (lattices may differ in Nx and Ntau), run by one persistent kernel
+ *   per phase from a shared work table; nrhs[i] right-hand sides per problem.
+ *   b[i], x[i]: device complex128 vectors of lattice i (mixed precision is
+ *   taken from o->mixed). p: NULL or UFG_PC_NONE. st: array of nprob stats
+ *   (may be NULL). Returns the worst status.
+ */
+int solve_batched(const ufg_lattice* Ls, int nprob, const void* const* b,
+                  void* const* x, const int* nrhs, const ufg_precond* p,
+                  const ufg_solve_opts* o, ufg_solve_stats* st);
+
+/*
+ * force_dS_dsigma -- gradient of S = sum_r phi_r^dagger (M^dagger M)^{-1} phi_r
+ *   (paper, Sec. 1) given X_r = (M^dagger M)^{-1} phi_r and y_r = M X_r:
+ *   grad(n,t) = -2 A cos sigma(n,t) s_t sum_r Re[X_r,t(n) conj((e^{-tau K} y_r,t+1)(n))].
+ *   X, y: device, lattice dtype, nrhs vectors. grad_dev: device float64 [Ntau][Nx^3],
+ *   overwritten. Asynchronous.
+ */
+int force_dS_dsigma(ufg_lattice L, const void* X, const void* y, int nrhs,
+                    double* grad_dev);
+
+/* lattice_info -- nx, ntau, dtype, A of a handle (host pointers, any may be NULL). */
+int lattice_info(ufg_lattice L, int* nx, int* ntau, int* dtype, double* A);
+
+/* ufg_last_error -- message for the last failing call on this thread. */
+const char* ufg_last_error(void);
+
+/*
+ * Host helpers (no device work; usable without a GPU):
+ *   ufg_cheb_roots: the 2n roots z_k (re, im interleaved into out[2*degree]) in
+ *     application (bit-reversal) order and the per-factor constant
+ *     c^{1/(2n)} (out_c[2]). Returns UFG_EINVAL unless degree is a power of two.
+ *   ufg_euler_weights: the weights w_0..w_d of Sec. 3.1 (out[d+1]).
+ *   ufg_transfer_matrix: the Nx x Nx factor T of e^{-tau K} (out[nx*nx]).
+ */
+int ufg_cheb_roots(int degree, double eps, double* out, double* out_c);
+int ufg_euler_weights(int order, double p, double* out);
+int ufg_transfer_matrix(int nx, double tau, double* out);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* UFG_H */

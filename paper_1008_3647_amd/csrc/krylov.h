@@ -1,0 +1,83 @@
+// Device state and kernel launchers of the Krylov solvers.
+#pragma once
+
+#include "ufg_internal.h"
+
+namespace ufg {
+
+constexpr int kVecBlocks = 1024;  // max blocks per rhs of the vector kernels
+
+// Scalars of one right-hand side, resident on the device.
+struct RhsState {
+  double2 rho, rho_old, alpha, omega;  // BiCGStab; CG uses rho = <r,z>, alpha, omega = beta
+  double r2;     // |r|^2 of the iterated residual
+  double b2;     // |b|^2
+  double maxr2;  // largest |r|^2 since the last reliable update
+  double tol2;   // tol^2 |b|^2
+  int iters, updates, conv, status;
+};
+
+struct KrylovParams {
+  double tol;
+  double delta2;  // reliable-update threshold squared
+  int mixed;
+  int bicg;       // 1: BiCGStab (rho = <rhat, r> refreshed at updates)
+  int unprec;     // CG without preconditioner: <r, z> = |r|^2
+};
+
+struct KrylovState {
+  int nrhs = 0;
+  RhsState* st = nullptr;
+  int* active = nullptr;
+  int* update = nullptr;
+  int* restart = nullptr;
+  double* part = nullptr;  // [nrhs][nblk][4]
+  KrylovParams prm{};
+};
+
+enum FinOp {
+  FIN_INIT_B = 0,
+  FIN_INIT_R,
+  FIN_ALPHA,
+  FIN_OMEGA,
+  FIN_RHO,
+  FIN_UPDATE,
+  FIN_RESTART,
+  FIN_CG_ALPHA,
+  FIN_CG_R,
+  FIN_CG_BETA,
+  FIN_CG_INIT_RZ,
+  FIN_NORM
+};
+
+int vec_blocks(long long n);
+
+template <typename R>
+int k_bicg_p(const Lattice& L, const C2<R>* r, C2<R>* p, const C2<R>* v, const KrylovState& K);
+template <typename R>
+int k_bicg_s(const Lattice& L, const C2<R>* r, const C2<R>* v, C2<R>* s, const KrylovState& K);
+template <typename R>
+int k_bicg_xr(const Lattice& L, C2<R>* x, const C2<R>* phat, const C2<R>* shat, const C2<R>* s,
+              const C2<R>* t, C2<R>* r, const C2<R>* rhat, const KrylovState& K);
+template <typename R>
+int k_reduce(const Lattice& L, const C2<R>* a, const C2<R>* b, int mode, const int* gate,
+             const KrylovState& K);
+template <typename R>
+int k_axpby(const Lattice& L, double2 a, const C2<R>* x, double2 b, C2<R>* y, int nrhs,
+            const int* gate);
+template <typename RI, typename RO>
+int k_convert(const Lattice& L, const C2<RI>* in, C2<RO>* out, int nrhs, const int* gate);
+int k_promote(const Lattice& L, double2* x64, float2* x32, int nrhs, const int* gate);
+int k_demote(const Lattice& L, const double2* r64, float2* r32, const float2* rhat,
+             const KrylovState& K, const int* gate);
+template <typename R>
+int k_cg_xr(const Lattice& L, C2<R>* x, const C2<R>* p, C2<R>* r, const C2<R>* w,
+            const KrylovState& K);
+template <typename R>
+int k_cg_p(const Lattice& L, const C2<R>* z, C2<R>* p, const KrylovState& K);
+template <typename R>
+int k_restart(const Lattice& L, const C2<R>* r, C2<R>* rhat, C2<R>* p, C2<R>* v,
+              const KrylovState& K);
+int k_finalize(const Lattice& L, int op, int nblk, const int* gate, const KrylovState& K);
+
+}  // namespace ufg

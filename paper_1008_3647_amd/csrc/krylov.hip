@@ -1,0 +1,508 @@
+// Krylov vector kernels for CG and BiCGStab on [nrhs][N] complex vectors.
+//
+// Every right-hand side runs its own iteration: its scalars (rho, alpha,
+// omega, ...) live on the device in RhsState and are updated by one-block
+// "finalize" kernels that sum per-block partials in a fixed order (FP64, so
+// results are reproducible run to run). Flags gate whole right-hand sides:
+// a kernel block whose rhs is not active returns at once, which lets the
+// host enqueue the same sequence every iteration without reading anything
+// back. Reductions always accumulate in FP64, whatever the vector type.
+#include "krylov.h"
+
+namespace ufg {
+namespace {
+
+template <typename R>
+__device__ __forceinline__ C2<R> c2(R a, R b) {
+  C2<R> c;
+  c.x = a;
+  c.y = b;
+  return c;
+}
+
+__device__ __forceinline__ double2 cmul(double2 a, double2 b) {
+  return double2{a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x};
+}
+__device__ __forceinline__ double2 cdiv(double2 a, double2 b) {
+  const double d = b.x * b.x + b.y * b.y;
+  return double2{(a.x * b.x + a.y * b.y) / d, (a.y * b.x - a.x * b.y) / d};
+}
+
+__device__ __forceinline__ double wsum(double v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+  return v;
+}
+
+// Block-reduce 4 doubles (blockDim.x == 256) into out[0..3] (thread 0).
+__device__ void bsum4(double a0, double a1, double a2, double a3, double* out) {
+  __shared__ double sm[4][4];
+  a0 = wsum(a0);
+  a1 = wsum(a1);
+  a2 = wsum(a2);
+  a3 = wsum(a3);
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  if (lane == 0) {
+    sm[wid][0] = a0;
+    sm[wid][1] = a1;
+    sm[wid][2] = a2;
+    sm[wid][3] = a3;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double s[4] = {0, 0, 0, 0};
+    for (int w = 0; w < 4; ++w)
+      for (int j = 0; j < 4; ++j) s[j] += sm[w][j];
+    for (int j = 0; j < 4; ++j) out[j] = s[j];
+  }
+}
+
+#define KR_LOOP(n) \
+  for (long long i = blockIdx.x * 256ll + threadIdx.x; i < (n); i += (long long)gridDim.x * 256)
+
+// p = r + beta (p - omega v), beta = (rho / rho_old)(alpha / omega)
+template <typename R>
+__global__ void __launch_bounds__(256) bicg_p_kernel(const C2<R>* r, C2<R>* p, const C2<R>* v,
+                                                     const RhsState* st, const int* active,
+                                                     long long n) {
+  const int k = blockIdx.y;
+  if (!active[k]) return;
+  const RhsState s = st[k];
+  const double2 beta = cmul(cdiv(s.rho, s.rho_old), cdiv(s.alpha, s.omega));
+  const R br = R(beta.x), bi = R(beta.y), wr = R(s.omega.x), wi = R(s.omega.y);
+  const long long off = (long long)k * n;
+  KR_LOOP(n) {
+    const C2<R> rv = r[off + i], pv = p[off + i], vv = v[off + i];
+    const R dx = pv.x - (wr * vv.x - wi * vv.y);
+    const R dy = pv.y - (wr * vv.y + wi * vv.x);
+    p[off + i] = c2<R>(rv.x + br * dx - bi * dy, rv.y + br * dy + bi * dx);
+  }
+}
+
+// s = r - alpha v
+template <typename R>
+__global__ void __launch_bounds__(256) bicg_s_kernel(const C2<R>* r, const C2<R>* v, C2<R>* s,
+                                                     const RhsState* st, const int* active,
+                                                     long long n) {
+  const int k = blockIdx.y;
+  if (!active[k]) return;
+  const double2 al = st[k].alpha;
+  const R ar = R(al.x), ai = R(al.y);
+  const long long off = (long long)k * n;
+  KR_LOOP(n) {
+    const C2<R> rv = r[off + i], vv = v[off + i];
+    s[off + i] = c2<R>(rv.x - (ar * vv.x - ai * vv.y), rv.y - (ar * vv.y + ai * vv.x));
+  }
+}
+
+// x += alpha phat + omega shat; r = s - omega t; partials <rhat, r>, |r|^2
+template <typename R>
+__global__ void __launch_bounds__(256) bicg_xr_kernel(C2<R>* x, const C2<R>* phat,
+                                                      const C2<R>* shat, const C2<R>* s,
+                                                      const C2<R>* t, C2<R>* r, const C2<R>* rhat,
+                                                      const RhsState* st, const int* active,
+                                                      long long n, double* part) {
+  const int k = blockIdx.y;
+  if (!active[k]) return;
+  const RhsState q = st[k];
+  const R ar = R(q.alpha.x), ai = R(q.alpha.y), wr = R(q.omega.x), wi = R(q.omega.y);
+  const long long off = (long long)k * n;
+  double d0 = 0, d1 = 0, d2 = 0;
+  KR_LOOP(n) {
+    const long long j = off + i;
+    const C2<R> pv = phat[j], sv = shat[j], ss = s[j], tv = t[j], h = rhat[j];
+    C2<R> xv = x[j];
+    xv.x += (ar * pv.x - ai * pv.y) + (wr * sv.x - wi * sv.y);
+    xv.y += (ar * pv.y + ai * pv.x) + (wr * sv.y + wi * sv.x);
+    x[j] = xv;
+    const C2<R> rv = c2<R>(ss.x - (wr * tv.x - wi * tv.y), ss.y - (wr * tv.y + wi * tv.x));
+    r[j] = rv;
+    d0 += double(h.x) * rv.x + double(h.y) * rv.y;
+    d1 += double(h.x) * rv.y - double(h.y) * rv.x;
+    d2 += double(rv.x) * rv.x + double(rv.y) * rv.y;
+  }
+  bsum4(d0, d1, d2, 0.0, part + ((long long)k * gridDim.x + blockIdx.x) * 4);
+}
+
+// Generic reductions: mode 0 |a|^2 -> [2]; mode 1 <a, b> -> [0,1];
+// mode 2 <a, b> -> [0,1] and |a|^2 -> [2]; mode 3 <b, a> -> [0,1] and |a|^2 -> [2].
+template <typename R>
+__global__ void __launch_bounds__(256) reduce_kernel(const C2<R>* a, const C2<R>* b, int mode,
+                                                     const int* gate, long long n, double* part) {
+  const int k = blockIdx.y;
+  if (gate && !gate[k]) return;
+  const long long off = (long long)k * n;
+  double d0 = 0, d1 = 0, d2 = 0;
+  KR_LOOP(n) {
+    const C2<R> av = a[off + i];
+    if (mode != 0) {
+      const C2<R> bv = b[off + i];
+      d0 += double(av.x) * bv.x + double(av.y) * bv.y;
+      d1 += (mode == 3) ? double(bv.x) * av.y - double(bv.y) * av.x
+                        : double(av.x) * bv.y - double(av.y) * bv.x;
+    }
+    if (mode != 1) d2 += double(av.x) * av.x + double(av.y) * av.y;
+  }
+  bsum4(d0, d1, d2, 0.0, part + ((long long)k * gridDim.x + blockIdx.x) * 4);
+}
+
+// y = a * x + b * y (complex scalars, same for every rhs); gate may be null.
+template <typename R>
+__global__ void __launch_bounds__(256) axpby_kernel(double2 a, const C2<R>* x, double2 b, C2<R>* y,
+                                                    const int* gate, long long n) {
+  const int k = blockIdx.y;
+  if (gate && !gate[k]) return;
+  const long long off = (long long)k * n;
+  const R ar = R(a.x), ai = R(a.y), br = R(b.x), bi = R(b.y);
+  KR_LOOP(n) {
+    const C2<R> xv = x[off + i], yv = y[off + i];
+    y[off + i] = c2<R>(ar * xv.x - ai * xv.y + br * yv.x - bi * yv.y,
+                       ar * xv.y + ai * xv.x + br * yv.y + bi * yv.x);
+  }
+}
+
+template <typename RI, typename RO>
+__global__ void __launch_bounds__(256) convert_kernel(const C2<RI>* in, C2<RO>* out,
+                                                      const int* gate, long long n) {
+  const int k = blockIdx.y;
+  if (gate && !gate[k]) return;
+  const long long off = (long long)k * n;
+  KR_LOOP(n) {
+    const C2<RI> v = in[off + i];
+    out[off + i] = c2<RO>(RO(v.x), RO(v.y));
+  }
+}
+
+// Mixed precision: x64 += x32, x32 = 0 (gated by the update flag).
+__global__ void __launch_bounds__(256) promote_kernel(double2* x64, float2* x32, const int* gate,
+                                                      long long n) {
+  const int k = blockIdx.y;
+  if (gate && !gate[k]) return;
+  const long long off = (long long)k * n;
+  KR_LOOP(n) {
+    const float2 v = x32[off + i];
+    double2 w = x64[off + i];
+    w.x += v.x;
+    w.y += v.y;
+    x64[off + i] = w;
+    x32[off + i] = float2{0.f, 0.f};
+  }
+}
+
+// r32 = r64 and partials <rhat, r>, |r64|^2 (gated).
+__global__ void __launch_bounds__(256) demote_kernel(const double2* r64, float2* r32,
+                                                     const float2* rhat, const int* gate,
+                                                     long long n, double* part) {
+  const int k = blockIdx.y;
+  if (gate && !gate[k]) return;
+  const long long off = (long long)k * n;
+  double d0 = 0, d1 = 0, d2 = 0;
+  KR_LOOP(n) {
+    const double2 v = r64[off + i];
+    r32[off + i] = float2{float(v.x), float(v.y)};
+    if (rhat) {
+      const float2 h = rhat[off + i];
+      d0 += double(h.x) * v.x + double(h.y) * v.y;
+      d1 += double(h.x) * v.y - double(h.y) * v.x;
+    }
+    d2 += v.x * v.x + v.y * v.y;
+  }
+  bsum4(d0, d1, d2, 0.0, part + ((long long)k * gridDim.x + blockIdx.x) * 4);
+}
+
+// CG: x += alpha p; r -= alpha w; partial |r|^2.
+template <typename R>
+__global__ void __launch_bounds__(256) cg_xr_kernel(C2<R>* x, const C2<R>* p, C2<R>* r,
+                                                    const C2<R>* w, const RhsState* st,
+                                                    const int* active, long long n, double* part) {
+  const int k = blockIdx.y;
+  if (!active[k]) return;
+  const double2 al = st[k].alpha;
+  const R ar = R(al.x), ai = R(al.y);
+  const long long off = (long long)k * n;
+  double d2 = 0;
+  KR_LOOP(n) {
+    const long long j = off + i;
+    const C2<R> pv = p[j], wv = w[j];
+    C2<R> xv = x[j], rv = r[j];
+    xv.x += ar * pv.x - ai * pv.y;
+    xv.y += ar * pv.y + ai * pv.x;
+    rv.x -= ar * wv.x - ai * wv.y;
+    rv.y -= ar * wv.y + ai * wv.x;
+    x[j] = xv;
+    r[j] = rv;
+    d2 += double(rv.x) * rv.x + double(rv.y) * rv.y;
+  }
+  bsum4(0.0, 0.0, d2, 0.0, part + ((long long)k * gridDim.x + blockIdx.x) * 4);
+}
+
+// CG: p = z + beta p (beta = st.omega slot).
+template <typename R>
+__global__ void __launch_bounds__(256) cg_p_kernel(const C2<R>* z, C2<R>* p, const RhsState* st,
+                                                   const int* active, long long n) {
+  const int k = blockIdx.y;
+  if (!active[k]) return;
+  const double2 be = st[k].omega;
+  const R br = R(be.x), bi = R(be.y);
+  const long long off = (long long)k * n;
+  KR_LOOP(n) {
+    const C2<R> zv = z[off + i], pv = p[off + i];
+    p[off + i] = c2<R>(zv.x + br * pv.x - bi * pv.y, zv.y + br * pv.y + bi * pv.x);
+  }
+}
+
+// BiCGStab restart after a breakdown (rho = 0): rhat = r, p = v = 0.
+template <typename R>
+__global__ void __launch_bounds__(256) restart_kernel(const C2<R>* r, C2<R>* rhat, C2<R>* p,
+                                                      C2<R>* v, const int* gate, long long n) {
+  const int k = blockIdx.y;
+  if (!gate[k]) return;
+  const long long off = (long long)k * n;
+  KR_LOOP(n) {
+    rhat[off + i] = r[off + i];
+    p[off + i] = c2<R>(R(0), R(0));
+    v[off + i] = c2<R>(R(0), R(0));
+  }
+}
+
+// One block per rhs: sum `nblk` partials (fixed order) and apply `op` to the state.
+__global__ void __launch_bounds__(256) finalize_kernel(int op, const double* part, int nblk,
+                                                       RhsState* st, int* active, int* update,
+                                                       int* restart, const int* gate,
+                                                       KrylovParams prm) {
+  const int k = blockIdx.x;
+  if (gate && !gate[k]) return;
+  double s0 = 0, s1 = 0, s2 = 0;
+  for (int b = threadIdx.x; b < nblk; b += 256) {
+    const double* q = part + ((long long)k * nblk + b) * 4;
+    s0 += q[0];
+    s1 += q[1];
+    s2 += q[2];
+  }
+  __shared__ double out[4];
+  bsum4(s0, s1, s2, 0.0, out);
+  if (threadIdx.x != 0) return;
+  s0 = out[0];
+  s1 = out[1];
+  s2 = out[2];
+  RhsState q = st[k];
+  const double2 d01 = double2{s0, s1};
+  switch (op) {
+    case FIN_INIT_B:  // |b|^2
+      q.b2 = s2;
+      q.tol2 = prm.tol * prm.tol * s2;
+      break;
+    case FIN_INIT_R:  // rhat = r: rho = <r, r>, r2
+      q.rho = double2{s2, 0.0};
+      q.rho_old = q.alpha = q.omega = double2{1.0, 0.0};
+      q.r2 = q.maxr2 = s2;
+      q.iters = 0;
+      q.updates = 0;
+      q.conv = (s2 <= q.tol2) ? 1 : 0;
+      active[k] = q.conv ? 0 : 1;
+      update[k] = 0;
+      restart[k] = 0;
+      q.status = 0;
+      break;
+    case FIN_ALPHA:  // alpha = rho / <rhat, v>
+      if (d01.x == 0.0 && d01.y == 0.0) {
+        restart[k] = 1;
+        q.alpha = double2{0.0, 0.0};
+      } else {
+        q.alpha = cdiv(q.rho, d01);
+      }
+      break;
+    case FIN_OMEGA:  // omega = <t, s> / <t, t>
+      q.omega = (s2 > 0.0) ? double2{s0 / s2, s1 / s2} : double2{0.0, 0.0};
+      break;
+    case FIN_RHO: {  // after x, r update: rho_old = rho; rho = <rhat, r>
+      q.rho_old = q.rho;
+      q.rho = d01;
+      q.r2 = s2;
+      q.iters += 1;
+      if (!(s2 == s2) || s2 > 1e300) {  // NaN / overflow: stop this rhs
+        active[k] = 0;
+        q.status = UFG_BREAKDOWN;
+        break;
+      }
+      if (q.omega.x == 0.0 && q.omega.y == 0.0 && s2 > q.tol2) restart[k] = 1;
+      if (s2 <= q.tol2) {
+        update[k] = 1;  // verify with a recomputed residual
+      } else if (prm.mixed && s2 < prm.delta2 * q.maxr2) {
+        update[k] = 1;
+      }
+      if (s2 > q.maxr2) q.maxr2 = s2;
+      if (!update[k] && d01.x == 0.0 && d01.y == 0.0) restart[k] = 1;
+      break;
+    }
+    case FIN_UPDATE:  // reliable update done: r is b - A x
+      q.r2 = s2;
+      q.maxr2 = s2;
+      q.updates += 1;
+      if (prm.bicg) q.rho = d01;
+      update[k] = 0;
+      if (s2 <= q.tol2) {
+        q.conv = 1;
+        active[k] = 0;
+      }
+      break;
+    case FIN_RESTART:  // rhat = r: rho = |r|^2, scalars reset
+      q.rho = double2{q.r2, 0.0};
+      q.rho_old = q.alpha = q.omega = double2{1.0, 0.0};
+      restart[k] = 0;
+      break;
+    case FIN_CG_ALPHA:  // alpha = rz / <p, w>
+      if (d01.x == 0.0 && d01.y == 0.0) {
+        active[k] = 0;
+        q.status = UFG_BREAKDOWN;
+        q.alpha = double2{0.0, 0.0};
+      } else {
+        q.alpha = cdiv(q.rho, d01);
+      }
+      break;
+    case FIN_CG_R:  // |r|^2 after x, r update
+      q.r2 = s2;
+      q.iters += 1;
+      if (!(s2 == s2) || s2 > 1e300) {
+        active[k] = 0;
+        q.status = UFG_BREAKDOWN;
+        break;
+      }
+      if (s2 <= q.tol2) {
+        update[k] = 1;
+      } else if (prm.mixed && s2 < prm.delta2 * q.maxr2) {
+        update[k] = 1;
+      }
+      if (s2 > q.maxr2) q.maxr2 = s2;
+      break;
+    case FIN_CG_BETA: {  // rz_new = <r, z>: beta = rz_new / rz (stored in omega)
+      const double2 rz = prm.unprec ? double2{q.r2, 0.0} : d01;
+      q.omega = (q.rho.x == 0.0 && q.rho.y == 0.0) ? double2{0.0, 0.0} : cdiv(rz, q.rho);
+      q.rho = rz;
+      break;
+    }
+    case FIN_CG_INIT_RZ:  // rz = <r, z>
+      q.rho = prm.unprec ? double2{q.r2, 0.0} : d01;
+      break;
+    case FIN_NORM:  // true residual norm into r2 (no flags)
+      q.r2 = s2;
+      break;
+  }
+  st[k] = q;
+}
+
+inline dim3 vgrid(long long n, int nrhs) {
+  long long nb = (n + 1023) / 1024;
+  if (nb > kVecBlocks) nb = kVecBlocks;
+  if (nb < 1) nb = 1;
+  return dim3((unsigned)nb, (unsigned)nrhs);
+}
+
+}  // namespace
+
+int vec_blocks(long long n) {
+  long long nb = (n + 1023) / 1024;
+  if (nb > kVecBlocks) nb = kVecBlocks;
+  if (nb < 1) nb = 1;
+  return (int)nb;
+}
+
+template <typename R>
+int k_bicg_p(const Lattice& L, const C2<R>* r, C2<R>* p, const C2<R>* v, const KrylovState& K) {
+  hipLaunchKernelGGL((bicg_p_kernel<R>), vgrid(L.N, K.nrhs), dim3(256), 0, L.stream, r, p, v, K.st,
+                     K.active, L.N);
+  return UFG_OK;
+}
+template <typename R>
+int k_bicg_s(const Lattice& L, const C2<R>* r, const C2<R>* v, C2<R>* s, const KrylovState& K) {
+  hipLaunchKernelGGL((bicg_s_kernel<R>), vgrid(L.N, K.nrhs), dim3(256), 0, L.stream, r, v, s, K.st,
+                     K.active, L.N);
+  return UFG_OK;
+}
+template <typename R>
+int k_bicg_xr(const Lattice& L, C2<R>* x, const C2<R>* phat, const C2<R>* shat, const C2<R>* s,
+              const C2<R>* t, C2<R>* r, const C2<R>* rhat, const KrylovState& K) {
+  hipLaunchKernelGGL((bicg_xr_kernel<R>), vgrid(L.N, K.nrhs), dim3(256), 0, L.stream, x, phat, shat,
+                     s, t, r, rhat, K.st, K.active, L.N, K.part);
+  return UFG_OK;
+}
+template <typename R>
+int k_reduce(const Lattice& L, const C2<R>* a, const C2<R>* b, int mode, const int* gate,
+             const KrylovState& K) {
+  hipLaunchKernelGGL((reduce_kernel<R>), vgrid(L.N, K.nrhs), dim3(256), 0, L.stream, a, b, mode,
+                     gate, L.N, K.part);
+  return UFG_OK;
+}
+template <typename R>
+int k_axpby(const Lattice& L, double2 a, const C2<R>* x, double2 b, C2<R>* y, int nrhs,
+            const int* gate) {
+  hipLaunchKernelGGL((axpby_kernel<R>), vgrid(L.N, nrhs), dim3(256), 0, L.stream, a, x, b, y, gate,
+                     L.N);
+  return UFG_OK;
+}
+template <typename RI, typename RO>
+int k_convert(const Lattice& L, const C2<RI>* in, C2<RO>* out, int nrhs, const int* gate) {
+  hipLaunchKernelGGL((convert_kernel<RI, RO>), vgrid(L.N, nrhs), dim3(256), 0, L.stream, in, out,
+                     gate, L.N);
+  return UFG_OK;
+}
+int k_promote(const Lattice& L, double2* x64, float2* x32, int nrhs, const int* gate) {
+  hipLaunchKernelGGL(promote_kernel, vgrid(L.N, nrhs), dim3(256), 0, L.stream, x64, x32, gate, L.N);
+  return UFG_OK;
+}
+int k_demote(const Lattice& L, const double2* r64, float2* r32, const float2* rhat,
+             const KrylovState& K, const int* gate) {
+  hipLaunchKernelGGL(demote_kernel, vgrid(L.N, K.nrhs), dim3(256), 0, L.stream, r64, r32, rhat,
+                     gate, L.N, K.part);
+  return UFG_OK;
+}
+template <typename R>
+int k_cg_xr(const Lattice& L, C2<R>* x, const C2<R>* p, C2<R>* r, const C2<R>* w,
+            const KrylovState& K) {
+  hipLaunchKernelGGL((cg_xr_kernel<R>), vgrid(L.N, K.nrhs), dim3(256), 0, L.stream, x, p, r, w,
+                     K.st, K.active, L.N, K.part);
+  return UFG_OK;
+}
+template <typename R>
+int k_cg_p(const Lattice& L, const C2<R>* z, C2<R>* p, const KrylovState& K) {
+  hipLaunchKernelGGL((cg_p_kernel<R>), vgrid(L.N, K.nrhs), dim3(256), 0, L.stream, z, p, K.st,
+                     K.active, L.N);
+  return UFG_OK;
+}
+template <typename R>
+int k_restart(const Lattice& L, const C2<R>* r, C2<R>* rhat, C2<R>* p, C2<R>* v,
+              const KrylovState& K) {
+  hipLaunchKernelGGL((restart_kernel<R>), vgrid(L.N, K.nrhs), dim3(256), 0, L.stream, r, rhat, p, v,
+                     K.restart, L.N);
+  return UFG_OK;
+}
+int k_finalize(const Lattice& L, int op, int nblk, const int* gate, const KrylovState& K) {
+  hipLaunchKernelGGL(finalize_kernel, dim3(K.nrhs), dim3(256), 0, L.stream, op, K.part, nblk, K.st,
+                     K.active, K.update, K.restart, gate, K.prm);
+  return UFG_OK;
+}
+
+#define INST(R)                                                                                  \
+  template int k_bicg_p<R>(const Lattice&, const C2<R>*, C2<R>*, const C2<R>*,                   \
+                           const KrylovState&);                                                  \
+  template int k_bicg_s<R>(const Lattice&, const C2<R>*, const C2<R>*, C2<R>*,                   \
+                           const KrylovState&);                                                  \
+  template int k_bicg_xr<R>(const Lattice&, C2<R>*, const C2<R>*, const C2<R>*, const C2<R>*,    \
+                            const C2<R>*, C2<R>*, const C2<R>*, const KrylovState&);             \
+  template int k_reduce<R>(const Lattice&, const C2<R>*, const C2<R>*, int, const int*,          \
+                           const KrylovState&);                                                  \
+  template int k_axpby<R>(const Lattice&, double2, const C2<R>*, double2, C2<R>*, int,           \
+                          const int*);                                                           \
+  template int k_cg_xr<R>(const Lattice&, C2<R>*, const C2<R>*, C2<R>*, const C2<R>*,            \
+                          const KrylovState&);                                                   \
+  template int k_cg_p<R>(const Lattice&, const C2<R>*, C2<R>*, const KrylovState&);              \
+  template int k_restart<R>(const Lattice&, const C2<R>*, C2<R>*, C2<R>*, C2<R>*,                \
+                            const KrylovState&);
+INST(float)
+INST(double)
+template int k_convert<float, double>(const Lattice&, const float2*, double2*, int, const int*);
+template int k_convert<double, float>(const Lattice&, const double2*, float2*, int, const int*);
+template int k_convert<double, double>(const Lattice&, const double2*, double2*, int, const int*);
+template int k_convert<float, float>(const Lattice&, const float2*, float2*, int, const int*);
+
+}  // namespace ufg

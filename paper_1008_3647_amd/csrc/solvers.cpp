@@ -1,0 +1,437 @@
+// Krylov solvers of the paper (Sec. 1): CG on the normal equations (Eq. 1,
+// left/"PCG" preconditioning, Eq. 3) and BiCGStab (van der Vorst) for M and
+// M^T, alone or as the two-step solve M^T y = b, M x = y (Eq. 2), right
+// preconditioned so that the iterated residual is that of the original system.
+//
+// Precision modes
+//   plain : every vector in the lattice dtype; the final residual is
+//           recomputed from scratch before a right-hand side is declared
+//           converged ("reliable update" in the working precision).
+//   mixed : complex64 inner iteration; x, b and the true residual stay in
+//           complex128. Whenever the inner residual falls below delta times
+//           its maximum since the last update (Sleijpen & van der Vorst's
+//           reliable updates), x64 += x32, r64 = b - A x64 in FP64, the inner
+//           residual restarts from r64 and the search direction is kept.
+// All scalar arithmetic is FP64 on the device; the host only enqueues kernels
+// and reads the per-rhs "active" flags every check_every iterations.
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstring>
+
+#include "ops.h"
+
+namespace ufg {
+
+namespace {
+
+struct StepResult {
+  int iters = 0;
+  int status = 0;
+  long long updates = 0;
+};
+
+template <typename R>
+struct Inner {
+  C2<R> *x, *r, *rhat, *p, *v, *s, *t, *phat, *shat, *z, *w, *tmp;
+};
+
+template <typename R>
+int inner_vectors(Lattice& L, int nrhs, bool need_pc, bool mixed, C2<R>* x_user, Inner<R>* V) {
+  int rc = 0;
+  C2<R>* slots[12];
+  for (int i = 0; i < 12; ++i) {
+    slots[i] = slot_vec<R>(L, SLOT_SOLVER0 + i, nrhs, &rc);
+    UFG_TRY(rc);
+  }
+  V->x = mixed ? slots[0] : x_user;
+  V->r = slots[1];
+  V->rhat = slots[2];
+  V->p = slots[3];
+  V->v = slots[4];
+  V->s = slots[5];
+  V->t = slots[6];
+  V->phat = need_pc ? slots[7] : V->p;
+  V->shat = need_pc ? slots[8] : V->s;
+  V->z = need_pc ? slots[9] : V->r;
+  V->w = slots[10];
+  V->tmp = slots[11];
+  return UFG_OK;
+}
+
+int all_inactive(Lattice& L, const KrylovState& K, int* host_flags, bool* done) {
+  UFG_HIP(hipMemcpyAsync(host_flags, K.active, sizeof(int) * K.nrhs, hipMemcpyDeviceToHost,
+                         L.stream));
+  UFG_HIP(hipStreamSynchronize(L.stream));
+  *done = true;
+  for (int i = 0; i < K.nrhs; ++i)
+    if (host_flags[i]) *done = false;
+  return UFG_OK;
+}
+
+int read_states(Lattice& L, const KrylovState& K, std::vector<RhsState>* out) {
+  out->resize(K.nrhs);
+  UFG_HIP(hipMemcpyAsync(out->data(), K.st, sizeof(RhsState) * K.nrhs, hipMemcpyDeviceToHost,
+                         L.stream));
+  UFG_HIP(hipStreamSynchronize(L.stream));
+  return UFG_OK;
+}
+
+// Worst relative true residual ||b - A x|| / ||b|| over the rhs, FP64 when RO = double.
+template <typename RO>
+int true_relres(Lattice& L, int op, const C2<RO>* x, const C2<RO>* b, int nrhs, double* worst) {
+  int rc = 0;
+  C2<RO>* res = slot_vec<RO>(L, SLOT_OUTER_T, nrhs, &rc);
+  UFG_TRY(rc);
+  KrylovState K;
+  UFG_TRY(krylov_state(L, nrhs, &K, SLOT_PSTATE));
+  const int nvb = vec_blocks(L.N);
+  if (op == UFG_OP_Q) {
+    C2<RO>* tmp = slot_vec<RO>(L, SLOT_OUTER_R + 3, nrhs, &rc);  // slot 15
+    UFG_TRY(rc);
+    UFG_TRY(q_residual<RO>(L, x, b, tmp, res, nrhs, nullptr));
+  } else {
+    UFG_TRY(op_residual<RO>(L, op, x, b, res, nrhs, nullptr));
+  }
+  UFG_TRY(k_reduce<RO>(L, b, nullptr, 0, nullptr, K));
+  UFG_TRY(k_finalize(L, FIN_INIT_B, nvb, nullptr, K));
+  UFG_TRY(k_reduce<RO>(L, res, nullptr, 0, nullptr, K));
+  UFG_TRY(k_finalize(L, FIN_NORM, nvb, nullptr, K));
+  std::vector<RhsState> st;
+  UFG_TRY(read_states(L, K, &st));
+  double w = 0.0;
+  for (auto& q : st) {
+    const double rr = q.b2 > 0 ? std::sqrt(q.r2 / q.b2) : std::sqrt(q.r2);
+    if (!(rr <= w)) w = rr;  // NaN propagates as worst
+  }
+  *worst = w;
+  return UFG_OK;
+}
+
+// ---------------------------------------------------------------------------
+// BiCGStab for A = op (M or M^T) on nrhs systems.
+//   RI: inner precision; RO: precision of b and x (RO == RI unless mixed).
+template <typename RI, typename RO>
+int bicgstab_step(Lattice& L, const PcPlan& pc, int op, const C2<RO>* b, C2<RO>* x, int nrhs,
+                  const ufg_solve_opts& o, Counters* cnt, StepResult* res) {
+  constexpr bool kMixed = !std::is_same<RI, RO>::value;
+  const bool need_pc = pc.kind != UFG_PC_NONE;
+  Inner<RI> V;
+  UFG_TRY(inner_vectors<RI>(L, nrhs, need_pc, kMixed, reinterpret_cast<C2<RI>*>(x), &V));
+  KrylovState K;
+  UFG_TRY(krylov_state(L, nrhs, &K, SLOT_STATE));
+  K.prm.tol = o.tol;
+  K.prm.delta2 = o.delta * o.delta;
+  K.prm.mixed = kMixed ? 1 : 0;
+  K.prm.bicg = 1;
+  K.prm.unprec = need_pc ? 0 : 1;
+  const int nvb = vec_blocks(L.N);
+  const int nhb = hop_blocks_per_rhs(L);
+  const double2 one{1.0, 0.0}, zero{0.0, 0.0};
+  int rc = 0;
+  C2<RO>* r64 = kMixed ? slot_vec<RO>(L, SLOT_OUTER_R, nrhs, &rc) : nullptr;
+  UFG_TRY(rc);
+
+  // ||b||^2
+  UFG_TRY(k_reduce<RO>(L, b, nullptr, 0, nullptr, K));
+  UFG_TRY(k_finalize(L, FIN_INIT_B, nvb, nullptr, K));
+  // r_0 = b - A x_0 (x_0 = 0 unless use_x0)
+  if (kMixed) {
+    if (o.use_x0) {
+      UFG_TRY(op_residual<RO>(L, op, x, b, r64, nrhs, nullptr));
+    } else {
+      UFG_HIP(hipMemsetAsync(x, 0, sizeof(C2<RO>) * L.N * nrhs, L.stream));
+      UFG_TRY(k_convert<RO, RO>(L, b, r64, nrhs, nullptr));
+    }
+    UFG_HIP(hipMemsetAsync(V.x, 0, sizeof(C2<RI>) * L.N * nrhs, L.stream));
+    UFG_TRY(k_convert<RO, RI>(L, r64, V.r, nrhs, nullptr));
+  } else {
+    if (o.use_x0) {
+      UFG_TRY(op_residual<RI>(L, op, V.x, reinterpret_cast<const C2<RI>*>(b), V.r, nrhs, nullptr));
+    } else {
+      UFG_HIP(hipMemsetAsync(V.x, 0, sizeof(C2<RI>) * L.N * nrhs, L.stream));
+      UFG_TRY(k_convert<RI, RI>(L, reinterpret_cast<const C2<RI>*>(b), V.r, nrhs, nullptr));
+    }
+  }
+  UFG_TRY(k_convert<RI, RI>(L, V.r, V.rhat, nrhs, nullptr));
+  UFG_HIP(hipMemsetAsync(V.p, 0, sizeof(C2<RI>) * L.N * nrhs, L.stream));
+  UFG_HIP(hipMemsetAsync(V.v, 0, sizeof(C2<RI>) * L.N * nrhs, L.stream));
+  if (kMixed) {
+    UFG_TRY(k_reduce<RO>(L, r64, nullptr, 0, nullptr, K));
+  } else {
+    UFG_TRY(k_reduce<RI>(L, V.r, nullptr, 0, nullptr, K));
+  }
+  UFG_TRY(k_finalize(L, FIN_INIT_R, nvb, nullptr, K));
+
+  std::vector<int> hflags(nrhs);
+  const int check = o.check_every > 0 ? o.check_every : 10;
+  int it = 0;
+  bool done = false;
+  UFG_TRY(all_inactive(L, K, hflags.data(), &done));
+  for (it = 0; it < o.maxit && !done; ++it) {
+    UFG_TRY(k_bicg_p<RI>(L, V.r, V.p, V.v, K));
+    if (need_pc) UFG_TRY(pc_apply<RI>(L, pc, op, V.p, V.phat, nrhs, K.active, cnt));
+    UFG_TRY(op_apply<RI>(L, op, V.phat, V.v, nrhs, K.active, 1, V.rhat, K.part));
+    UFG_TRY(k_finalize(L, FIN_ALPHA, nhb, K.active, K));
+    UFG_TRY(k_bicg_s<RI>(L, V.r, V.v, V.s, K));
+    if (need_pc) UFG_TRY(pc_apply<RI>(L, pc, op, V.s, V.shat, nrhs, K.active, cnt));
+    UFG_TRY(op_apply<RI>(L, op, V.shat, V.t, nrhs, K.active, 2, V.s, K.part));
+    UFG_TRY(k_finalize(L, FIN_OMEGA, nhb, K.active, K));
+    UFG_TRY(k_bicg_xr<RI>(L, V.x, V.phat, V.shat, V.s, V.t, V.r, V.rhat, K));
+    UFG_TRY(k_finalize(L, FIN_RHO, nvb, K.active, K));
+    cnt->mv += 2;
+    // reliable update / convergence verification (only rhs with update set do work)
+    if (kMixed) {
+      UFG_TRY(k_promote(L, reinterpret_cast<double2*>(x), reinterpret_cast<float2*>(V.x), nrhs,
+                        K.update));
+      UFG_TRY(op_residual<RO>(L, op, x, b, r64, nrhs, K.update));
+      UFG_TRY(k_demote(L, reinterpret_cast<const double2*>(r64), reinterpret_cast<float2*>(V.r),
+                       reinterpret_cast<const float2*>(V.rhat), K, K.update));
+    } else {
+      UFG_TRY(op_residual<RI>(L, op, V.x, reinterpret_cast<const C2<RI>*>(b), V.r, nrhs,
+                              K.update));
+      UFG_TRY(k_reduce<RI>(L, V.r, V.rhat, 3, K.update, K));
+    }
+    UFG_TRY(k_finalize(L, FIN_UPDATE, nvb, K.update, K));
+    UFG_TRY(k_restart<RI>(L, V.r, V.rhat, V.p, V.v, K));
+    UFG_TRY(k_finalize(L, FIN_RESTART, 1, K.restart, K));
+    if ((it + 1) % check == 0) UFG_TRY(all_inactive(L, K, hflags.data(), &done));
+  }
+  if (kMixed) {
+    UFG_TRY(k_promote(L, reinterpret_cast<double2*>(x), reinterpret_cast<float2*>(V.x), nrhs,
+                      nullptr));
+  }
+  std::vector<RhsState> st;
+  UFG_TRY(read_states(L, K, &st));
+  res->iters = 0;
+  res->status = 0;
+  for (auto& q : st) {
+    res->iters = std::max(res->iters, q.iters);
+    res->updates = std::max<long long>(res->updates, q.updates);
+    if (q.status) res->status = std::max(res->status, q.status);
+    else if (!q.conv) res->status = std::max(res->status, (int)UFG_NOT_CONVERGED);
+  }
+  (void)one;
+  (void)zero;
+  return UFG_OK;
+}
+
+// ---------------------------------------------------------------------------
+// CG on Q = M^T M with an HPD preconditioner.
+template <typename RI, typename RO>
+int cg_solve(Lattice& L, const PcPlan& pc, const C2<RO>* b, C2<RO>* x, int nrhs,
+             const ufg_solve_opts& o, Counters* cnt, StepResult* res) {
+  constexpr bool kMixed = !std::is_same<RI, RO>::value;
+  const bool need_pc = pc.kind != UFG_PC_NONE;
+  Inner<RI> V;
+  UFG_TRY(inner_vectors<RI>(L, nrhs, need_pc, kMixed, reinterpret_cast<C2<RI>*>(x), &V));
+  KrylovState K;
+  UFG_TRY(krylov_state(L, nrhs, &K, SLOT_STATE));
+  K.prm.tol = o.tol;
+  K.prm.delta2 = o.delta * o.delta;
+  K.prm.mixed = kMixed ? 1 : 0;
+  K.prm.bicg = 0;
+  K.prm.unprec = need_pc ? 0 : 1;
+  const int nvb = vec_blocks(L.N);
+  const int nhb = hop_blocks_per_rhs(L);
+  int rc = 0;
+  C2<RO>* r64 = kMixed ? slot_vec<RO>(L, SLOT_OUTER_R, nrhs, &rc) : nullptr;
+  UFG_TRY(rc);
+  C2<RO>* t64 = kMixed ? slot_vec<RO>(L, SLOT_OUTER_Y + 2, nrhs, &rc) : nullptr;  // slot 15
+  UFG_TRY(rc);
+
+  UFG_TRY(k_reduce<RO>(L, b, nullptr, 0, nullptr, K));
+  UFG_TRY(k_finalize(L, FIN_INIT_B, nvb, nullptr, K));
+  if (kMixed) {
+    if (o.use_x0) {
+      UFG_TRY(q_residual<RO>(L, x, b, t64, r64, nrhs, nullptr));
+    } else {
+      UFG_HIP(hipMemsetAsync(x, 0, sizeof(C2<RO>) * L.N * nrhs, L.stream));
+      UFG_TRY(k_convert<RO, RO>(L, b, r64, nrhs, nullptr));
+    }
+    UFG_HIP(hipMemsetAsync(V.x, 0, sizeof(C2<RI>) * L.N * nrhs, L.stream));
+    UFG_TRY(k_convert<RO, RI>(L, r64, V.r, nrhs, nullptr));
+    UFG_TRY(k_reduce<RO>(L, r64, nullptr, 0, nullptr, K));
+  } else {
+    const C2<RI>* bi = reinterpret_cast<const C2<RI>*>(b);
+    if (o.use_x0) {
+      UFG_TRY(q_residual<RI>(L, V.x, bi, V.tmp, V.r, nrhs, nullptr));
+    } else {
+      UFG_HIP(hipMemsetAsync(V.x, 0, sizeof(C2<RI>) * L.N * nrhs, L.stream));
+      UFG_TRY(k_convert<RI, RI>(L, bi, V.r, nrhs, nullptr));
+    }
+    UFG_TRY(k_reduce<RI>(L, V.r, nullptr, 0, nullptr, K));
+  }
+  UFG_TRY(k_finalize(L, FIN_INIT_R, nvb, nullptr, K));
+  if (need_pc) {
+    UFG_TRY(pc_apply<RI>(L, pc, UFG_OP_Q, V.r, V.z, nrhs, nullptr, cnt));
+    UFG_TRY(k_reduce<RI>(L, V.r, V.z, 1, nullptr, K));
+  }
+  UFG_TRY(k_finalize(L, FIN_CG_INIT_RZ, nvb, nullptr, K));
+  UFG_TRY(k_convert<RI, RI>(L, V.z, V.p, nrhs, nullptr));
+
+  std::vector<int> hflags(nrhs);
+  const int check = o.check_every > 0 ? o.check_every : 10;
+  bool done = false;
+  UFG_TRY(all_inactive(L, K, hflags.data(), &done));
+  for (int it = 0; it < o.maxit && !done; ++it) {
+    UFG_TRY(q_apply<RI>(L, V.p, V.tmp, V.w, nrhs, K.active, 1, V.p, K.part));
+    UFG_TRY(k_finalize(L, FIN_CG_ALPHA, nhb, K.active, K));
+    UFG_TRY(k_cg_xr<RI>(L, V.x, V.p, V.r, V.w, K));
+    UFG_TRY(k_finalize(L, FIN_CG_R, nvb, K.active, K));
+    cnt->mv += 2;
+    if (kMixed) {
+      UFG_TRY(k_promote(L, reinterpret_cast<double2*>(x), reinterpret_cast<float2*>(V.x), nrhs,
+                        K.update));
+      UFG_TRY(q_residual<RO>(L, x, b, t64, r64, nrhs, K.update));
+      UFG_TRY(k_demote(L, reinterpret_cast<const double2*>(r64), reinterpret_cast<float2*>(V.r),
+                       nullptr, K, K.update));
+    } else {
+      UFG_TRY(q_residual<RI>(L, V.x, reinterpret_cast<const C2<RI>*>(b), V.tmp, V.r, nrhs,
+                             K.update));
+      UFG_TRY(k_reduce<RI>(L, V.r, nullptr, 0, K.update, K));
+    }
+    UFG_TRY(k_finalize(L, FIN_UPDATE, nvb, K.update, K));
+    if (need_pc) {
+      UFG_TRY(pc_apply<RI>(L, pc, UFG_OP_Q, V.r, V.z, nrhs, K.active, cnt));
+      UFG_TRY(k_reduce<RI>(L, V.r, V.z, 1, K.active, K));
+    }
+    UFG_TRY(k_finalize(L, FIN_CG_BETA, nvb, K.active, K));
+    UFG_TRY(k_cg_p<RI>(L, V.z, V.p, K));
+    if ((it + 1) % check == 0) UFG_TRY(all_inactive(L, K, hflags.data(), &done));
+  }
+  if (kMixed) {
+    UFG_TRY(k_promote(L, reinterpret_cast<double2*>(x), reinterpret_cast<float2*>(V.x), nrhs,
+                      nullptr));
+  }
+  std::vector<RhsState> st;
+  UFG_TRY(read_states(L, K, &st));
+  res->iters = 0;
+  res->status = 0;
+  for (auto& q : st) {
+    res->iters = std::max(res->iters, q.iters);
+    res->updates = std::max<long long>(res->updates, q.updates);
+    if (q.status) res->status = std::max(res->status, q.status);
+    else if (!q.conv) res->status = std::max(res->status, (int)UFG_NOT_CONVERGED);
+  }
+  return UFG_OK;
+}
+
+int validate_opts(const Lattice& L, const ufg_solve_opts* o, int nrhs) {
+  UFG_CHECK(o != nullptr, "solve options are required");
+  UFG_CHECK(nrhs >= 1, "nrhs must be >= 1");
+  UFG_CHECK(o->tol > 0 && o->tol < 1, "tol must be in (0, 1)");
+  UFG_CHECK(o->maxit >= 1, "maxit must be >= 1");
+  UFG_CHECK(!o->mixed || L.dtype == UFG_C128, "mixed solves need a complex128 lattice");
+  UFG_CHECK(!o->mixed || (o->delta > 0 && o->delta < 1), "delta must be in (0, 1)");
+  return UFG_OK;
+}
+
+template <typename RI, typename RO>
+int bicgstab_dispatch(Lattice& L, const PcPlan& pc, int op, const void* bv, void* xv, int nrhs,
+                      const ufg_solve_opts& o, ufg_solve_stats* st) {
+  Counters cnt;
+  const C2<RO>* b = reinterpret_cast<const C2<RO>*>(bv);
+  C2<RO>* x = reinterpret_cast<C2<RO>*>(xv);
+  StepResult r1, r2;
+  int rc = 0;
+  double rel1 = 0, rel2 = 0, relq = -1;
+  if (op == UFG_OP_TWO_STEP) {
+    C2<RO>* y = slot_vec<RO>(L, SLOT_OUTER_Y, nrhs, &rc);
+    UFG_TRY(rc);
+    UFG_TRY((bicgstab_step<RI, RO>(L, pc, UFG_OP_MDAG, b, y, nrhs, o, &cnt, &r1)));
+    UFG_TRY(true_relres<RO>(L, UFG_OP_MDAG, y, b, nrhs, &rel1));
+    UFG_TRY((bicgstab_step<RI, RO>(L, pc, UFG_OP_M, y, x, nrhs, o, &cnt, &r2)));
+    UFG_TRY(true_relres<RO>(L, UFG_OP_M, x, y, nrhs, &rel2));
+    UFG_TRY(true_relres<RO>(L, UFG_OP_Q, x, b, nrhs, &relq));
+  } else {
+    UFG_TRY((bicgstab_step<RI, RO>(L, pc, op, b, x, nrhs, o, &cnt, &r1)));
+    UFG_TRY(true_relres<RO>(L, op, x, b, nrhs, &rel1));
+  }
+  if (st) {
+    st->iters[0] = r1.iters;
+    st->iters[1] = r2.iters;
+    st->mv = cnt.mv;
+    st->m0inv = cnt.m0inv;
+    st->sca_sweeps = cnt.sca;
+    st->reliable_updates = r1.updates + r2.updates;
+    st->relres[0] = rel1;
+    st->relres[1] = rel2;
+    st->relres_normal = relq;
+    st->paper_mv = (double)(r1.iters + r2.iters) * (2.0 + 2.0 * pc.paper_cost());
+    st->status = std::max(r1.status, r2.status);
+  }
+  return std::max(r1.status, r2.status);
+}
+
+template <typename RI, typename RO>
+int cg_dispatch(Lattice& L, const PcPlan& pc, const void* bv, void* xv, int nrhs,
+                const ufg_solve_opts& o, ufg_solve_stats* st) {
+  Counters cnt;
+  StepResult r1;
+  const C2<RO>* b = reinterpret_cast<const C2<RO>*>(bv);
+  C2<RO>* x = reinterpret_cast<C2<RO>*>(xv);
+  UFG_TRY((cg_solve<RI, RO>(L, pc, b, x, nrhs, o, &cnt, &r1)));
+  double relq = 0;
+  UFG_TRY(true_relres<RO>(L, UFG_OP_Q, x, b, nrhs, &relq));
+  if (st) {
+    st->iters[0] = r1.iters;
+    st->iters[1] = 0;
+    st->mv = cnt.mv;
+    st->m0inv = cnt.m0inv;
+    st->sca_sweeps = cnt.sca;
+    st->reliable_updates = r1.updates;
+    st->relres[0] = relq;
+    st->relres[1] = 0;
+    st->relres_normal = relq;
+    st->paper_mv = (double)r1.iters * (2.0 + pc.paper_cost());
+    st->status = r1.status;
+  }
+  return r1.status;
+}
+
+}  // namespace
+
+int solve_bicgstab_impl(Lattice& L, const ufg_precond* p, int op, const void* b, void* x,
+                        int nrhs, const ufg_solve_opts* o, ufg_solve_stats* st) {
+  UFG_TRY(validate_opts(L, o, nrhs));
+  UFG_CHECK(op == UFG_OP_M || op == UFG_OP_MDAG || op == UFG_OP_TWO_STEP,
+            "solve_bicgstab: op must be M, MDAG or TWO_STEP");
+  UFG_CHECK(b && x && b != x, "solve_bicgstab: b and x must be distinct device pointers");
+  PcPlan pc;
+  UFG_TRY(resolve_precond(L, p, &pc));
+  const auto t0 = std::chrono::steady_clock::now();
+  int rc;
+  if (o->mixed)
+    rc = bicgstab_dispatch<float, double>(L, pc, op, b, x, nrhs, *o, st);
+  else if (L.dtype == UFG_C128)
+    rc = bicgstab_dispatch<double, double>(L, pc, op, b, x, nrhs, *o, st);
+  else
+    rc = bicgstab_dispatch<float, float>(L, pc, op, b, x, nrhs, *o, st);
+  if (rc < 0) return rc;
+  UFG_HIP(hipStreamSynchronize(L.stream));
+  if (st) st->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+  return rc;
+}
+
+int solve_cg_impl(Lattice& L, const ufg_precond* p, const void* b, void* x, int nrhs,
+                  const ufg_solve_opts* o, ufg_solve_stats* st) {
+  UFG_TRY(validate_opts(L, o, nrhs));
+  UFG_CHECK(b && x && b != x, "solve_cg_normal: b and x must be distinct device pointers");
+  PcPlan pc;
+  UFG_TRY(resolve_precond(L, p, &pc));
+  const auto t0 = std::chrono::steady_clock::now();
+  int rc;
+  if (o->mixed)
+    rc = cg_dispatch<float, double>(L, pc, b, x, nrhs, *o, st);
+  else if (L.dtype == UFG_C128)
+    rc = cg_dispatch<double, double>(L, pc, b, x, nrhs, *o, st);
+  else
+    rc = cg_dispatch<float, float>(L, pc, b, x, nrhs, *o, st);
+  if (rc < 0) return rc;
+  UFG_HIP(hipStreamSynchronize(L.stream));
+  if (st) st->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+  return rc;
+}
+
+}  // namespace ufg

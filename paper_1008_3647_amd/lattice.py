@@ -1,0 +1,178 @@
+"""Python handle over a libufg lattice: torch tensors in, torch tensors out.
+
+Method names follow the C ABI (create_lattice / set_aux_field / apply_M /
+apply_Mdag / apply_precond / solve_cg_normal / solve_bicgstab /
+force_dS_dsigma); each one checks shapes, dtypes and devices and then makes
+exactly one library call.
+"""
+from __future__ import annotations
+
+import ctypes as C
+
+import torch
+
+from . import _lib as L
+from ._lib import Precond, UfgError  # noqa: F401
+
+_OPS = {"M": L.UFG_OP_M, "Mdag": L.UFG_OP_MDAG, "two_step": L.UFG_OP_TWO_STEP, "Q": L.UFG_OP_Q}
+
+
+def _stream_ptr(stream=None):
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return C.c_void_p(s.cuda_stream)
+
+
+class Lattice:
+    """Nx^3 x Ntau lattice with field sigma (paper, Sec. 1).
+
+    dtype: torch.complex64 or torch.complex128 (the vector type of apply_* and
+    of plain solves; mixed-precision solves need complex128).
+    """
+
+    def __init__(self, nx, ntau, tau=0.05, g=5.0, dtype=torch.complex128, stream=None):
+        self._lib = L.load()
+        if dtype not in (torch.complex64, torch.complex128):
+            raise ValueError("dtype must be torch.complex64 or torch.complex128")
+        self.nx, self.ntau, self.tau, self.g, self.dtype = nx, ntau, tau, g, dtype
+        self.device = torch.device("cuda", torch.cuda.current_device())
+        h = C.c_void_p()
+        code = self._lib.create_lattice(nx, ntau, tau, g,
+                                        L.UFG_C128 if dtype == torch.complex128 else L.UFG_C64,
+                                        _stream_ptr(stream), C.byref(h))
+        L.check(code, "create_lattice")
+        self._h = h
+        A = C.c_double()
+        L.check(self._lib.lattice_info(h, None, None, None, C.byref(A)), "lattice_info")
+        self.A = A.value
+        self._sigma = None
+
+    # ------------------------------------------------------------------ utils
+    @property
+    def shape(self):
+        return (self.ntau, self.nx, self.nx, self.nx)
+
+    def _vec(self, x, name, dtype=None):
+        dtype = dtype or self.dtype
+        if not isinstance(x, torch.Tensor) or x.device.type != "cuda":
+            raise TypeError(f"{name} must be a CUDA tensor")
+        if x.dtype != dtype:
+            raise TypeError(f"{name} must have dtype {dtype}, got {x.dtype}")
+        if not x.is_contiguous():
+            raise ValueError(f"{name} must be contiguous")
+        if tuple(x.shape[-4:]) != self.shape:
+            raise ValueError(f"{name} must end in shape {self.shape}, got {tuple(x.shape)}")
+        return x.numel() // (self.ntau * self.nx ** 3)
+
+    def new_vectors(self, nrhs, dtype=None):
+        return torch.empty((nrhs,) + self.shape, dtype=dtype or self.dtype, device=self.device)
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            self._lib.destroy_lattice(self._h)
+            self._h = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def set_stream(self, stream=None):
+        L.check(self._lib.set_lattice_stream(self._h, _stream_ptr(stream)), "set_lattice_stream")
+
+    # ---------------------------------------------------------------- the ABI
+    def set_aux_field(self, sigma: torch.Tensor):
+        if sigma.dtype != torch.float64 or sigma.device.type != "cuda":
+            raise TypeError("sigma must be a float64 CUDA tensor")
+        if tuple(sigma.shape) != self.shape or not sigma.is_contiguous():
+            raise ValueError(f"sigma must be contiguous with shape {self.shape}")
+        L.check(self._lib.set_aux_field(self._h, C.c_void_p(sigma.data_ptr())), "set_aux_field")
+        self._sigma = sigma
+
+    def apply_M(self, x, out=None):
+        n = self._vec(x, "x")
+        y = torch.empty_like(x) if out is None else out
+        self._vec(y, "out")
+        L.check(self._lib.apply_M(self._h, C.c_void_p(x.data_ptr()), C.c_void_p(y.data_ptr()), n),
+                "apply_M")
+        return y
+
+    def apply_Mdag(self, x, out=None):
+        n = self._vec(x, "x")
+        y = torch.empty_like(x) if out is None else out
+        self._vec(y, "out")
+        L.check(self._lib.apply_Mdag(self._h, C.c_void_p(x.data_ptr()), C.c_void_p(y.data_ptr()),
+                                     n), "apply_Mdag")
+        return y
+
+    def apply_precond(self, x, precond: Precond, op="M", out=None):
+        n = self._vec(x, "x")
+        y = torch.empty_like(x) if out is None else out
+        p = precond.to_c()
+        L.check(self._lib.apply_precond(self._h, C.byref(p), _OPS[op], C.c_void_p(x.data_ptr()),
+                                        C.c_void_p(y.data_ptr()), n), "apply_precond")
+        return y
+
+    def _solve_dtype(self, mixed):
+        return torch.complex128 if mixed else self.dtype
+
+    def solve_cg_normal(self, b, precond: Precond | None = None, tol=1e-10, maxit=10000,
+                        mixed=False, delta=0.1, check_every=10, x0=None):
+        dt = self._solve_dtype(mixed)
+        n = self._vec(b, "b", dt)
+        x = torch.empty_like(b) if x0 is None else x0
+        o = L.solve_opts(tol, maxit, mixed, delta, check_every, x0 is not None)
+        st = L.ufg_solve_stats()
+        p = precond.to_c() if precond else None
+        code = self._lib.solve_cg_normal(self._h, C.byref(p) if p else None,
+                                         C.c_void_p(b.data_ptr()), C.c_void_p(x.data_ptr()), n,
+                                         C.byref(o), C.byref(st))
+        L.check(code, "solve_cg_normal")
+        return x, st.as_dict()
+
+    def solve_bicgstab(self, b, op="two_step", precond: Precond | None = None, tol=1e-10,
+                       maxit=10000, mixed=False, delta=0.1, check_every=10, x0=None):
+        dt = self._solve_dtype(mixed)
+        n = self._vec(b, "b", dt)
+        x = torch.empty_like(b) if x0 is None else x0
+        o = L.solve_opts(tol, maxit, mixed, delta, check_every, x0 is not None)
+        st = L.ufg_solve_stats()
+        p = precond.to_c() if precond else None
+        code = self._lib.solve_bicgstab(self._h, C.byref(p) if p else None, _OPS[op],
+                                        C.c_void_p(b.data_ptr()), C.c_void_p(x.data_ptr()), n,
+                                        C.byref(o), C.byref(st))
+        L.check(code, "solve_bicgstab")
+        return x, st.as_dict()
+
+    def force_dS_dsigma(self, X, y, out=None):
+        n = self._vec(X, "X")
+        self._vec(y, "y")
+        g = torch.empty(self.shape, dtype=torch.float64, device=self.device) if out is None else out
+        L.check(self._lib.force_dS_dsigma(self._h, C.c_void_p(X.data_ptr()),
+                                          C.c_void_p(y.data_ptr()), n, C.c_void_p(g.data_ptr())),
+                "force_dS_dsigma")
+        return g
+
+
+# Host helpers (no GPU needed)
+def cheb_roots(degree, eps):
+    lib = L.load()
+    out = (C.c_double * (2 * degree))()
+    c = (C.c_double * 2)()
+    L.check(lib.ufg_cheb_roots(degree, eps, out, c), "ufg_cheb_roots")
+    roots = [complex(out[2 * i], out[2 * i + 1]) for i in range(degree)]
+    return roots, complex(c[0], c[1])
+
+
+def euler_weights(order, p=0.5):
+    lib = L.load()
+    out = (C.c_double * (order + 1))()
+    L.check(lib.ufg_euler_weights(order, p, out), "ufg_euler_weights")
+    return list(out)
+
+
+def transfer_matrix(nx, tau):
+    lib = L.load()
+    out = (C.c_double * (nx * nx))()
+    L.check(lib.ufg_transfer_matrix(nx, tau, out), "ufg_transfer_matrix")
+    return [[out[i * nx + j] for j in range(nx)] for i in range(nx)]

@@ -1,0 +1,100 @@
+"""Parity of apply_M / apply_Mdag (HIP, through the C ABI) with the FP64 oracle.
+
+Tolerance (element-wise, relative to the largest output magnitude):
+  complex128: 1e-13 (a few ulps of the 3 x Nx-term sums and the FFT route)
+  complex64 : 5e-6  (3 x 16-term FP32 sums, ~sqrt(48) * 6e-8, with margin)
+"""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from synthetic import sigma_field, gaussian_rhs, WORKLOADS
+from gpu_util import require_gpu, to_dev, to_host, rel_err, say, TAU, G
+
+pytestmark = pytest.mark.gpu
+
+TOL = {torch.complex128: 1e-13, torch.complex64: 5e-6}
+
+# (nx, ntau, nrhs): every supported Nx, slices-per-workgroup tails, the two
+# smallest cases and the antiperiodic corner at Ntau = 2.
+SHAPES = [(2, 2, 1), (2, 3, 2), (4, 40, 1), (4, 17, 2), (6, 9, 3), (8, 5, 2), (10, 3, 2),
+          (12, 4, 1), (14, 3, 1), (16, 6, 2), (8, 160, 4)]
+
+
+def _oracle(fn, x, sigma):
+    return np.stack([fn(xi, sigma, TAU, G) for xi in x])
+
+
+@pytest.mark.parametrize("dtype", [torch.complex128, torch.complex64])
+@pytest.mark.parametrize("nx,ntau,nrhs", SHAPES)
+def test_apply_matches_oracle(nx, ntau, nrhs, dtype):
+    require_gpu()
+    from paper_1008_3647_amd import Lattice
+    say(f"apply parity nx={nx} ntau={ntau} nrhs={nrhs} {dtype}")
+    sigma = sigma_field(nx, ntau, 100 + nx + ntau)
+    x = gaussian_rhs(nx, ntau, range(200, 200 + nrhs))
+    L = Lattice(nx, ntau, TAU, G, dtype)
+    L.set_aux_field(to_dev(sigma))
+    xd = to_dev(x, dtype)
+    y = to_host(L.apply_M(xd))
+    yd = to_host(L.apply_Mdag(xd))
+    ref = _oracle(oracle.apply_M, x.astype(np.complex64).astype(np.complex128)
+                  if dtype == torch.complex64 else x, sigma)
+    refd = _oracle(oracle.apply_Mdag, x.astype(np.complex64).astype(np.complex128)
+                   if dtype == torch.complex64 else x, sigma)
+    assert rel_err(y, ref) < TOL[dtype]
+    assert rel_err(yd, refd) < TOL[dtype]
+
+
+def test_adjoint_identity_on_device():
+    require_gpu()
+    from paper_1008_3647_amd import Lattice
+    nx, ntau = 8, 24
+    sigma = sigma_field(nx, ntau, 301)
+    u, v = gaussian_rhs(nx, ntau, [302, 303])
+    L = Lattice(nx, ntau, TAU, G, torch.complex128)
+    L.set_aux_field(to_dev(sigma))
+    Mu = to_host(L.apply_M(to_dev(u[None])))[0]
+    Mtv = to_host(L.apply_Mdag(to_dev(v[None])))[0]
+    lhs, rhs = np.vdot(Mu, v), np.vdot(u, Mtv)
+    assert abs(lhs - rhs) <= 1e-13 * abs(lhs)
+
+
+def test_full_size_lattice_16x400():
+    """Full 16^3 x 400 lattice, 8 RHS, both precisions, in the launch the bench
+    times: two right-hand sides (first and last) compared entry by entry."""
+    require_gpu()
+    from paper_1008_3647_amd import Lattice
+    w = WORKLOADS["lattice_16x400"]
+    nx, ntau = w["nx"], w["ntau"]
+    sigma = sigma_field(nx, ntau, w["sigma_seed"])
+    b = gaussian_rhs(nx, ntau, w["rhs_seeds"])
+    for dtype in (torch.complex128, torch.complex64):
+        say(f"full-size apply {dtype}")
+        L = Lattice(nx, ntau, TAU, G, dtype)
+        L.set_aux_field(to_dev(sigma))
+        bd = to_dev(b, dtype)
+        y = L.apply_M(bd)
+        yd = L.apply_Mdag(bd)
+        for k in (0, len(w["rhs_seeds"]) - 1):
+            xk = b[k].astype(np.complex64).astype(np.complex128) if dtype == torch.complex64 else b[k]
+            assert rel_err(to_host(y[k]), oracle.apply_M(xk, sigma, TAU, G)) < TOL[dtype]
+            assert rel_err(to_host(yd[k]), oracle.apply_Mdag(xk, sigma, TAU, G)) < TOL[dtype]
+        L.close()
+
+
+def test_invalid_arguments_are_rejected():
+    require_gpu()
+    from paper_1008_3647_amd import Lattice, UfgError
+    with pytest.raises(UfgError):
+        Lattice(5, 8)
+    with pytest.raises(UfgError):
+        Lattice(4, 1)
+    with pytest.raises(UfgError):
+        Lattice(18, 4)
+    L = Lattice(4, 4)
+    with pytest.raises(TypeError):
+        L.apply_M(torch.zeros((1, 4, 4, 4, 4), dtype=torch.complex64, device="cuda"))
+    with pytest.raises(ValueError):
+        L.apply_M(torch.zeros((1, 5, 4, 4, 4), dtype=torch.complex128, device="cuda"))

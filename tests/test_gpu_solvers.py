@@ -1,0 +1,91 @@
+"""Parity of the HIP solvers with the oracle (paper, Eqs. 1-3).
+
+The solution of M^T M x = b is unique, so every solver and preconditioner must
+reach the same x; iteration counts are not compared. Checks:
+  * true residual ||b - A x|| / ||b|| <= tol recomputed by the ORACLE's M;
+  * forward error against the oracle's solution (dense LU on the 4^3 x 40
+    lattice, the oracle's own BiCGStab to 1e-13 elsewhere) within
+    cond-limited bounds stated per test.
+"""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from oracle import operator as op
+from oracle import solvers as osol
+from synthetic import sigma_field, gaussian_rhs, WORKLOADS
+from gpu_util import require_gpu, to_dev, to_host, say, TAU, G
+
+pytestmark = pytest.mark.gpu
+
+
+def _relres_oracle(x, b, sigma, kind):
+    """||b - A x|| / ||b|| with the oracle's operator (per rhs, worst)."""
+    worst = 0.0
+    for xi, bi in zip(x, b):
+        if kind == "M":
+            r = bi - oracle.apply_M(xi, sigma, TAU, G)
+        elif kind == "Mdag":
+            r = bi - oracle.apply_Mdag(xi, sigma, TAU, G)
+        else:
+            r = bi - oracle.apply_Q(xi, sigma, TAU, G)
+        worst = max(worst, np.linalg.norm(r) / np.linalg.norm(bi))
+    return worst
+
+
+@pytest.fixture(scope="module")
+def lattice_4x40():
+    w = WORKLOADS["lattice_4x40"]
+    sigma = sigma_field(w["nx"], w["ntau"], w["sigma_seed"])
+    b = gaussian_rhs(w["nx"], w["ntau"], w["rhs_seeds"])
+    Md = op.dense_M(sigma, TAU, G)
+    x_lu = osol.dense_two_step(Md, b[0].ravel()).reshape(b[0].shape)
+    y_lu = np.linalg.solve(Md.T, b[0].ravel()).reshape(b[0].shape)
+    return sigma, b, x_lu, y_lu
+
+
+@pytest.mark.parametrize("solver", ["cg", "bicgstab"])
+@pytest.mark.parametrize("mixed", [False, True])
+def test_lattice_4x40_against_dense_lu(lattice_4x40, solver, mixed):
+    require_gpu()
+    from paper_1008_3647_amd import Lattice
+    sigma, b, x_lu, y_lu = lattice_4x40
+    say(f"4x40 {solver} mixed={mixed}")
+    L = Lattice(4, 40, TAU, G, torch.complex128)
+    L.set_aux_field(to_dev(sigma))
+    bd = to_dev(b)
+    if solver == "cg":
+        x, st = L.solve_cg_normal(bd, tol=1e-10, mixed=mixed)
+    else:
+        x, st = L.solve_bicgstab(bd, "two_step", tol=1e-10, mixed=mixed)
+    x = to_host(x)
+    say(st)
+    assert st["status"] == 0
+    assert max(st["relres"]) <= 1e-10 if solver == "bicgstab" else st["relres"][0] <= 1e-10
+    if solver == "cg":
+        assert _relres_oracle(x, b, sigma, "Q") <= 1.2e-10
+    # forward error <= cond * residual: cond(M) ~ 1e2 per step here
+    assert np.linalg.norm(x[0] - x_lu) / np.linalg.norm(x_lu) < 1e-6
+
+
+@pytest.mark.parametrize("op_name", ["M", "Mdag"])
+@pytest.mark.parametrize("dtype,mixed", [(torch.complex128, False), (torch.complex64, False),
+                                         (torch.complex128, True)])
+def test_single_system_bicgstab(op_name, dtype, mixed):
+    require_gpu()
+    from paper_1008_3647_amd import Lattice
+    nx, ntau, nrhs = 6, 24, 3
+    sigma = sigma_field(nx, ntau, 401)
+    b = gaussian_rhs(nx, ntau, [402, 403, 404])
+    say(f"bicgstab {op_name} {dtype} mixed={mixed}")
+    L = Lattice(nx, ntau, TAU, G, dtype)
+    L.set_aux_field(to_dev(sigma))
+    tol = 1e-10 if (dtype == torch.complex128) else 1e-5
+    bd = to_dev(b, torch.complex128 if mixed else dtype)
+    x, st = L.solve_bicgstab(bd, op_name, tol=tol, mixed=mixed)
+    say(st)
+    assert st["status"] == 0
+    x = to_host(x).astype(np.complex128)
+    bb = to_host(bd).astype(np.complex128)
+    assert _relres_oracle(x, bb, sigma, op_name) <= 1.2 * tol
