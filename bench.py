@@ -1,0 +1,256 @@
+"""Benchmark: time-to-solution of the two-step BiCGStab solve (M^T y = b, then
+M x = y; paper, Eq. 2) on the 16^3 x 400 lattice with 8 right-hand sides at a
+true relative residual of 1e-10, FP32-refined (complex64 inner iteration, FP64
+reliable updates and reductions) against all-FP64, plus the bandwidth of
+apply_M against the HBM roofline.
+
+One step = one FP32-refined two-step solve of all 8 right-hand sides, inputs
+resident in HBM. Prints one JSON line.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline]
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0  # MI355X HBM3E
+PROFILE_TRAFFIC = os.path.join(ROOT, "profiles", "hop_c64_16x400_traffic.json")
+HOP_SOURCE = os.path.join(ROOT, "paper_1008_3647_amd", "csrc", "hop.hip")
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--fp64-steps", type=int, default=1)
+    ap.add_argument("--mv-launches", type=int, default=200)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--precond", default="none", choices=["none", "wce2"])
+    ap.add_argument("--mv-only", action="store_true",
+                    help="only time apply_M (complex64, 8 rhs) and a 256 MiB device copy; "
+                         "used for the hardware-counter runs")
+    return ap.parse_args()
+
+
+def mv_only(a):
+    """apply_M launches alone (the counter runs), plus a plain copy of known size
+    that calibrates FETCH_SIZE / WRITE_SIZE."""
+    import torch
+    from synthetic import sigma_field, gaussian_rhs, WORKLOADS
+    from paper_1008_3647_amd import Lattice
+    w = WORKLOADS["lattice_16x400"]
+    nx, ntau = w["nx"], w["ntau"]
+    N = nx ** 3 * ntau
+    L = Lattice(nx, ntau, 0.05, 5.0, torch.complex64)
+    L.set_aux_field(torch.from_numpy(sigma_field(nx, ntau, w["sigma_seed"])).cuda())
+    x = torch.from_numpy(gaussian_rhs(nx, ntau, w["rhs_seeds"])).cuda().to(torch.complex64)
+    y = torch.empty_like(x)
+    src = torch.ones(64 << 20, dtype=torch.float32, device="cuda")  # 256 MiB
+    dst = torch.empty_like(src)
+    for _ in range(3):
+        L.apply_M(x, y)
+    dst.copy_(src)
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(a.mv_launches):
+        L.apply_M(x, y)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / a.mv_launches
+    alg = N * (x.shape[0] * 16 + 4)
+    e0.record()
+    dst.copy_(src)
+    e1.record()
+    torch.cuda.synchronize()
+    cms = e0.elapsed_time(e1)
+    print(json.dumps(dict(mode="mv-only", apply_M_us=ms * 1e3, apply_M_GBs=alg / ms / 1e6,
+                          alg_bytes=alg, copy_bytes=2 * src.numel() * 4,
+                          copy_GBs=2 * src.numel() * 4 / cms / 1e6,
+                          hop_source_sha256_16=hop_source_hash())), flush=True)
+    return 0
+
+
+def hop_source_hash():
+    with open(HOP_SOURCE, "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()[:16]
+
+
+def measured_traffic():
+    """HBM bytes per apply_M launch from the committed rocprofv3 counters, if
+    they were taken on the current kernel source; else None."""
+    try:
+        with open(PROFILE_TRAFFIC) as f:
+            d = json.load(f)
+    except (OSError, ValueError):
+        return None
+    if d.get("hop_source_sha256_16") != hop_source_hash():
+        return None
+    return d.get("bytes_per_launch")
+
+
+def cpu_baseline(sigma, b, iters_gpu, budget_s):
+    """The oracle's FP64 two-step BiCGStab on right-hand side 0, run for a
+    bounded number of iterations; seconds per iteration scaled to the GPU
+    solve's iteration count and to all right-hand sides."""
+    import oracle
+    from oracle import solvers as osol
+    tau, g = 0.05, 5.0
+    M = lambda v: oracle.apply_M(v, sigma, tau, g)  # noqa: E731
+    Mt = lambda v: oracle.apply_Mdag(v, sigma, tau, g)  # noqa: E731
+    t0 = time.time()
+    n = 0
+    chunk = 5
+    while time.time() - t0 < budget_s:
+        osol.bicgstab(Mt, b[0], tol=1e-30, maxit=chunk)
+        n += chunk
+    dt = (time.time() - t0) / n
+    total_iters = sum(iters_gpu)
+    return dict(value=dt * total_iters * b.shape[0], unit="s", cores=1, kind="oracle",
+                sample=f"{n} BiCGStab iterations of the numpy FP64 oracle on 1 of {b.shape[0]} "
+                       f"right-hand sides ({dt:.3f} s/iteration), scaled to the GPU solve's "
+                       f"{total_iters} iterations x {b.shape[0]} right-hand sides")
+
+
+def main():
+    a = parse()
+    if a.mv_only:
+        return mv_only(a)
+    if a.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for --gpus {a.gpus}); the multi-GPU "
+              "time-slab sharding of this solver is a design note, not built.", file=sys.stderr)
+        return 2
+    import torch
+    from synthetic import sigma_field, gaussian_rhs, WORKLOADS
+    from paper_1008_3647_amd import Lattice, Precond
+
+    w = WORKLOADS["lattice_16x400"]
+    nx, ntau, seeds = w["nx"], w["ntau"], w["rhs_seeds"]
+    nrhs = len(seeds)
+    N = nx ** 3 * ntau
+    sigma_h = sigma_field(nx, ntau, w["sigma_seed"])
+    b_h = gaussian_rhs(nx, ntau, seeds)
+    sigma = torch.from_numpy(sigma_h).cuda()
+    b = torch.from_numpy(b_h).cuda()
+    tol = 1e-10
+    pc = Precond("wce", wce_order=2) if a.precond == "wce2" else None
+
+    L = Lattice(nx, ntau, 0.05, 5.0, torch.complex128)
+    L.set_aux_field(sigma)
+
+    def solve(mixed):
+        return L.solve_bicgstab(b, "two_step", precond=pc, tol=tol, mixed=mixed, maxit=20000)
+
+    for _ in range(a.warmup):
+        solve(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(a.steps):
+        x, st = solve(True)
+    torch.cuda.synchronize()
+    t_mixed = (time.perf_counter() - t0) / a.steps
+    ok = st["status"] == 0 and max(st["relres"]) <= tol
+
+    # all-FP64 comparison on the same GPU
+    solve(False)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(a.fp64_steps):
+        x64, st64 = solve(False)
+    torch.cuda.synchronize()
+    t_fp64 = (time.perf_counter() - t0) / a.fp64_steps
+
+    # error against the FP64 oracle: the oracle's M recomputes the residuals of rhs 0
+    import oracle
+    xh = x[0].cpu().numpy()
+    mx = oracle.apply_M(xh, sigma_h, 0.05, 5.0)
+    qx = oracle.apply_Mdag(mx, sigma_h, 0.05, 5.0)
+    relres_q_oracle = float(np.linalg.norm(b_h[0] - qx) / np.linalg.norm(b_h[0]))
+    diff_fp64 = float((x - x64).abs().max().item() / x64.abs().max().item())
+
+    # apply_M bandwidth (the dominant kernel of the solve), HIP events on the lattice stream
+    mv = {}
+    roofline = None
+    for dt, c, f in ((torch.complex64, 8, 4), (torch.complex128, 16, 8)):
+        Lm = Lattice(nx, ntau, 0.05, 5.0, dt)
+        Lm.set_aux_field(sigma)
+        xs = b.to(dt)
+        ys = torch.empty_like(xs)
+        for _ in range(5):
+            Lm.apply_M(xs, ys)
+        torch.cuda.synchronize()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        res = {}
+        for name, fn in (("apply_M", Lm.apply_M), ("apply_Mdag", Lm.apply_Mdag)):
+            e0.record()
+            for _ in range(a.mv_launches):
+                fn(xs, ys)
+            e1.record()
+            torch.cuda.synchronize()
+            ms = e0.elapsed_time(e1) / a.mv_launches
+            alg = N * (nrhs * 2 * c + f)
+            res[name] = dict(us=ms * 1e3, GBs=alg / ms / 1e6, alg_bytes=alg)
+        mv["c64" if dt == torch.complex64 else "c128"] = res
+        if dt == torch.complex64:
+            r = res["apply_M"]
+            roofline = dict(bound="hbm", achieved=round(r["GBs"], 1), peak=HBM_PEAK_GBS,
+                            unit="GB/s", frac=round(r["GBs"] / HBM_PEAK_GBS, 4),
+                            traffic=measured_traffic(),
+                            kernel="hop_kernel<float,16> (apply_M, complex64, 8 rhs)",
+                            alg_bytes_per_launch=r["alg_bytes"])
+        Lm.close()
+
+    out = {
+        "metric": "time-to-solution at rel resid 1e-10 (FP32-refined vs FP64), Nx=16 Ntau=400; MV GB/s",
+        "value": round(t_mixed, 4),
+        "unit": "s",
+        "n_gpus": 1,
+        "steps": a.steps,
+        "warmup": a.warmup,
+        "ms_per_step": round(t_mixed * 1e3, 2),
+        "higher_is_better": False,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32+f64",
+        "data": "synthetic",
+        "config": {"workload": "lattice_16x400: two-step BiCGStab, 8 rhs, tol 1e-10",
+                   "nx": nx, "ntau": ntau, "nrhs": nrhs, "tau": 0.05, "g": 5.0,
+                   "precond": a.precond, "precision": "fp32-refined"},
+        "converged": bool(ok),
+        "iters": list(st["iters"]),
+        "relres_steps": list(st["relres"]),
+        "relres_normal": st["relres_normal"],
+        "relres_normal_oracle_rhs0": relres_q_oracle,
+        "reliable_updates": st["reliable_updates"],
+        "fp64_seconds": round(t_fp64, 4),
+        "fp64_iters": list(st64["iters"]),
+        "fp64_relres_steps": list(st64["relres"]),
+        "speedup_vs_fp64": round(t_fp64 / t_mixed, 3),
+        "max_rel_diff_vs_fp64_solution": diff_fp64,
+        "mv": mv,
+        "roofline": roofline,
+    }
+    if not a.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(sigma_h, b_h, st["iters"], a.cpu_seconds)
+    else:
+        out["cpu_baseline"] = None
+    print(json.dumps(out), flush=True)
+    return 0 if ok else 1
+
+
+if __name__ == "__main__":
+    sys.exit(main())
