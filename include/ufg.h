@@ -206,6 +206,14 @@ int solve_batched(const ufg_lattice* Ls, int nprob, const void* const* b,
 int force_dS_dsigma(ufg_lattice L, const void* X, const void* y, int nrhs,
                     double* grad_dev);
 
+/*
+ * lattice_norm2 -- out_host[r] = ||x_r||^2 for nrhs vectors of the lattice dtype
+ *   (FP64 accumulation, fixed summation order). The pseudofermion action of
+ *   Sec. 1 is S = ||y||^2 with M^dagger y = phi. out_host: host array of nrhs
+ *   doubles. Synchronous.
+ */
+int lattice_norm2(ufg_lattice L, const void* x, int nrhs, double* out_host);
+
 /* lattice_info -- nx, ntau, dtype, A of a handle (host pointers, any may be NULL). */
 int lattice_info(ufg_lattice L, int* nx, int* ntau, int* dtype, double* A);
 

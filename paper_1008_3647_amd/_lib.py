@@ -63,6 +63,7 @@ _SIGNATURES = {
                                 C.POINTER(C.c_int), C.POINTER(ufg_precond),
                                 C.POINTER(ufg_solve_opts), C.POINTER(ufg_solve_stats)]),
     "force_dS_dsigma": (C.c_int, [_P, _P, _P, C.c_int, _P]),
+    "lattice_norm2": (C.c_int, [_P, _P, C.c_int, C.POINTER(C.c_double)]),
     "lattice_info": (C.c_int, [_P, C.POINTER(C.c_int), C.POINTER(C.c_int),
                                C.POINTER(C.c_int), C.POINTER(C.c_double)]),
     "ufg_last_error": (C.c_char_p, []),
@@ -111,7 +112,7 @@ class Precond:
     degree: int = 16
     eps: float = 1e-2
     lam_max: float = 0.0        # >0 given, 0 bound, <0 power iteration
-    alpha: float = 1.0
+    alpha: float = 2.0          # SCA shift (Sec. 4 leaves it to tuning)
     wce_order: int = 0
     euler: bool = False
     euler_p: float = 0.5

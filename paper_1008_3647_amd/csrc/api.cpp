@@ -296,6 +296,25 @@ int force_dS_dsigma(ufg_lattice h, const void* X, const void* y, int nrhs, doubl
   return launch_force<float>(*L, (const float2*)X, (const float2*)y, nrhs, grad_dev);
 }
 
+int lattice_norm2(ufg_lattice h, const void* x, int nrhs, double* out_host) {
+  Lattice* L = check_handle(h);
+  UFG_CHECK(L != nullptr, "lattice_norm2: NULL handle");
+  UFG_CHECK(x && out_host && nrhs >= 1, "lattice_norm2: bad pointers or nrhs");
+  KrylovState K;
+  UFG_TRY(krylov_state(*L, nrhs, &K, SLOT_PSTATE));
+  if (L->dtype == UFG_C128)
+    UFG_TRY(k_reduce<double>(*L, (const double2*)x, nullptr, 0, nullptr, K));
+  else
+    UFG_TRY(k_reduce<float>(*L, (const float2*)x, nullptr, 0, nullptr, K));
+  UFG_TRY(k_finalize(*L, FIN_NORM, vec_blocks(L->N), nullptr, K));
+  std::vector<RhsState> st(nrhs);
+  UFG_HIP(hipMemcpyAsync(st.data(), K.st, sizeof(RhsState) * nrhs, hipMemcpyDeviceToHost,
+                         L->stream));
+  UFG_HIP(hipStreamSynchronize(L->stream));
+  for (int i = 0; i < nrhs; ++i) out_host[i] = st[i].r2;
+  return UFG_OK;
+}
+
 int lattice_info(ufg_lattice h, int* nx, int* ntau, int* dtype, double* A) {
   Lattice* L = check_handle(h);
   UFG_CHECK(L != nullptr, "lattice_info: NULL handle");

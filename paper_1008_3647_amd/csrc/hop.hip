@@ -273,8 +273,10 @@ __global__ void __launch_bounds__(HopShape<NX>::THREADS)
 }
 
 template <typename R, int NX>
-int launch_hop_nx(const Lattice& L, const HopArgs<R>& a) {
+int launch_hop_nx(const Lattice& L, const HopArgs<R>& args) {
   using S = HopShape<NX>;
+  HopArgs<R> a = args;
+  if (a.beta.x == 0.0 && a.beta.y == 0.0) a.aux = nullptr;  // never read an unused operand
   const int tgroups = (L.ntau + S::SPW - 1) / S::SPW;
   const size_t lds = size_t(S::SPW) * S::SL * sizeof(C2<R>);
   const bool general = (a.alpha.x != 1.0 || a.alpha.y != 0.0 || a.aux != nullptr);

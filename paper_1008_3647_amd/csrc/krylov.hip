@@ -154,10 +154,16 @@ __global__ void __launch_bounds__(256) axpby_kernel(double2 a, const C2<R>* x, d
   if (gate && !gate[k]) return;
   const long long off = (long long)k * n;
   const R ar = R(a.x), ai = R(a.y), br = R(b.x), bi = R(b.y);
+  const bool read_y = (b.x != 0.0 || b.y != 0.0);  // y may be uninitialised when b = 0
   KR_LOOP(n) {
-    const C2<R> xv = x[off + i], yv = y[off + i];
-    y[off + i] = c2<R>(ar * xv.x - ai * xv.y + br * yv.x - bi * yv.y,
-                       ar * xv.y + ai * xv.x + br * yv.y + bi * yv.x);
+    const C2<R> xv = x[off + i];
+    C2<R> out = c2<R>(ar * xv.x - ai * xv.y, ar * xv.y + ai * xv.x);
+    if (read_y) {
+      const C2<R> yv = y[off + i];
+      out.x += br * yv.x - bi * yv.y;
+      out.y += br * yv.y + bi * yv.x;
+    }
+    y[off + i] = out;
   }
 }
 

@@ -144,6 +144,14 @@ class Lattice:
         L.check(code, "solve_bicgstab")
         return x, st.as_dict()
 
+    def norm2(self, x):
+        """||x_r||^2 per right-hand side (host list), FP64 accumulation."""
+        n = self._vec(x, "x")
+        out = (C.c_double * n)()
+        L.check(self._lib.lattice_norm2(self._h, C.c_void_p(x.data_ptr()), n, out),
+                "lattice_norm2")
+        return list(out)
+
     def force_dS_dsigma(self, X, y, out=None):
         n = self._vec(X, "X")
         self._vec(y, "y")

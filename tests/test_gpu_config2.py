@@ -1,0 +1,85 @@
+"""The solver x preconditioner grid on the 8^3 x 160 lattice (4 right-hand sides,
+complex128): every cell must reach the unique solution of M^T M x = b.
+
+For each cell: status 0; the true residual of every step, recomputed by the
+ORACLE's M, <= 1.05 tol; and the forward error against the oracle's reference
+solution (tests/golden/lattice_8x160_reference.npz, sampled entries, written
+by tests/golden/make_reference_solutions.py from oracle/ only) <= 1e-6. That
+bound: per step ||x - x*|| <= cond(M) ||r|| / sigma-scale with cond(M) <= ~1e3
+here and tol = 1e-10 per step, plus the reference's own 1e-13 residual.
+Iteration counts are reported, not compared (several counts are correct).
+"""
+import os
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from synthetic import sigma_field, gaussian_rhs, WORKLOADS
+from gpu_util import require_gpu, to_dev, to_host, say, TAU, G
+
+pytestmark = pytest.mark.gpu
+HERE = os.path.dirname(__file__)
+TOL = 1e-10
+
+CG_CELLS = [("none", {}), ("cheb", dict(degree=8, eps=1e-2, lam_max=-1.0)),
+            ("cheb", dict(degree=16, eps=3e-3, lam_max=-1.0)),
+            ("cheb", dict(degree=32, eps=1e-3, lam_max=-1.0)),
+            ("sca", dict(alpha=2.0)), ("wce", dict(wce_order=1))]
+BICG_CELLS = [("none", {}), ("wce", dict(wce_order=0)), ("wce", dict(wce_order=1)),
+              ("wce", dict(wce_order=2)), ("wce", dict(wce_order=2, euler=True)),
+              ("wce", dict(wce_order=4)), ("wce", dict(wce_order=4, euler=True)),
+              ("cheb", dict(degree=8, eps=1e-2, lam_max=-1.0)), ("sca", dict(alpha=2.0))]
+
+
+@pytest.fixture(scope="module")
+def setup():
+    require_gpu()
+    from paper_1008_3647_amd import Lattice
+    w = WORKLOADS["lattice_8x160"]
+    sigma = sigma_field(w["nx"], w["ntau"], w["sigma_seed"])
+    b = gaussian_rhs(w["nx"], w["ntau"], w["rhs_seeds"])
+    L = Lattice(w["nx"], w["ntau"], TAU, G, torch.complex128)
+    L.set_aux_field(to_dev(sigma))
+    ref = np.load(os.path.join(HERE, "golden", "lattice_8x160_reference.npz"))
+    return L, sigma, b, to_dev(b), ref
+
+
+def _check_solution(x, b, sigma, ref, two_step):
+    for k in range(b.shape[0]):
+        # ||b - Q x|| bounds both steps of a two-step solve together
+        r = b[k] - oracle.apply_Q(x[k], sigma, TAU, G)
+        assert np.linalg.norm(r) / np.linalg.norm(b[k]) < 1e-7
+        idx = ref["sample_index"]
+        xs = x[k].reshape(-1)[idx]
+        err = np.max(np.abs(xs - ref[f"x{k}_sample"])) / np.max(np.abs(ref[f"x{k}_sample"]))
+        assert err < 1e-6, (k, err)
+
+
+@pytest.mark.parametrize("kind,kw", CG_CELLS, ids=[f"{k}{v}" for k, v in CG_CELLS])
+def test_cg_cell(setup, kind, kw):
+    from paper_1008_3647_amd import Precond
+    L, sigma, b, bd, ref = setup
+    p = Precond(kind, **kw) if kind != "none" else None
+    x, st = L.solve_cg_normal(bd, p, tol=TOL, maxit=20000)
+    say(f"CG {kind} {kw}: iters {st['iters'][0]} mv {st['mv']} paper_mv {st['paper_mv']} "
+        f"{st['seconds']:.3f}s relres {st['relres'][0]:.2e}")
+    assert st["status"] == 0 and st["relres"][0] <= TOL
+    x = to_host(x)
+    worst = max(np.linalg.norm(b[k] - oracle.apply_Q(x[k], sigma, TAU, G)) / np.linalg.norm(b[k])
+                for k in range(b.shape[0]))
+    assert worst <= 1.05 * TOL
+    _check_solution(x, b, sigma, ref, False)
+
+
+@pytest.mark.parametrize("kind,kw", BICG_CELLS, ids=[f"{k}{v}" for k, v in BICG_CELLS])
+def test_bicgstab_cell(setup, kind, kw):
+    from paper_1008_3647_amd import Precond
+    L, sigma, b, bd, ref = setup
+    p = Precond(kind, **kw) if kind != "none" else None
+    x, st = L.solve_bicgstab(bd, "two_step", p, tol=TOL, maxit=20000)
+    say(f"BiCGStab {kind} {kw}: iters {st['iters']} mv {st['mv']} m0inv {st['m0inv']} "
+        f"paper_mv {st['paper_mv']} {st['seconds']:.3f}s relres {st['relres']}")
+    assert st["status"] == 0 and max(st["relres"]) <= TOL
+    _check_solution(to_host(x), b, sigma, ref, True)

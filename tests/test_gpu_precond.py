@@ -1,0 +1,133 @@
+"""Parity of the preconditioners (apply_precond through the C ABI) with the oracle.
+
+  SCA (Sec. 4): (L^dagger D L)^{-1} for alpha in {1, 1.5}
+  WCE (Sec. 3, 3.1): W_d and W_d^T, d in {0, 1, 2, 4}, plain and Euler weights;
+      W_d W_d^T for the CG (op Q) form
+  Chebyshev (Sec. 2): P(Q/lam_max), degrees 8 and 16, bit-reversal order, and
+      the BiCGStab extension P M^T / M P.
+Tolerances (element-wise, relative to the largest output): complex128 1e-12
+(WCE and Chebyshev chain up to 2d+2 operator applications), complex64 2e-5.
+"""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from oracle import precond as pc
+from synthetic import sigma_field, gaussian_rhs
+from gpu_util import require_gpu, to_dev, to_host, rel_err, say, TAU, G
+
+pytestmark = pytest.mark.gpu
+
+TOL = {torch.complex128: 1e-12, torch.complex64: 2e-5}
+SHAPES = [(4, 12, 2), (6, 9, 1), (8, 20, 3), (16, 5, 1)]
+
+
+def _setup(nx, ntau, nrhs, dtype, seed):
+    from paper_1008_3647_amd import Lattice
+    sigma = sigma_field(nx, ntau, seed)
+    x = gaussian_rhs(nx, ntau, range(seed + 1, seed + 1 + nrhs))
+    if dtype == torch.complex64:
+        x = x.astype(np.complex64).astype(np.complex128)
+    L = Lattice(nx, ntau, TAU, G, dtype)
+    L.set_aux_field(to_dev(sigma))
+    return L, sigma, x, to_dev(x, dtype)
+
+
+@pytest.mark.parametrize("dtype", [torch.complex128, torch.complex64])
+@pytest.mark.parametrize("nx,ntau,nrhs", SHAPES)
+@pytest.mark.parametrize("alpha", [1.0, 1.5])
+def test_sca(nx, ntau, nrhs, dtype, alpha):
+    require_gpu()
+    from paper_1008_3647_amd import Precond
+    say(f"sca nx={nx} ntau={ntau} alpha={alpha} {dtype}")
+    L, sigma, x, xd = _setup(nx, ntau, nrhs, dtype, 500)
+    y = to_host(L.apply_precond(xd, Precond("sca", alpha=alpha), "Q"))
+    D, Lb = pc.sca_setup(sigma, TAU, G, alpha)
+    ref = np.stack([pc.sca_apply(xi, D, Lb) for xi in x])
+    assert rel_err(y, ref) < TOL[dtype]
+
+
+@pytest.mark.parametrize("dtype", [torch.complex128, torch.complex64])
+@pytest.mark.parametrize("nx,ntau,nrhs", SHAPES)
+@pytest.mark.parametrize("order,euler", [(0, False), (1, False), (2, False), (2, True), (4, True)])
+def test_wce(nx, ntau, nrhs, dtype, order, euler):
+    require_gpu()
+    from paper_1008_3647_amd import Precond
+    say(f"wce nx={nx} ntau={ntau} d={order} euler={euler} {dtype}")
+    L, sigma, x, xd = _setup(nx, ntau, nrhs, dtype, 600)
+    p = Precond("wce", wce_order=order, euler=euler)
+    yM = to_host(L.apply_precond(xd, p, "M"))
+    yT = to_host(L.apply_precond(xd, p, "Mdag"))
+    refM = np.stack([pc.wce_apply(xi, sigma, TAU, G, order, euler) for xi in x])
+    refT = np.stack([pc.wce_apply_dag(xi, sigma, TAU, G, order, euler) for xi in x])
+    assert rel_err(yM, refM) < TOL[dtype]
+    assert rel_err(yT, refT) < TOL[dtype]
+    if order == 2 and dtype == torch.complex128:
+        yQ = to_host(L.apply_precond(xd, p, "Q"))
+        refQ = np.stack([pc.wce_apply(pc.wce_apply_dag(xi, sigma, TAU, G, order, euler),
+                                      sigma, TAU, G, order, euler) for xi in x])
+        assert rel_err(yQ, refQ) < TOL[dtype]
+
+
+def test_m0_inverse_on_device():
+    """WCE of order 0 is M0^{-1}; M0 (g = 0) undoes it."""
+    require_gpu()
+    from paper_1008_3647_amd import Lattice, Precond
+    nx, ntau = 8, 16
+    x = gaussian_rhs(nx, ntau, [650, 651])
+    L0 = Lattice(nx, ntau, TAU, 0.0, torch.complex128)
+    xd = to_dev(x)
+    u = L0.apply_precond(xd, Precond("wce", wce_order=0), "M")
+    back = to_host(L0.apply_M(u))
+    assert rel_err(back, x) < 1e-13
+    ut = L0.apply_precond(xd, Precond("wce", wce_order=0), "Mdag")
+    assert rel_err(to_host(L0.apply_Mdag(ut)), x) < 1e-13
+
+
+@pytest.mark.parametrize("dtype", [torch.complex128, torch.complex64])
+@pytest.mark.parametrize("degree", [8, 16])
+def test_chebyshev(dtype, degree):
+    require_gpu()
+    from paper_1008_3647_amd import Precond
+    nx, ntau, nrhs = 6, 10, 2
+    say(f"cheb degree={degree} {dtype}")
+    L, sigma, x, xd = _setup(nx, ntau, nrhs, dtype, 700)
+    lam_max, eps = 7.0, 1e-2
+    p = Precond("cheb", degree=degree, eps=eps, lam_max=lam_max)
+    yQ = to_host(L.apply_precond(xd, p, "Q"))
+    refQ = np.stack([pc.apply_cheb(xi, sigma, TAU, G, degree, eps, lam_max) for xi in x])
+    tol = TOL[dtype] * (10 if dtype == torch.complex64 else 1)
+    assert rel_err(yQ, refQ) < tol
+    if dtype == torch.complex128:
+        yM = to_host(L.apply_precond(xd, p, "M"))
+        refM = np.stack([pc.apply_cheb(oracle.apply_Mdag(xi, sigma, TAU, G), sigma, TAU, G,
+                                       degree, eps, lam_max) for xi in x])
+        assert rel_err(yM, refM) < tol
+        yT = to_host(L.apply_precond(xd, p, "Mdag"))
+        refT = np.stack([oracle.apply_M(pc.apply_cheb(xi, sigma, TAU, G, degree, eps, lam_max),
+                                        sigma, TAU, G) for xi in x])
+        assert rel_err(yT, refT) < tol
+
+
+def test_chebyshev_lam_max_estimates():
+    """lam_max = 0 uses the bound (1 + max|b|)^2 >= ||Q|| exactly; lam_max < 0
+    estimates it by power iteration, and PCG with it must still converge."""
+    require_gpu()
+    from paper_1008_3647_amd import Lattice, Precond
+    from oracle import operator as op
+    nx, ntau = 2, 8
+    sigma = sigma_field(nx, ntau, 710)
+    Md = op.dense_M(sigma, TAU, G)
+    lam_true = np.linalg.eigvalsh(Md.T @ Md)[-1]
+    b = oracle.field_b(sigma, oracle.coupling_A(TAU, G))
+    bound = (1 + np.abs(b).max()) ** 2
+    assert bound >= lam_true
+    L = Lattice(nx, ntau, TAU, G, torch.complex128)
+    L.set_aux_field(to_dev(sigma))
+    x = gaussian_rhs(nx, ntau, [711])
+    xd = to_dev(x)
+    y = to_host(L.apply_precond(xd, Precond("cheb", degree=8, eps=1e-2, lam_max=0.0), "Q"))
+    assert rel_err(y, pc.apply_cheb(x[0], sigma, TAU, G, 8, 1e-2, bound)[None]) < 1e-12
+    sol, st = L.solve_cg_normal(xd, Precond("cheb", degree=8, eps=1e-2, lam_max=-1.0), tol=1e-10)
+    assert st["status"] == 0 and st["relres"][0] <= 1e-10
