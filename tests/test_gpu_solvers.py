@@ -89,3 +89,35 @@ def test_single_system_bicgstab(op_name, dtype, mixed):
     x = to_host(x).astype(np.complex128)
     bb = to_host(bd).astype(np.complex128)
     assert _relres_oracle(x, bb, sigma, op_name) <= 1.2 * tol
+
+
+@pytest.mark.parametrize("mixed", [True, False])
+def test_lattice_16x400_against_oracle_reference(mixed):
+    """Full-size two-step solve, 8 rhs, in the configuration bench.py times.
+    Right-hand side 0 is compared with the oracle's reference solution
+    (tests/golden/lattice_16x400_reference.npz, sampled entries, residual
+    ~1e-13 per step): forward error <= 1e-7 (cond(M) ~ 1e3 times the 1e-10
+    per-step residual, with margin); its residual is recomputed by the oracle."""
+    require_gpu()
+    import os
+    from paper_1008_3647_amd import Lattice
+    w = WORKLOADS["lattice_16x400"]
+    nx, ntau = w["nx"], w["ntau"]
+    sigma = sigma_field(nx, ntau, w["sigma_seed"])
+    b = gaussian_rhs(nx, ntau, w["rhs_seeds"])
+    say(f"16x400 two-step mixed={mixed}")
+    L = Lattice(nx, ntau, TAU, G, torch.complex128)
+    L.set_aux_field(to_dev(sigma))
+    x, st = L.solve_bicgstab(to_dev(b), "two_step", tol=1e-10, mixed=mixed, maxit=20000)
+    say(st)
+    assert st["status"] == 0 and max(st["relres"]) <= 1e-10
+    x0 = to_host(x[0])
+    ref = np.load(os.path.join(os.path.dirname(__file__), "golden", "lattice_16x400_reference.npz"))
+    xs = x0.reshape(-1)[ref["sample_index"]]
+    err = np.max(np.abs(xs - ref["x0_sample"])) / np.max(np.abs(ref["x0_sample"]))
+    say(f"forward error vs oracle reference: {err:.2e}; norm ratio "
+        f"{np.linalg.norm(x0) / ref['x0_norm']:.12f}")
+    assert err < 1e-7
+    assert np.linalg.norm(x0) / ref["x0_norm"] == pytest.approx(1.0, abs=1e-8)
+    r = b[0] - oracle.apply_Q(x0, sigma, TAU, G)
+    assert np.linalg.norm(r) / np.linalg.norm(b[0]) < 1e-8
