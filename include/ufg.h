@@ -214,6 +214,15 @@ int force_dS_dsigma(ufg_lattice L, const void* X, const void* y, int nrhs,
  */
 int lattice_norm2(ufg_lattice L, const void* x, int nrhs, double* out_host);
 
+/*
+ * lattice_tune -- launch parameters chosen by the autotuner (0 keeps the
+ *   default): `slab` time slices per workgroup of the streaming M / M^T kernel
+ *   (Nx in {8, 12, 16}; 1..Ntau), `vec_blocks` workgroups per right-hand side of
+ *   the Krylov vector kernels (1..4096). Results do not depend on them beyond
+ *   floating-point summation order.
+ */
+int lattice_tune(ufg_lattice L, int slab, int vec_blocks);
+
 /* lattice_info -- nx, ntau, dtype, A of a handle (host pointers, any may be NULL). */
 int lattice_info(ufg_lattice L, int* nx, int* ntau, int* dtype, double* A);
 

@@ -63,6 +63,7 @@ _SIGNATURES = {
                                 C.POINTER(C.c_int), C.POINTER(ufg_precond),
                                 C.POINTER(ufg_solve_opts), C.POINTER(ufg_solve_stats)]),
     "force_dS_dsigma": (C.c_int, [_P, _P, _P, C.c_int, _P]),
+    "lattice_tune": (C.c_int, [_P, C.c_int, C.c_int]),
     "lattice_norm2": (C.c_int, [_P, _P, C.c_int, C.POINTER(C.c_double)]),
     "lattice_info": (C.c_int, [_P, C.POINTER(C.c_int), C.POINTER(C.c_int),
                                C.POINTER(C.c_int), C.POINTER(C.c_double)]),

@@ -1,0 +1,89 @@
+"""Autotuner for the launch shapes of a lattice (slab size of the streaming
+M / M^T kernel, workgroups per right-hand side of the Krylov vector kernels).
+
+Each candidate is timed on the real workload: a BiCGStab run of a fixed number
+of iterations (tolerance unreachable, so every candidate does identical work)
+on the caller's right-hand sides. The best pair is applied with
+Lattice.tune() and cached in a JSON file keyed by device, lattice shape,
+number of right-hand sides, dtype and precision mode.
+"""
+from __future__ import annotations
+
+import json
+import os
+import time
+
+import torch
+
+from .lattice import Lattice
+
+DEFAULT_CACHE = os.path.join(os.environ.get("XDG_CACHE_HOME", os.path.expanduser("~/.cache")),
+                             "ufg_mi355x", "tune.json")
+
+
+def _key(L: Lattice, nrhs, mixed):
+    dev = torch.cuda.get_device_properties(L.device)
+    arch = getattr(dev, "gcnArchName", dev.name)
+    return f"{arch}|{L.nx}|{L.ntau}|{nrhs}|{L.dtype}|{int(mixed)}"
+
+
+def _load(path):
+    try:
+        with open(path) as f:
+            return json.load(f)
+    except (OSError, ValueError):
+        return {}
+
+
+def _store(path, data):
+    try:
+        os.makedirs(os.path.dirname(path), exist_ok=True)
+        tmp = path + ".tmp"
+        with open(tmp, "w") as f:
+            json.dump(data, f, indent=1, sort_keys=True)
+        os.replace(tmp, path)
+    except OSError:
+        pass
+
+
+def candidate_slabs(L: Lattice):
+    if L.nx not in (8, 12, 16):
+        return [0]
+    return [s for s in (1, 2, 3, 4, 6, 8) if s <= L.ntau]
+
+
+def tune(L: Lattice, b: torch.Tensor, mixed=False, op="M", iters=16, reps=2,
+         vec_blocks=(0, 32, 64, 128, 256, 512), cache: str | None = DEFAULT_CACHE,
+         force=False, verbose=False):
+    """Pick (slab, vec_blocks) for solves of `b` on `L`; returns a dict with the
+    choice and the timings of every candidate."""
+    nrhs = b.shape[0]
+    key = _key(L, nrhs, mixed)
+    data = _load(cache) if cache else {}
+    if not force and key in data:
+        best = data[key]
+        L.tune(best["slab"], best["vec_blocks"])
+        return dict(best, cached=True)
+    results = []
+    for slab in candidate_slabs(L):
+        for vb in vec_blocks:
+            L.tune(slab, vb)
+            L.solve_bicgstab(b, op, tol=1e-30, maxit=2, mixed=mixed)  # warm-up
+            best_t = float("inf")
+            for _ in range(reps):
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                L.solve_bicgstab(b, op, tol=1e-30, maxit=iters, mixed=mixed, check_every=iters)
+                torch.cuda.synchronize()
+                best_t = min(best_t, time.perf_counter() - t0)
+            results.append(dict(slab=slab, vec_blocks=vb, seconds=best_t))
+            if verbose:
+                print(f"tune slab={slab} vec_blocks={vb}: {best_t * 1e3:.2f} ms", flush=True)
+    best = min(results, key=lambda d: d["seconds"])
+    L.tune(best["slab"], best["vec_blocks"])
+    choice = dict(slab=best["slab"], vec_blocks=best["vec_blocks"], seconds=best["seconds"],
+                  iters=iters)
+    if cache:
+        data[key] = choice
+        _store(cache, data)
+    return dict(choice, cached=False, candidates=results)

@@ -15,8 +15,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libufg.so")
-SOURCES = ["api.cpp", "ops.cpp", "solvers.cpp", "batched.hip", "hop.hip", "temporal.hip",
-           "krylov.hip"]
+SOURCES = ["api.cpp", "ops.cpp", "solvers.cpp", "split.cpp", "batched.hip", "hop.hip",
+           "hop_stream.hip", "temporal.hip", "krylov.hip"]
 ARCH = "gfx950"
 
 

@@ -6,6 +6,7 @@
 #include <new>
 
 #include "ops.h"
+#include "hop_stream.h"
 
 namespace ufg {
 
@@ -188,6 +189,12 @@ int create_lattice(int nx, int ntau, double tau, double g, int dtype, void* hip_
     set_error("create_lattice: eigenbasis check failed");
     return UFG_EHIP;
   }
+  if (split_coefficients(nx, L->T_host, &L->split_host) > 1e-13) {
+    free_fields(*L);
+    delete L;
+    set_error("create_lattice: block form of T failed its check");
+    return UFG_EHIP;
+  }
   std::vector<double> Ut(nx * nx), lam3(L->V);
   for (int i = 0; i < nx; ++i)
     for (int j = 0; j < nx; ++j) Ut[i * nx + j] = L->U_host[j * nx + i];
@@ -306,12 +313,23 @@ int lattice_norm2(ufg_lattice h, const void* x, int nrhs, double* out_host) {
     UFG_TRY(k_reduce<double>(*L, (const double2*)x, nullptr, 0, nullptr, K));
   else
     UFG_TRY(k_reduce<float>(*L, (const float2*)x, nullptr, 0, nullptr, K));
-  UFG_TRY(k_finalize(*L, FIN_NORM, vec_blocks(L->N), nullptr, K));
+  UFG_TRY(k_finalize(*L, FIN_NORM, vec_blocks(*L, nrhs), nullptr, K));
   std::vector<RhsState> st(nrhs);
   UFG_HIP(hipMemcpyAsync(st.data(), K.st, sizeof(RhsState) * nrhs, hipMemcpyDeviceToHost,
                          L->stream));
   UFG_HIP(hipStreamSynchronize(L->stream));
   for (int i = 0; i < nrhs; ++i) out_host[i] = st[i].r2;
+  return UFG_OK;
+}
+
+int lattice_tune(ufg_lattice h, int slab, int vec_blocks) {
+  Lattice* L = check_handle(h);
+  UFG_CHECK(L != nullptr, "lattice_tune: NULL handle");
+  UFG_CHECK(slab >= 0 && slab <= L->ntau, "lattice_tune: slab must be 0..ntau");
+  UFG_CHECK(vec_blocks >= 0 && vec_blocks <= 4096, "lattice_tune: vec_blocks must be 0..4096");
+  UFG_HIP(hipStreamSynchronize(L->stream));  // launches in flight used the old shapes
+  L->slab = slab;
+  L->vec_blocks = vec_blocks;
   return UFG_OK;
 }
 

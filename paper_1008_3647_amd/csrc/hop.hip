@@ -19,6 +19,7 @@
 //   epilogue            : coalesced loads of the identity / auxiliary terms,
 //                         one coalesced store, optional fused dot products.
 #include "ufg_internal.h"
+#include "hop_stream.h"
 
 namespace ufg {
 namespace {
@@ -337,12 +338,20 @@ int launch_force_nx(const Lattice& L, const C2<R>* X, const C2<R>* y, int nrhs, 
 
 template <typename R>
 int launch_hop(const Lattice& L, const HopArgs<R>& a) {
+  // M and M^T with the kinetic factor T go through the streaming kernel
+  if (a.shift != 0 && a.mat == fields<R>(L).T && (a.id == nullptr || a.id == a.src) &&
+      stream_supported(L))
+    return launch_hop_stream<R>(L, a);
 #define CALL_HOP(NX) launch_hop_nx<R, NX>(L, a)
   UFG_NX_SWITCH(L.nx, CALL_HOP)
 #undef CALL_HOP
 }
 
 int hop_blocks_per_rhs(const Lattice& L) {
+  if (stream_supported(L)) {
+    const int slab = stream_slab(L);
+    return (L.ntau + slab - 1) / slab;
+  }
   int spw = 256 / (L.nx * L.nx);
   if (spw < 1) spw = 1;
   return (L.ntau + spw - 1) / spw;

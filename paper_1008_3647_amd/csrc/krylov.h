@@ -5,7 +5,6 @@
 
 namespace ufg {
 
-constexpr int kVecBlocks = 1024;  // max blocks per rhs of the vector kernels
 
 // Scalars of one right-hand side, resident on the device.
 struct RhsState {
@@ -50,7 +49,7 @@ enum FinOp {
   FIN_NORM
 };
 
-int vec_blocks(long long n);
+int vec_blocks(const Lattice& L, int nrhs);
 
 template <typename R>
 int k_bicg_p(const Lattice& L, const C2<R>* r, C2<R>* p, const C2<R>* v, const KrylovState& K);
@@ -59,6 +58,9 @@ int k_bicg_s(const Lattice& L, const C2<R>* r, const C2<R>* v, C2<R>* s, const K
 template <typename R>
 int k_bicg_xr(const Lattice& L, C2<R>* x, const C2<R>* phat, const C2<R>* shat, const C2<R>* s,
               const C2<R>* t, C2<R>* r, const C2<R>* rhat, const KrylovState& K);
+template <typename R>
+int k_bicg_xr_fused(const Lattice& L, C2<R>* x, const C2<R>* p, C2<R>* r, const C2<R>* v,
+                    const C2<R>* t, const C2<R>* rhat, const KrylovState& K);
 template <typename R>
 int k_reduce(const Lattice& L, const C2<R>* a, const C2<R>* b, int mode, const int* gate,
              const KrylovState& K);

@@ -7,6 +7,8 @@
 // a kernel block whose rhs is not active returns at once, which lets the
 // host enqueue the same sequence every iteration without reading anything
 // back. Reductions always accumulate in FP64, whatever the vector type.
+#include <algorithm>
+
 #include "krylov.h"
 
 namespace ufg {
@@ -120,6 +122,37 @@ __global__ void __launch_bounds__(256) bicg_xr_kernel(C2<R>* x, const C2<R>* pha
     d0 += double(h.x) * rv.x + double(h.y) * rv.y;
     d1 += double(h.x) * rv.y - double(h.y) * rv.x;
     d2 += double(rv.x) * rv.x + double(rv.y) * rv.y;
+  }
+  bsum4(d0, d1, d2, 0.0, part + ((long long)k * gridDim.x + blockIdx.x) * 4);
+}
+
+// Fused BiCGStab update with s = r - alpha v recomputed instead of stored:
+// x += alpha p + omega s; r = s - omega t; partials <rhat, r>, |r|^2.
+template <typename R>
+__global__ void __launch_bounds__(256) bicg_xr_fused_kernel(C2<R>* x, const C2<R>* p, C2<R>* r,
+                                                            const C2<R>* v, const C2<R>* t,
+                                                            const C2<R>* rhat, const RhsState* st,
+                                                            const int* active, long long n,
+                                                            double* part) {
+  const int k = blockIdx.y;
+  if (!active[k]) return;
+  const RhsState q = st[k];
+  const R ar = R(q.alpha.x), ai = R(q.alpha.y), wr = R(q.omega.x), wi = R(q.omega.y);
+  const long long off = (long long)k * n;
+  double d0 = 0, d1 = 0, d2 = 0;
+  KR_LOOP(n) {
+    const long long j = off + i;
+    const C2<R> pv = p[j], vv = v[j], tv = t[j], h = rhat[j], rv = r[j];
+    const C2<R> sv = c2<R>(rv.x - (ar * vv.x - ai * vv.y), rv.y - (ar * vv.y + ai * vv.x));
+    C2<R> xv = x[j];
+    xv.x += (ar * pv.x - ai * pv.y) + (wr * sv.x - wi * sv.y);
+    xv.y += (ar * pv.y + ai * pv.x) + (wr * sv.y + wi * sv.x);
+    x[j] = xv;
+    const C2<R> rn = c2<R>(sv.x - (wr * tv.x - wi * tv.y), sv.y - (wr * tv.y + wi * tv.x));
+    r[j] = rn;
+    d0 += double(h.x) * rn.x + double(h.y) * rn.y;
+    d1 += double(h.x) * rn.y - double(h.y) * rn.x;
+    d2 += double(rn.x) * rn.x + double(rn.y) * rn.y;
   }
   bsum4(d0, d1, d2, 0.0, part + ((long long)k * gridDim.x + blockIdx.x) * 4);
 }
@@ -397,21 +430,26 @@ __global__ void __launch_bounds__(256) finalize_kernel(int op, const double* par
   st[k] = q;
 }
 
-inline dim3 vgrid(long long n, int nrhs) {
-  long long nb = (n + 1023) / 1024;
-  if (nb > kVecBlocks) nb = kVecBlocks;
-  if (nb < 1) nb = 1;
-  return dim3((unsigned)nb, (unsigned)nrhs);
-}
-
 }  // namespace
 
-int vec_blocks(long long n) {
-  long long nb = (n + 1023) / 1024;
-  if (nb > kVecBlocks) nb = kVecBlocks;
+// Workgroups per rhs of the vector kernels: enough 256-thread groups for
+// about four elements per thread, capped so that all right-hand sides
+// together launch about 2048 groups (grid-stride loops keep them busy).
+int vec_blocks(const Lattice& L, int nrhs) {
+  if (L.vec_blocks > 0) return L.vec_blocks;
+  long long nb = (L.N + 1023) / 1024;
+  const long long cap = std::max(16, 2048 / std::max(1, nrhs));
+  if (nb > cap) nb = cap;
   if (nb < 1) nb = 1;
   return (int)nb;
 }
+
+namespace {
+inline dim3 vgrid_for(const Lattice& L, int nrhs) {
+  return dim3((unsigned)vec_blocks(L, nrhs), (unsigned)nrhs);
+}
+}  // namespace
+#define vgrid(n, nrhs) vgrid_for(L, nrhs)
 
 template <typename R>
 int k_bicg_p(const Lattice& L, const C2<R>* r, C2<R>* p, const C2<R>* v, const KrylovState& K) {
@@ -430,6 +468,13 @@ int k_bicg_xr(const Lattice& L, C2<R>* x, const C2<R>* phat, const C2<R>* shat, 
               const C2<R>* t, C2<R>* r, const C2<R>* rhat, const KrylovState& K) {
   hipLaunchKernelGGL((bicg_xr_kernel<R>), vgrid(L.N, K.nrhs), dim3(256), 0, L.stream, x, phat, shat,
                      s, t, r, rhat, K.st, K.active, L.N, K.part);
+  return UFG_OK;
+}
+template <typename R>
+int k_bicg_xr_fused(const Lattice& L, C2<R>* x, const C2<R>* p, C2<R>* r, const C2<R>* v,
+                    const C2<R>* t, const C2<R>* rhat, const KrylovState& K) {
+  hipLaunchKernelGGL((bicg_xr_fused_kernel<R>), vgrid(L.N, K.nrhs), dim3(256), 0, L.stream, x, p,
+                     r, v, t, rhat, K.st, K.active, L.N, K.part);
   return UFG_OK;
 }
 template <typename R>
@@ -495,6 +540,8 @@ int k_finalize(const Lattice& L, int op, int nblk, const int* gate, const Krylov
                            const KrylovState&);                                                  \
   template int k_bicg_xr<R>(const Lattice&, C2<R>*, const C2<R>*, const C2<R>*, const C2<R>*,    \
                             const C2<R>*, C2<R>*, const C2<R>*, const KrylovState&);             \
+  template int k_bicg_xr_fused<R>(const Lattice&, C2<R>*, const C2<R>*, C2<R>*, const C2<R>*,   \
+                                  const C2<R>*, const C2<R>*, const KrylovState&);               \
   template int k_reduce<R>(const Lattice&, const C2<R>*, const C2<R>*, int, const int*,          \
                            const KrylovState&);                                                  \
   template int k_axpby<R>(const Lattice&, double2, const C2<R>*, double2, C2<R>*, int,           \

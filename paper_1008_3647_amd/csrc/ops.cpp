@@ -38,7 +38,7 @@ template float2* slot_vec<float>(Lattice&, int, int, int*);
 template double2* slot_vec<double>(Lattice&, int, int, int*);
 
 int krylov_state(Lattice& L, int nrhs, KrylovState* K, int slot_red) {
-  const int nblk = std::max(vec_blocks(L.N), hop_blocks_per_rhs(L));
+  const int nblk = std::max(vec_blocks(L, nrhs), hop_blocks_per_rhs(L));
   const size_t st_bytes = sizeof(RhsState) * nrhs;
   const size_t flag_bytes = sizeof(int) * nrhs;
   const size_t red_bytes = sizeof(double) * 4 * (size_t)nblk * nrhs;
@@ -404,7 +404,7 @@ static int estimate_lam_max(Lattice& L, double* out) {
   UFG_HIP(hipMemcpyAsync(v, h.data(), sizeof(double2) * L.N, hipMemcpyHostToDevice, L.stream));
   KrylovState K;
   UFG_TRY(krylov_state(L, 1, &K, SLOT_PSTATE));
-  const int nvb = vec_blocks(L.N);
+  const int nvb = vec_blocks(L, 1);
   double lam = 0.0;
   RhsState hs;
   for (int it = 0; it < 30; ++it) {

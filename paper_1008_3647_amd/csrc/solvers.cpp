@@ -19,6 +19,7 @@
 #include <cmath>
 #include <cstring>
 
+#include "hop_stream.h"
 #include "ops.h"
 
 namespace ufg {
@@ -59,8 +60,9 @@ int inner_vectors(Lattice& L, int nrhs, bool need_pc, bool mixed, C2<R>* x_user,
   return UFG_OK;
 }
 
-int all_inactive(Lattice& L, const KrylovState& K, int* host_flags, bool* done) {
-  UFG_HIP(hipMemcpyAsync(host_flags, K.active, sizeof(int) * K.nrhs, hipMemcpyDeviceToHost,
+// Copies active, update and restart flags (3 nrhs ints) to the host.
+int read_flags(Lattice& L, const KrylovState& K, int* host_flags, bool* done) {
+  UFG_HIP(hipMemcpyAsync(host_flags, K.active, 3 * sizeof(int) * K.nrhs, hipMemcpyDeviceToHost,
                          L.stream));
   UFG_HIP(hipStreamSynchronize(L.stream));
   *done = true;
@@ -85,7 +87,7 @@ int true_relres(Lattice& L, int op, const C2<RO>* x, const C2<RO>* b, int nrhs, 
   UFG_TRY(rc);
   KrylovState K;
   UFG_TRY(krylov_state(L, nrhs, &K, SLOT_PSTATE));
-  const int nvb = vec_blocks(L.N);
+  const int nvb = vec_blocks(L, nrhs);
   if (op == UFG_OP_Q) {
     C2<RO>* tmp = slot_vec<RO>(L, SLOT_OUTER_R + 3, nrhs, &rc);  // slot 15
     UFG_TRY(rc);
@@ -125,7 +127,7 @@ int bicgstab_step(Lattice& L, const PcPlan& pc, int op, const C2<RO>* b, C2<RO>*
   K.prm.mixed = kMixed ? 1 : 0;
   K.prm.bicg = 1;
   K.prm.unprec = need_pc ? 0 : 1;
-  const int nvb = vec_blocks(L.N);
+  const int nvb = vec_blocks(L, nrhs);
   const int nhb = hop_blocks_per_rhs(L);
   const double2 one{1.0, 0.0}, zero{0.0, 0.0};
   int rc = 0;
@@ -163,24 +165,24 @@ int bicgstab_step(Lattice& L, const PcPlan& pc, int op, const C2<RO>* b, C2<RO>*
   }
   UFG_TRY(k_finalize(L, FIN_INIT_R, nvb, nullptr, K));
 
-  std::vector<int> hflags(nrhs);
-  const int check = o.check_every > 0 ? o.check_every : 10;
-  int it = 0;
-  bool done = false;
-  UFG_TRY(all_inactive(L, K, hflags.data(), &done));
-  for (it = 0; it < o.maxit && !done; ++it) {
-    UFG_TRY(k_bicg_p<RI>(L, V.r, V.p, V.v, K));
-    if (need_pc) UFG_TRY(pc_apply<RI>(L, pc, op, V.p, V.phat, nrhs, K.active, cnt));
-    UFG_TRY(op_apply<RI>(L, op, V.phat, V.v, nrhs, K.active, 1, V.rhat, K.part));
-    UFG_TRY(k_finalize(L, FIN_ALPHA, nhb, K.active, K));
-    UFG_TRY(k_bicg_s<RI>(L, V.r, V.v, V.s, K));
-    if (need_pc) UFG_TRY(pc_apply<RI>(L, pc, op, V.s, V.shat, nrhs, K.active, cnt));
-    UFG_TRY(op_apply<RI>(L, op, V.shat, V.t, nrhs, K.active, 2, V.s, K.part));
-    UFG_TRY(k_finalize(L, FIN_OMEGA, nhb, K.active, K));
-    UFG_TRY(k_bicg_xr<RI>(L, V.x, V.phat, V.shat, V.s, V.t, V.r, V.rhat, K));
-    UFG_TRY(k_finalize(L, FIN_RHO, nvb, K.active, K));
-    cnt->mv += 2;
-    // reliable update / convergence verification (only rhs with update set do work)
+  // Unpreconditioned BiCGStab with the streaming operator runs fused: the
+  // p update rides on the first operator launch, s = r - alpha v is formed on
+  // the fly by the second one and recomputed by the x/r update, so s is never
+  // stored. p and v alternate between two buffers (a workgroup reads the halo
+  // slice of the previous iterate while its neighbour writes the new one).
+  const bool fused = !need_pc && stream_supported(L);
+  C2<RI>* P2[2] = {V.p, nullptr};
+  C2<RI>* V2[2] = {V.v, nullptr};
+  if (fused) {
+    P2[1] = slot_vec<RI>(L, SLOT_SOLVER0 + 7, nrhs, &rc);
+    UFG_TRY(rc);
+    V2[1] = slot_vec<RI>(L, SLOT_SOLVER0 + 8, nrhs, &rc);
+    UFG_TRY(rc);
+  }
+  const Fields<RI>& F = fields<RI>(L);
+
+  // reliable update / convergence check for the rhs whose update flag is set
+  auto reliable_update = [&]() -> int {
     if (kMixed) {
       UFG_TRY(k_promote(L, reinterpret_cast<double2*>(x), reinterpret_cast<float2*>(V.x), nrhs,
                         K.update));
@@ -192,10 +194,83 @@ int bicgstab_step(Lattice& L, const PcPlan& pc, int op, const C2<RO>* b, C2<RO>*
                               K.update));
       UFG_TRY(k_reduce<RI>(L, V.r, V.rhat, 3, K.update, K));
     }
-    UFG_TRY(k_finalize(L, FIN_UPDATE, nvb, K.update, K));
-    UFG_TRY(k_restart<RI>(L, V.r, V.rhat, V.p, V.v, K));
-    UFG_TRY(k_finalize(L, FIN_RESTART, 1, K.restart, K));
-    if ((it + 1) % check == 0) UFG_TRY(all_inactive(L, K, hflags.data(), &done));
+    return k_finalize(L, FIN_UPDATE, nvb, K.update, K);
+  };
+  auto restart = [&]() -> int {
+    UFG_TRY(k_restart<RI>(L, V.r, V.rhat, P2[0], V2[0], K));
+    if (fused) UFG_TRY(k_restart<RI>(L, V.r, V.rhat, P2[1], V2[1], K));
+    return k_finalize(L, FIN_RESTART, 1, K.restart, K);
+  };
+
+  std::vector<int> hflags(3 * nrhs);
+  const int check = o.check_every > 0 ? o.check_every : 10;
+  int it = 0;
+  bool done = false;
+  UFG_TRY(read_flags(L, K, hflags.data(), &done));
+  for (it = 0; it < o.maxit && !done; ++it) {
+    if (fused) {
+      const int cur = it & 1;
+      HopArgs<RI> a1;  // v_new = A p_new, p_new = r + beta (p - omega v); <rhat, v_new>
+      a1.src = a1.id = P2[cur ^ 1];
+      a1.dst = V2[cur ^ 1];
+      a1.mat = F.T;
+      a1.nrhs = nrhs;
+      a1.gate = K.active;
+      a1.src_mode = 1;
+      a1.fr = V.r;
+      a1.fp = P2[cur];
+      a1.fv = V2[cur];
+      a1.fpnew = P2[cur ^ 1];
+      a1.st = K.st;
+      a1.red_mode = 1;
+      a1.red_w = V.rhat;
+      a1.red_out = K.part;
+      if (op == UFG_OP_M) {
+        a1.shift = kShiftM;
+        a1.pre = F.b;
+      } else {
+        a1.shift = kShiftMdag;
+        a1.post = F.b;
+      }
+      UFG_TRY(launch_hop<RI>(L, a1));
+      UFG_TRY(k_finalize(L, FIN_ALPHA, nhb, K.active, K));
+      HopArgs<RI> a2 = a1;  // t = A s, s = r - alpha v_new; <t, s>, |t|^2
+      a2.src = a2.id = V2[cur ^ 1];
+      a2.dst = V.t;
+      a2.src_mode = 2;
+      a2.fv = V2[cur ^ 1];
+      a2.fp = nullptr;
+      a2.fpnew = nullptr;
+      a2.red_mode = 3;
+      a2.red_w = nullptr;
+      UFG_TRY(launch_hop<RI>(L, a2));
+      UFG_TRY(k_finalize(L, FIN_OMEGA, nhb, K.active, K));
+      UFG_TRY(k_bicg_xr_fused<RI>(L, V.x, P2[cur ^ 1], V.r, V2[cur ^ 1], V.t, V.rhat, K));
+      UFG_TRY(k_finalize(L, FIN_RHO, nvb, K.active, K));
+    } else {
+      UFG_TRY(k_bicg_p<RI>(L, V.r, V.p, V.v, K));
+      if (need_pc) UFG_TRY(pc_apply<RI>(L, pc, op, V.p, V.phat, nrhs, K.active, cnt));
+      UFG_TRY(op_apply<RI>(L, op, V.phat, V.v, nrhs, K.active, 1, V.rhat, K.part));
+      UFG_TRY(k_finalize(L, FIN_ALPHA, nhb, K.active, K));
+      UFG_TRY(k_bicg_s<RI>(L, V.r, V.v, V.s, K));
+      if (need_pc) UFG_TRY(pc_apply<RI>(L, pc, op, V.s, V.shat, nrhs, K.active, cnt));
+      UFG_TRY(op_apply<RI>(L, op, V.shat, V.t, nrhs, K.active, 2, V.s, K.part));
+      UFG_TRY(k_finalize(L, FIN_OMEGA, nhb, K.active, K));
+      UFG_TRY(k_bicg_xr<RI>(L, V.x, V.phat, V.shat, V.s, V.t, V.r, V.rhat, K));
+      UFG_TRY(k_finalize(L, FIN_RHO, nvb, K.active, K));
+    }
+    cnt->mv += 2;
+    if ((it + 1) % check == 0 || it + 1 == o.maxit) {
+      UFG_TRY(read_flags(L, K, hflags.data(), &done));
+      bool any_update = false, any_restart = false;
+      for (int i = 0; i < nrhs; ++i) {
+        any_update |= hflags[nrhs + i] != 0;
+        any_restart |= hflags[2 * nrhs + i] != 0;
+      }
+      if (any_update) UFG_TRY(reliable_update());
+      if (any_restart) UFG_TRY(restart());
+      if (any_update || any_restart) UFG_TRY(read_flags(L, K, hflags.data(), &done));
+    }
   }
   if (kMixed) {
     UFG_TRY(k_promote(L, reinterpret_cast<double2*>(x), reinterpret_cast<float2*>(V.x), nrhs,
@@ -232,7 +307,7 @@ int cg_solve(Lattice& L, const PcPlan& pc, const C2<RO>* b, C2<RO>* x, int nrhs,
   K.prm.mixed = kMixed ? 1 : 0;
   K.prm.bicg = 0;
   K.prm.unprec = need_pc ? 0 : 1;
-  const int nvb = vec_blocks(L.N);
+  const int nvb = vec_blocks(L, nrhs);
   const int nhb = hop_blocks_per_rhs(L);
   int rc = 0;
   C2<RO>* r64 = kMixed ? slot_vec<RO>(L, SLOT_OUTER_R, nrhs, &rc) : nullptr;
@@ -270,16 +345,7 @@ int cg_solve(Lattice& L, const PcPlan& pc, const C2<RO>* b, C2<RO>* x, int nrhs,
   UFG_TRY(k_finalize(L, FIN_CG_INIT_RZ, nvb, nullptr, K));
   UFG_TRY(k_convert<RI, RI>(L, V.z, V.p, nrhs, nullptr));
 
-  std::vector<int> hflags(nrhs);
-  const int check = o.check_every > 0 ? o.check_every : 10;
-  bool done = false;
-  UFG_TRY(all_inactive(L, K, hflags.data(), &done));
-  for (int it = 0; it < o.maxit && !done; ++it) {
-    UFG_TRY(q_apply<RI>(L, V.p, V.tmp, V.w, nrhs, K.active, 1, V.p, K.part));
-    UFG_TRY(k_finalize(L, FIN_CG_ALPHA, nhb, K.active, K));
-    UFG_TRY(k_cg_xr<RI>(L, V.x, V.p, V.r, V.w, K));
-    UFG_TRY(k_finalize(L, FIN_CG_R, nvb, K.active, K));
-    cnt->mv += 2;
+  auto reliable_update = [&]() -> int {
     if (kMixed) {
       UFG_TRY(k_promote(L, reinterpret_cast<double2*>(x), reinterpret_cast<float2*>(V.x), nrhs,
                         K.update));
@@ -292,13 +358,39 @@ int cg_solve(Lattice& L, const PcPlan& pc, const C2<RO>* b, C2<RO>* x, int nrhs,
       UFG_TRY(k_reduce<RI>(L, V.r, nullptr, 0, K.update, K));
     }
     UFG_TRY(k_finalize(L, FIN_UPDATE, nvb, K.update, K));
+    // the search direction is kept; rz is refreshed from the new residual
+    if (need_pc) {
+      UFG_TRY(pc_apply<RI>(L, pc, UFG_OP_Q, V.r, V.z, nrhs, K.active, cnt));
+      UFG_TRY(k_reduce<RI>(L, V.r, V.z, 1, K.active, K));
+    }
+    return k_finalize(L, FIN_CG_INIT_RZ, nvb, K.active, K);
+  };
+
+  std::vector<int> hflags(3 * nrhs);
+  const int check = o.check_every > 0 ? o.check_every : 10;
+  bool done = false;
+  UFG_TRY(read_flags(L, K, hflags.data(), &done));
+  for (int it = 0; it < o.maxit && !done; ++it) {
+    UFG_TRY(q_apply<RI>(L, V.p, V.tmp, V.w, nrhs, K.active, 1, V.p, K.part));
+    UFG_TRY(k_finalize(L, FIN_CG_ALPHA, nhb, K.active, K));
+    UFG_TRY(k_cg_xr<RI>(L, V.x, V.p, V.r, V.w, K));
+    UFG_TRY(k_finalize(L, FIN_CG_R, nvb, K.active, K));
+    cnt->mv += 2;
     if (need_pc) {
       UFG_TRY(pc_apply<RI>(L, pc, UFG_OP_Q, V.r, V.z, nrhs, K.active, cnt));
       UFG_TRY(k_reduce<RI>(L, V.r, V.z, 1, K.active, K));
     }
     UFG_TRY(k_finalize(L, FIN_CG_BETA, nvb, K.active, K));
     UFG_TRY(k_cg_p<RI>(L, V.z, V.p, K));
-    if ((it + 1) % check == 0) UFG_TRY(all_inactive(L, K, hflags.data(), &done));
+    if ((it + 1) % check == 0 || it + 1 == o.maxit) {
+      UFG_TRY(read_flags(L, K, hflags.data(), &done));
+      bool any_update = false;
+      for (int i = 0; i < nrhs; ++i) any_update |= hflags[nrhs + i] != 0;
+      if (any_update) {
+        UFG_TRY(reliable_update());
+        UFG_TRY(read_flags(L, K, hflags.data(), &done));
+      }
+    }
   }
   if (kMixed) {
     UFG_TRY(k_promote(L, reinterpret_cast<double2*>(x), reinterpret_cast<float2*>(V.x), nrhs,

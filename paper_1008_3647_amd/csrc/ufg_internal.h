@@ -84,6 +84,9 @@ struct Lattice {
   Fields<double> f64;
   Fields<float> f32;
   std::vector<double> T_host, U_host, lam1_host;  // 1D factors (host)
+  std::vector<double> split_host;  // block-diagonal form of T (streaming kernel)
+  int slab = 0;                    // time slices per workgroup of the streaming kernel (0: default)
+  int vec_blocks = 0;              // workgroups per rhs of the vector kernels (0: default)
   DevBuf work[24];          // vector workspaces (solver / preconditioner)
   DevBuf red;               // reduction partials
   DevBuf state;             // solver state
@@ -129,7 +132,17 @@ struct HopArgs {
   //   red_mode 1: <w, dst>  (complex)        red_mode 2: <dst, id>, <dst, dst>
   int red_mode = 0;
   const C2<R>* red_w = nullptr;
-  double* red_out = nullptr;  // [nrhs][nblk_per_rhs][3]
+  double* red_out = nullptr;  // [nrhs][nblk_per_rhs][4]
+  // Fused BiCGStab source (streaming kernel only). src_mode 0: the source is
+  // `src`. 1: p = r + beta (p_old - omega v_old) with beta, omega of the rhs
+  // state, stored to fpnew for the workgroup's own slices. 2: s = r - alpha v.
+  // red_mode 3 then gives <out, source> and |out|^2.
+  int src_mode = 0;
+  const C2<R>* fr = nullptr;
+  const C2<R>* fp = nullptr;
+  const C2<R>* fv = nullptr;
+  C2<R>* fpnew = nullptr;
+  const void* st = nullptr;  // RhsState array
 };
 
 template <typename R>

@@ -144,6 +144,10 @@ class Lattice:
         L.check(code, "solve_bicgstab")
         return x, st.as_dict()
 
+    def tune(self, slab=0, vec_blocks=0):
+        """Launch parameters (0 = library default); see lattice_tune in ufg.h."""
+        L.check(self._lib.lattice_tune(self._h, int(slab), int(vec_blocks)), "lattice_tune")
+
     def norm2(self, x):
         """||x_r||^2 per right-hand side (host list), FP64 accumulation."""
         n = self._vec(x, "x")

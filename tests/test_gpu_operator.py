@@ -19,7 +19,8 @@ TOL = {torch.complex128: 1e-13, torch.complex64: 5e-6}
 # (nx, ntau, nrhs): every supported Nx, slices-per-workgroup tails, the two
 # smallest cases and the antiperiodic corner at Ntau = 2.
 SHAPES = [(2, 2, 1), (2, 3, 2), (4, 40, 1), (4, 17, 2), (6, 9, 3), (8, 5, 2), (10, 3, 2),
-          (12, 4, 1), (14, 3, 1), (16, 6, 2), (8, 160, 4)]
+          (12, 4, 1), (14, 3, 1), (16, 6, 2), (8, 160, 4), (16, 2, 1), (8, 9, 3), (12, 7, 2),
+          (16, 13, 3)]
 
 
 def _oracle(fn, x, sigma):
