@@ -185,16 +185,31 @@ int solve_bicgstab(ufg_lattice L, const ufg_precond* p, int op, const void* b,
                    ufg_solve_stats* st);
 
 /*
- * solve_batched -- nprob independent two-step BiCGStab solves, one lattice
- *   each (lattices may differ in Nx and Ntau), run by one persistent kernel
- *   per phase from a shared work table; nrhs[i] right-hand sides per problem.
- *   b[i], x[i]: device complex128 vectors of lattice i (mixed precision is
- *   taken from o->mixed). p: NULL or UFG_PC_NONE. st: array of nprob stats
- *   (may be NULL). Returns the worst status.
+ * solve_batched -- nprob independent two-step BiCGStab solves (M^dagger y = b,
+ *   then M x = y; paper, Eq. 2), one lattice each (lattices may differ in Nx
+ *   and Ntau), nrhs[i] right-hand sides per problem. Every phase of an
+ *   iteration is one persistent launch over a work table covering all
+ *   problems, the iteration body is replayed from a captured HIP graph, and
+ *   every (problem, rhs) keeps its own device state and stops on its own.
+ *   Ls[i]: complex128 lattices (fields installed). b[i], x[i]: device
+ *   complex128 vectors [nrhs[i]][Ntau][Nx]^3 of lattice i. o->mixed: complex64
+ *   inner iteration with FP64 reliable updates (else complex128 inner).
+ *   o->use_x0 must be 0. p: NULL or UFG_PC_NONE. st: array of nprob stats (may
+ *   be NULL; seconds is the wall time of the whole batch). Synchronous; uses
+ *   its own stream after synchronising the lattices' streams. Returns the
+ *   worst status.
  */
 int solve_batched(const ufg_lattice* Ls, int nprob, const void* const* b,
                   void* const* x, const int* nrhs, const ufg_precond* p,
                   const ufg_solve_opts* o, ufg_solve_stats* st);
+
+/*
+ * solve_batched_tune -- launch shape of solve_batched chosen by the autotuner
+ *   (0 keeps the default): workgroups per compute unit of the persistent
+ *   operator and vector launches (1..64) and elements per vector work item
+ *   (256..4194304). Process-wide; not thread safe against concurrent solves.
+ */
+int solve_batched_tune(int hop_blocks_per_cu, int vec_blocks_per_cu, long long chunk);
 
 /*
  * force_dS_dsigma -- gradient of S = sum_r phi_r^dagger (M^dagger M)^{-1} phi_r

@@ -39,6 +39,10 @@ int solve_bicgstab_impl(Lattice& L, const ufg_precond* p, int op, const void* b,
 int solve_cg_impl(Lattice& L, const ufg_precond* p, const void* b, void* x, int nrhs,
                   const ufg_solve_opts* o, ufg_solve_stats* st);
 int cheb_plan(int degree, double eps, std::vector<double2>* roots, double2* cf);
+int solve_batched_impl(const ufg_lattice* Ls, int nprob, const void* const* b, void* const* x,
+                       const int* nrhs, const ufg_precond* p, const ufg_solve_opts* o,
+                       ufg_solve_stats* st);
+int batched_tune(int hop_blocks_per_cu, int vec_blocks_per_cu, long long chunk);
 int euler_weights(int order, double p, double* w);
 
 // T_{xy} = (1/Nx) sum_m exp(-tau k_m^2 / 2) cos(k_m (x - y)), k_m = 2 pi m / Nx,
@@ -381,16 +385,11 @@ int ufg_transfer_matrix(int nx, double tau, double* out) {
 int solve_batched(const ufg_lattice* Ls, int nprob, const void* const* b, void* const* x,
                   const int* nrhs, const ufg_precond* p, const ufg_solve_opts* o,
                   ufg_solve_stats* st) {
-  (void)Ls;
-  (void)nprob;
-  (void)b;
-  (void)x;
-  (void)nrhs;
-  (void)p;
-  (void)o;
-  (void)st;
-  set_error("solve_batched: not available yet");
-  return UFG_EINVAL;
+  return solve_batched_impl(Ls, nprob, b, x, nrhs, p, o, st);
+}
+
+int solve_batched_tune(int hop_blocks_per_cu, int vec_blocks_per_cu, long long chunk) {
+  return batched_tune(hop_blocks_per_cu, vec_blocks_per_cu, chunk);
 }
 
 }  // extern "C"

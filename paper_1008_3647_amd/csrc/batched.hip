@@ -1,2 +1,703 @@
-// Batched persistent solver (placeholder translation unit; filled in below).
-#include "ufg_internal.h"
+// Batched two-step BiCGStab over many independent lattices (uneven Nx, Ntau).
+//
+// All systems (problem, right-hand side) of the batch are "segments" of one
+// set of concatenated Krylov vectors, each with its own device-resident
+// scalars and flags. Every phase of an iteration is ONE launch over the whole
+// batch: a persistent grid (compute units x occupancy) walks a work table of
+// (segment, slice group) items for the operator and (segment, chunk) items for
+// the vector updates, so small lattices share the GPU instead of each paying
+// its own launches. The iteration body of one check interval is captured once
+// in a hipGraph and replayed; between replays the host reads the flags and
+// runs the reliable updates (FP64 residual of the outer complex128 vectors)
+// and restarts for the segments that asked for them.
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstring>
+
+#include "hop_common.h"
+#include "ops.h"
+
+namespace ufg {
+namespace {
+using namespace hopc;
+
+struct BSeg {
+  int nx, ntau, V, spw;
+  long long n;    // elements of one vector of this system
+  long long off;  // offset of the segment in the concatenated inner vectors
+  const double2* b64;
+  double2* x64;
+  double2* r64;
+  const float* f32;  // 1 + A sin sigma of the problem
+  const double* f64;
+  const float* T32;  // Nx x Nx transfer factor
+  const double* T64;
+};
+struct BHop {
+  int seg, t0;
+};
+struct BVec {
+  int seg;
+  long long lo, hi;
+};
+
+int g_hop_blocks_per_cu = 4;
+int g_vec_blocks_per_cu = 8;
+long long g_chunk = 4096;
+
+template <typename R>
+__device__ __forceinline__ const R* fld(const BSeg& g);
+template <>
+__device__ __forceinline__ const float* fld<float>(const BSeg& g) { return g.f32; }
+template <>
+__device__ __forceinline__ const double* fld<double>(const BSeg& g) { return g.f64; }
+template <typename R>
+__device__ __forceinline__ const R* tmat(const BSeg& g);
+template <>
+__device__ __forceinline__ const float* tmat<float>(const BSeg& g) { return g.T32; }
+template <>
+__device__ __forceinline__ const double* tmat<double>(const BSeg& g) { return g.T64; }
+
+__device__ __forceinline__ double wsum(double v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+  return v;
+}
+
+// Block sum of 4 doubles into out[0..3] (thread 0 writes). `scratch` >= 4 doubles x 4 waves.
+__device__ void bsum4b(double a0, double a1, double a2, double a3, double* out, double* scratch) {
+  a0 = wsum(a0);
+  a1 = wsum(a1);
+  a2 = wsum(a2);
+  a3 = wsum(a3);
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  __syncthreads();
+  if (lane == 0) {
+    scratch[wid * 4 + 0] = a0;
+    scratch[wid * 4 + 1] = a1;
+    scratch[wid * 4 + 2] = a2;
+    scratch[wid * 4 + 3] = a3;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double s0 = 0, s1 = 0, s2 = 0, s3 = 0;
+    for (int w = 0; w < (int)(blockDim.x >> 6); ++w) {
+      s0 += scratch[w * 4 + 0];
+      s1 += scratch[w * 4 + 1];
+      s2 += scratch[w * 4 + 2];
+      s3 += scratch[w * 4 + 3];
+    }
+    out[0] = s0;
+    out[1] = s1;
+    out[2] = s2;
+    out[3] = s3;
+  }
+  __syncthreads();
+}
+
+// Transform of one slice held as z-lines (thread (y,x) of its slice); threads
+// with act == false take part in the barriers only.
+template <typename R, int NX>
+__device__ __forceinline__ void guarded_transform(const R* __restrict__ mat, C2<R>* my, int l,
+                                                  bool act, C2<R> (&v)[NX], C2<R> (&w)[NX]) {
+  constexpr int LD = NX + 1;
+  const int y = l / NX, x = l - (l / NX) * NX;
+  if (act) {
+    line_transform<R, NX>(mat, v, w);
+#pragma unroll
+    for (int z = 0; z < NX; ++z) my[(z * NX + y) * LD + x] = w[z];
+  }
+  __syncthreads();
+  if (act) {
+    const int z = l / NX, xx = l - (l / NX) * NX;
+#pragma unroll
+    for (int yy = 0; yy < NX; ++yy) v[yy] = my[(z * NX + yy) * LD + xx];
+    line_transform<R, NX>(mat, v, w);
+#pragma unroll
+    for (int yy = 0; yy < NX; ++yy) my[(z * NX + yy) * LD + xx] = w[yy];
+  }
+  __syncthreads();
+  if (act) {
+    const int z = l / NX, yy = l - (l / NX) * NX;
+    C2<R>* row = my + (z * NX + yy) * LD;
+#pragma unroll
+    for (int xx = 0; xx < NX; ++xx) v[xx] = row[xx];
+    line_transform<R, NX>(mat, v, w);
+#pragma unroll
+    for (int xx = 0; xx < NX; ++xx) row[xx] = w[xx];
+  }
+  __syncthreads();
+  if (act) {
+#pragma unroll
+    for (int z = 0; z < NX; ++z) w[z] = my[(z * NX + y) * LD + x];
+  }
+}
+
+// One operator work item: y_t = x_t + sgn T^3(...) for the item's slices.
+// RES: y = b - (M x) on the outer FP64 vectors of the segment.
+template <typename R, int NX, int DIR, bool RES>
+__device__ void hop_item(const BSeg& g, int t0, const C2<R>* src, C2<R>* dst, const C2<R>* aux,
+                         int red_mode, const C2<R>* redw, double* part_out, C2<R>* lds,
+                         double* scratch) {
+  constexpr int P = NX * NX, V = NX * NX * NX, SPW = (256 / P) > 0 ? 256 / P : 1;
+  constexpr int SL = NX * NX * (NX + 1);
+  const int tid = threadIdx.x;
+  const int sub = tid / P, l = tid - (tid / P) * P;
+  const bool inb = sub < SPW;
+  const int t = t0 + (inb ? sub : 0);
+  const bool valid = inb && t < g.ntau;
+  int ts = t + (DIR < 0 ? -1 : 1);
+  if (ts < 0) ts += g.ntau;
+  if (ts >= g.ntau) ts -= g.ntau;
+  const R* f = fld<R>(g);
+  C2<R> v[NX], w[NX];
+  if (valid) {
+#pragma unroll
+    for (int z = 0; z < NX; ++z) v[z] = src[(long long)ts * V + z * P + l];
+    if (DIR < 0) {
+#pragma unroll
+      for (int z = 0; z < NX; ++z) {
+        const R fz = f[(long long)ts * V + z * P + l];
+        v[z].x *= fz;
+        v[z].y *= fz;
+      }
+    }
+  }
+  guarded_transform<R, NX>(tmat<R>(g), lds + (inb ? sub : 0) * SL, l, valid, v, w);
+  double a0 = 0, a1 = 0, a2 = 0, a3 = 0;
+  if (valid) {
+    R sgn;
+    if (DIR < 0)
+      sgn = (ts == g.ntau - 1) ? R(1) : R(-1);
+    else
+      sgn = (t == g.ntau - 1) ? R(1) : R(-1);
+#pragma unroll
+    for (int z = 0; z < NX; ++z) {
+      const long long idx = (long long)t * V + z * P + l;
+      R c = sgn;
+      if (DIR > 0) c *= f[idx];
+      const C2<R> xi = src[idx];
+      C2<R> out = mk<R>(xi.x + c * w[z].x, xi.y + c * w[z].y);
+      if (RES) {
+        const C2<R> bb = aux[idx];
+        out = mk<R>(bb.x - out.x, bb.y - out.y);
+      }
+      dst[idx] = out;
+      if (red_mode == 1) {
+        const C2<R> q = redw[idx];
+        a0 += double(q.x) * out.x + double(q.y) * out.y;
+        a1 += double(q.x) * out.y - double(q.y) * out.x;
+      } else if (red_mode == 2) {
+        const C2<R> q = redw[idx];
+        a0 += double(out.x) * q.x + double(out.y) * q.y;
+        a1 += double(out.x) * q.y - double(out.y) * q.x;
+        a2 += double(out.x) * out.x + double(out.y) * out.y;
+        a3 += double(q.x) * q.x + double(q.y) * q.y;
+      }
+    }
+  }
+  if (red_mode) bsum4b(a0, a1, a2, a3, part_out, scratch);
+}
+
+template <typename R, int DIR, bool RES>
+__global__ void __launch_bounds__(256)
+    bhop_kernel(const BSeg* __restrict__ segs, const BHop* __restrict__ items, int nitems,
+                const C2<R>* src_cat, C2<R>* dst_cat, int red_mode, const C2<R>* redw_cat,
+                double* part, const int* gate) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  C2<R>* lds = reinterpret_cast<C2<R>*>(smem_raw);
+  __shared__ double scratch[16];
+  for (int it = blockIdx.x; it < nitems; it += gridDim.x) {
+    const BHop h = items[it];
+    if (gate && gate[h.seg] == 0) continue;
+    const BSeg g = segs[h.seg];
+    const C2<R>* src;
+    C2<R>* dst;
+    const C2<R>* aux = nullptr;
+    if (RES) {
+      src = reinterpret_cast<const C2<R>*>(g.x64);
+      dst = reinterpret_cast<C2<R>*>(g.r64);
+      aux = reinterpret_cast<const C2<R>*>(g.b64);
+    } else {
+      src = src_cat + g.off;
+      dst = dst_cat + g.off;
+    }
+    const C2<R>* redw = redw_cat ? redw_cat + g.off : nullptr;
+    double* po = part + (long long)it * 4;
+    switch (g.nx) {
+#define BH(NXV)                                                                              \
+  case NXV:                                                                                  \
+    hop_item<R, NXV, DIR, RES>(g, h.t0, src, dst, aux, red_mode, redw, po, lds, scratch);    \
+    break;
+      BH(2) BH(4) BH(6) BH(8) BH(10) BH(12) BH(14) BH(16)
+#undef BH
+      default:
+        break;
+    }
+    __syncthreads();  // LDS is reused by the next item
+  }
+}
+
+#define BV_LOOP(v) for (long long i = v.lo + threadIdx.x; i < v.hi; i += blockDim.x)
+
+__device__ __forceinline__ double2 cmul(double2 a, double2 b) {
+  return double2{a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x};
+}
+__device__ __forceinline__ double2 cdiv(double2 a, double2 b) {
+  const double d = b.x * b.x + b.y * b.y;
+  return double2{(a.x * b.x + a.y * b.y) / d, (a.y * b.x - a.x * b.y) / d};
+}
+
+// Vector phases. op: 0 p-update, 1 s-update, 2 x/r update (+partials),
+// 3 init (x_in = 0, r = b, rhat = r, p = v = 0; |b|^2 partials, x64 = 0),
+// 4 promote (x64 += x_in, x_in = 0), 5 demote (r = r64; <rhat, r>, |r64|^2),
+// 6 restart (rhat = r, p = v = 0), 7 |b64|^2 partials, 8 |r64|^2 partials.
+struct BVecArgs {
+  void* x;
+  void* r;
+  void* rhat;
+  void* p;
+  void* v;
+  void* s;
+  void* t;
+};
+
+template <typename R>
+__global__ void __launch_bounds__(256)
+    bvec_kernel(int op, const BSeg* __restrict__ segs, const BVec* __restrict__ items, int nitems,
+                BVecArgs A, const RhsState* st, const int* gate, double* part) {
+  __shared__ double scratch[16];
+  C2<R>* X = reinterpret_cast<C2<R>*>(A.x);
+  C2<R>* Rr = reinterpret_cast<C2<R>*>(A.r);
+  C2<R>* Rh = reinterpret_cast<C2<R>*>(A.rhat);
+  C2<R>* Pp = reinterpret_cast<C2<R>*>(A.p);
+  C2<R>* Vv = reinterpret_cast<C2<R>*>(A.v);
+  C2<R>* Ss = reinterpret_cast<C2<R>*>(A.s);
+  C2<R>* Tt = reinterpret_cast<C2<R>*>(A.t);
+  for (int it = blockIdx.x; it < nitems; it += gridDim.x) {
+    const BVec item = items[it];
+    if (gate && gate[item.seg] == 0) continue;
+    const BSeg g = segs[item.seg];
+    const long long o = g.off;
+    const RhsState q = st[item.seg];
+    double a0 = 0, a1 = 0, a2 = 0;
+    if (op == 0) {
+      const double2 beta = cmul(cdiv(q.rho, q.rho_old), cdiv(q.alpha, q.omega));
+      const R br = R(beta.x), bi = R(beta.y), wr = R(q.omega.x), wi = R(q.omega.y);
+      BV_LOOP(item) {
+        const C2<R> rv = Rr[o + i], pv = Pp[o + i], vv = Vv[o + i];
+        const R dx = pv.x - (wr * vv.x - wi * vv.y), dy = pv.y - (wr * vv.y + wi * vv.x);
+        Pp[o + i] = mk<R>(rv.x + br * dx - bi * dy, rv.y + br * dy + bi * dx);
+      }
+    } else if (op == 1) {
+      const R ar = R(q.alpha.x), ai = R(q.alpha.y);
+      BV_LOOP(item) {
+        const C2<R> rv = Rr[o + i], vv = Vv[o + i];
+        Ss[o + i] = mk<R>(rv.x - (ar * vv.x - ai * vv.y), rv.y - (ar * vv.y + ai * vv.x));
+      }
+    } else if (op == 2) {
+      const R ar = R(q.alpha.x), ai = R(q.alpha.y), wr = R(q.omega.x), wi = R(q.omega.y);
+      BV_LOOP(item) {
+        const C2<R> pv = Pp[o + i], sv = Ss[o + i], tv = Tt[o + i], h = Rh[o + i];
+        C2<R> xv = X[o + i];
+        xv.x += (ar * pv.x - ai * pv.y) + (wr * sv.x - wi * sv.y);
+        xv.y += (ar * pv.y + ai * pv.x) + (wr * sv.y + wi * sv.x);
+        X[o + i] = xv;
+        const C2<R> rn = mk<R>(sv.x - (wr * tv.x - wi * tv.y), sv.y - (wr * tv.y + wi * tv.x));
+        Rr[o + i] = rn;
+        a0 += double(h.x) * rn.x + double(h.y) * rn.y;
+        a1 += double(h.x) * rn.y - double(h.y) * rn.x;
+        a2 += double(rn.x) * rn.x + double(rn.y) * rn.y;
+      }
+    } else if (op == 3) {
+      BV_LOOP(item) {
+        const double2 bb = g.b64[i];
+        const C2<R> rv = mk<R>(R(bb.x), R(bb.y));
+        X[o + i] = mk<R>(R(0), R(0));
+        Rr[o + i] = rv;
+        Rh[o + i] = rv;
+        Pp[o + i] = mk<R>(R(0), R(0));
+        Vv[o + i] = mk<R>(R(0), R(0));
+        g.x64[i] = double2{0.0, 0.0};
+        a2 += bb.x * bb.x + bb.y * bb.y;
+      }
+    } else if (op == 4) {
+      BV_LOOP(item) {
+        const C2<R> v = X[o + i];
+        double2 w = g.x64[i];
+        w.x += double(v.x);
+        w.y += double(v.y);
+        g.x64[i] = w;
+        X[o + i] = mk<R>(R(0), R(0));
+      }
+    } else if (op == 5) {
+      BV_LOOP(item) {
+        const double2 v = g.r64[i];
+        Rr[o + i] = mk<R>(R(v.x), R(v.y));
+        const C2<R> h = Rh[o + i];
+        a0 += double(h.x) * v.x + double(h.y) * v.y;
+        a1 += double(h.x) * v.y - double(h.y) * v.x;
+        a2 += v.x * v.x + v.y * v.y;
+      }
+    } else if (op == 6) {
+      BV_LOOP(item) {
+        Rh[o + i] = Rr[o + i];
+        Pp[o + i] = mk<R>(R(0), R(0));
+        Vv[o + i] = mk<R>(R(0), R(0));
+      }
+    } else if (op == 7) {
+      BV_LOOP(item) {
+        const double2 bb = g.b64[i];
+        a2 += bb.x * bb.x + bb.y * bb.y;
+      }
+    } else if (op == 8) {
+      BV_LOOP(item) {
+        const double2 v = g.r64[i];
+        a2 += v.x * v.x + v.y * v.y;
+      }
+    }
+    if (op == 2 || op == 3 || op == 5 || op >= 7)
+      bsum4b(a0, a1, a2, 0.0, part + (long long)it * 4, scratch);
+  }
+}
+
+// --------------------------------------------------------------------------
+
+struct Dev {
+  void* p = nullptr;
+  ~Dev() {
+    if (p) (void)hipFree(p);
+  }
+  int alloc(size_t bytes) {
+    if (hipMalloc(&p, bytes) != hipSuccess) {
+      p = nullptr;
+      (void)hipGetLastError();
+      set_error("solve_batched: device allocation failed");
+      return UFG_ENOMEM;
+    }
+    return UFG_OK;
+  }
+};
+
+struct Graph {
+  hipGraph_t g = nullptr;
+  hipGraphExec_t e = nullptr;
+  ~Graph() {
+    if (e) (void)hipGraphExecDestroy(e);
+    if (g) (void)hipGraphDestroy(g);
+  }
+};
+
+template <typename RI>
+int run_batched(std::vector<Lattice*>& Ls, const void* const* bu, void* const* xu,
+                const int* nrhs, const ufg_solve_opts& o, ufg_solve_stats* stats) {
+  const int nprob = (int)Ls.size();
+  int ncu = 256;
+  (void)hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, Ls[0]->device);
+  // segments and work tables
+  std::vector<BSeg> segs;
+  std::vector<int> seg_prob;
+  long long total = 0;
+  size_t lds_bytes = 0;
+  for (int i = 0; i < nprob; ++i) {
+    Lattice& L = *Ls[i];
+    for (int r = 0; r < nrhs[i]; ++r) {
+      BSeg g{};
+      g.nx = L.nx;
+      g.ntau = L.ntau;
+      g.V = L.V;
+      g.spw = std::max(1, 256 / (L.nx * L.nx));
+      g.n = L.N;
+      g.off = total;
+      g.f32 = L.f32.b;
+      g.f64 = L.f64.b;
+      g.T32 = L.f32.T;
+      g.T64 = L.f64.T;
+      total += L.N;
+      segs.push_back(g);
+      seg_prob.push_back(i);
+      lds_bytes = std::max(lds_bytes, size_t(g.spw) * L.nx * L.nx * (L.nx + 1) * sizeof(double2));
+    }
+  }
+  const int S = (int)segs.size();
+  std::vector<BHop> hops;
+  std::vector<int> hfirst(S), hcount(S);
+  std::vector<BVec> vecs;
+  std::vector<int> vfirst(S), vcount(S);
+  for (int s = 0; s < S; ++s) {
+    hfirst[s] = (int)hops.size();
+    for (int t0 = 0; t0 < segs[s].ntau; t0 += segs[s].spw) hops.push_back(BHop{s, t0});
+    hcount[s] = (int)hops.size() - hfirst[s];
+    vfirst[s] = (int)vecs.size();
+    for (long long lo = 0; lo < segs[s].n; lo += g_chunk)
+      vecs.push_back(BVec{s, lo, std::min(segs[s].n, lo + g_chunk)});
+    vcount[s] = (int)vecs.size() - vfirst[s];
+  }
+  // device memory
+  const size_t vbytes = sizeof(C2<RI>) * (size_t)total;
+  Dev dvec[7], dr64, dy, dsegs, dhops, dvecs, dtab, dhpart, dvpart, dstate;
+  for (auto& d : dvec) UFG_TRY(d.alloc(vbytes));
+  UFG_TRY(dr64.alloc(sizeof(double2) * (size_t)total));
+  UFG_TRY(dy.alloc(sizeof(double2) * (size_t)total));
+  UFG_TRY(dsegs.alloc(sizeof(BSeg) * S));
+  UFG_TRY(dhops.alloc(sizeof(BHop) * hops.size()));
+  UFG_TRY(dvecs.alloc(sizeof(BVec) * vecs.size()));
+  UFG_TRY(dtab.alloc(sizeof(int) * 4 * S));
+  UFG_TRY(dhpart.alloc(sizeof(double) * 4 * hops.size()));
+  UFG_TRY(dvpart.alloc(sizeof(double) * 4 * vecs.size()));
+  UFG_TRY(dstate.alloc(sizeof(RhsState) * S + sizeof(int) * 3 * S));
+  hipStream_t cs = nullptr;
+  UFG_HIP(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking));
+  struct StreamGuard {
+    hipStream_t s;
+    ~StreamGuard() {
+      if (s) (void)hipStreamDestroy(s);
+    }
+  } guard{cs};
+  int* tab = reinterpret_cast<int*>(dtab.p);
+  std::vector<int> htab(4 * S);
+  for (int s = 0; s < S; ++s) {
+    htab[s] = hfirst[s];
+    htab[S + s] = hcount[s];
+    htab[2 * S + s] = vfirst[s];
+    htab[3 * S + s] = vcount[s];
+  }
+  UFG_HIP(hipMemcpyAsync(tab, htab.data(), sizeof(int) * 4 * S, hipMemcpyHostToDevice, cs));
+  UFG_HIP(hipMemcpyAsync(dhops.p, hops.data(), sizeof(BHop) * hops.size(), hipMemcpyHostToDevice,
+                         cs));
+  UFG_HIP(hipMemcpyAsync(dvecs.p, vecs.data(), sizeof(BVec) * vecs.size(), hipMemcpyHostToDevice,
+                         cs));
+  KrylovState K;
+  K.nrhs = S;
+  K.st = reinterpret_cast<RhsState*>(dstate.p);
+  K.active = reinterpret_cast<int*>(K.st + S);
+  K.update = K.active + S;
+  K.restart = K.update + S;
+  K.part = reinterpret_cast<double*>(dvpart.p);
+  K.prm.tol = o.tol;
+  K.prm.delta2 = o.delta * o.delta;
+  K.prm.mixed = 1;  // inner vectors are corrections to the FP64 x (reliable updates)
+  K.prm.bicg = 1;
+  K.prm.unprec = 1;
+  K.prm.limit_omega = 1;
+  const int* hf = tab;
+  const int* hc = tab + S;
+  const int* vf = tab + 2 * S;
+  const int* vc = tab + 3 * S;
+  double* hpart = reinterpret_cast<double*>(dhpart.p);
+  double* vpart = reinterpret_cast<double*>(dvpart.p);
+  BVecArgs VA{dvec[0].p, dvec[1].p, dvec[2].p, dvec[3].p, dvec[4].p, dvec[5].p, dvec[6].p};
+  C2<RI>* vp = reinterpret_cast<C2<RI>*>(dvec[3].p);
+  C2<RI>* vv = reinterpret_cast<C2<RI>*>(dvec[4].p);
+  C2<RI>* vs = reinterpret_cast<C2<RI>*>(dvec[5].p);
+  C2<RI>* vt = reinterpret_cast<C2<RI>*>(dvec[6].p);
+  C2<RI>* vrh = reinterpret_cast<C2<RI>*>(dvec[2].p);
+  const BSeg* dseg = reinterpret_cast<const BSeg*>(dsegs.p);
+  const BHop* dhop = reinterpret_cast<const BHop*>(dhops.p);
+  const BVec* dvv = reinterpret_cast<const BVec*>(dvecs.p);
+  const int nh = (int)hops.size(), nv = (int)vecs.size();
+  const dim3 hgrid(std::min(nh, ncu * g_hop_blocks_per_cu)),
+      vgrid(std::min(nv, ncu * g_vec_blocks_per_cu));
+  const size_t lds = std::max<size_t>(lds_bytes, 64);
+  // attributes are set before any capture
+  UFG_HIP(hipFuncSetAttribute((const void*)bhop_kernel<RI, -1, false>,
+                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+  UFG_HIP(hipFuncSetAttribute((const void*)bhop_kernel<RI, 1, false>,
+                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+  UFG_HIP(hipFuncSetAttribute((const void*)bhop_kernel<double, -1, true>,
+                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+  UFG_HIP(hipFuncSetAttribute((const void*)bhop_kernel<double, 1, true>,
+                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+  const int check = o.check_every > 0 ? o.check_every : 10;
+  std::vector<RhsState> hst(S);
+  std::vector<int> hflags(3 * S);
+  std::vector<int> iters_step[2];
+  std::vector<double> relres_step[2];
+  std::vector<int> status(nprob, 0);
+
+  for (int step = 0; step < 2; ++step) {
+    const int dir = (step == 0) ? +1 : -1;  // M^T first, then M
+    for (int s = 0; s < S; ++s) {
+      const int i = seg_prob[s];
+      const int r = s - (int)(std::lower_bound(seg_prob.begin(), seg_prob.end(), i) -
+                              seg_prob.begin());
+      const long long N = Ls[i]->N;
+      double2* ycat = reinterpret_cast<double2*>(dy.p) + segs[s].off;
+      if (step == 0) {
+        segs[s].b64 = reinterpret_cast<const double2*>(bu[i]) + r * N;
+        segs[s].x64 = ycat;
+      } else {
+        segs[s].b64 = ycat;
+        segs[s].x64 = reinterpret_cast<double2*>(xu[i]) + r * N;
+      }
+      segs[s].r64 = reinterpret_cast<double2*>(dr64.p) + segs[s].off;
+    }
+    UFG_HIP(hipMemcpyAsync(dsegs.p, segs.data(), sizeof(BSeg) * S, hipMemcpyHostToDevice, cs));
+    auto hop = [&](int red_mode, const C2<RI>* src, C2<RI>* dst, const C2<RI>* redw) {
+      if (dir < 0)
+        hipLaunchKernelGGL((bhop_kernel<RI, -1, false>), hgrid, dim3(256), lds, cs, dseg, dhop, nh,
+                           src, dst, red_mode, redw, hpart, K.active);
+      else
+        hipLaunchKernelGGL((bhop_kernel<RI, 1, false>), hgrid, dim3(256), lds, cs, dseg, dhop, nh,
+                           src, dst, red_mode, redw, hpart, K.active);
+    };
+    auto residual = [&](const int* gate) {
+      if (dir < 0)
+        hipLaunchKernelGGL((bhop_kernel<double, -1, true>), hgrid, dim3(256), lds, cs, dseg, dhop,
+                           nh, (const double2*)nullptr, (double2*)nullptr, 0,
+                           (const double2*)nullptr, hpart, gate);
+      else
+        hipLaunchKernelGGL((bhop_kernel<double, 1, true>), hgrid, dim3(256), lds, cs, dseg, dhop,
+                           nh, (const double2*)nullptr, (double2*)nullptr, 0,
+                           (const double2*)nullptr, hpart, gate);
+    };
+    auto vop = [&](int op, const int* gate) {
+      hipLaunchKernelGGL((bvec_kernel<RI>), vgrid, dim3(256), 0, cs, op, dseg, dvv, nv, VA, K.st,
+                         gate, vpart);
+    };
+    // initial state: x = 0, r = b, rhat = r
+    vop(3, nullptr);
+    UFG_TRY(k_finalize_seg(cs, FIN_INIT_B, vpart, vf, vc, nullptr, K));
+    UFG_TRY(k_finalize_seg(cs, FIN_INIT_R, vpart, vf, vc, nullptr, K));
+    UFG_HIP(hipGetLastError());
+    // one check interval of iterations, captured once
+    auto body = [&]() -> int {
+      for (int k = 0; k < check; ++k) {
+        vop(0, K.active);
+        hop(1, vp, vv, vrh);
+        UFG_TRY(k_finalize_seg(cs, FIN_ALPHA, hpart, hf, hc, K.active, K));
+        vop(1, K.active);
+        hop(2, vs, vt, vs);
+        UFG_TRY(k_finalize_seg(cs, FIN_OMEGA, hpart, hf, hc, K.active, K));
+        vop(2, K.active);
+        UFG_TRY(k_finalize_seg(cs, FIN_RHO, vpart, vf, vc, K.active, K));
+      }
+      return UFG_OK;
+    };
+    Graph G;
+    UFG_HIP(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
+    const int brc = body();
+    hipGraph_t graph = nullptr;
+    const hipError_t ec = hipStreamEndCapture(cs, &graph);
+    G.g = graph;
+    UFG_TRY(brc);
+    UFG_HIP(ec);
+    UFG_HIP(hipGraphInstantiate(&G.e, G.g, nullptr, nullptr, 0));
+    const int launches = (o.maxit + check - 1) / check;
+    bool done = false;
+    UFG_HIP(hipMemcpyAsync(hflags.data(), K.active, sizeof(int) * 3 * S, hipMemcpyDeviceToHost, cs));
+    UFG_HIP(hipStreamSynchronize(cs));
+    done = std::all_of(hflags.begin(), hflags.begin() + S, [](int v) { return v == 0; });
+    for (int n = 0; n < launches && !done; ++n) {
+      UFG_HIP(hipGraphLaunch(G.e, cs));
+      UFG_HIP(hipMemcpyAsync(hflags.data(), K.active, sizeof(int) * 3 * S, hipMemcpyDeviceToHost,
+                             cs));
+      UFG_HIP(hipStreamSynchronize(cs));
+      bool any_update = false, any_restart = false;
+      for (int s = 0; s < S; ++s) {
+        any_update |= hflags[S + s] != 0;
+        any_restart |= hflags[2 * S + s] != 0;
+      }
+      if (any_update) {  // reliable update: x64 += x_in, r64 = b - A x64, r = r64
+        vop(4, K.update);
+        residual(K.update);
+        vop(5, K.update);
+        UFG_TRY(k_finalize_seg(cs, FIN_UPDATE, vpart, vf, vc, K.update, K));
+      }
+      if (any_restart) {
+        vop(6, K.restart);
+        UFG_TRY(k_finalize_seg(cs, FIN_RESTART, vpart, vf, vc, K.restart, K));
+      }
+      UFG_HIP(hipGetLastError());
+      UFG_HIP(hipMemcpyAsync(hflags.data(), K.active, sizeof(int) * 3 * S, hipMemcpyDeviceToHost,
+                             cs));
+      UFG_HIP(hipStreamSynchronize(cs));
+      done = std::all_of(hflags.begin(), hflags.begin() + S, [](int v) { return v == 0; });
+    }
+    vop(4, nullptr);  // final x64 += x_in
+    UFG_HIP(hipMemcpyAsync(hst.data(), K.st, sizeof(RhsState) * S, hipMemcpyDeviceToHost, cs));
+    UFG_HIP(hipStreamSynchronize(cs));
+    iters_step[step].assign(nprob, 0);
+    for (int s = 0; s < S; ++s) {
+      const int i = seg_prob[s];
+      iters_step[step][i] = std::max(iters_step[step][i], hst[s].iters);
+      if (hst[s].status) status[i] = std::max(status[i], hst[s].status);
+      else if (!hst[s].conv) status[i] = std::max(status[i], (int)UFG_NOT_CONVERGED);
+    }
+    // true residuals of this step, FP64
+    residual(nullptr);
+    vop(7, nullptr);
+    UFG_TRY(k_finalize_seg(cs, FIN_INIT_B, vpart, vf, vc, nullptr, K));
+    vop(8, nullptr);
+    UFG_TRY(k_finalize_seg(cs, FIN_NORM, vpart, vf, vc, nullptr, K));
+    UFG_HIP(hipMemcpyAsync(hst.data(), K.st, sizeof(RhsState) * S, hipMemcpyDeviceToHost, cs));
+    UFG_HIP(hipStreamSynchronize(cs));
+    relres_step[step].assign(nprob, 0.0);
+    for (int s = 0; s < S; ++s) {
+      const int i = seg_prob[s];
+      const double rr = hst[s].b2 > 0 ? std::sqrt(hst[s].r2 / hst[s].b2) : std::sqrt(hst[s].r2);
+      if (!(rr <= relres_step[step][i])) relres_step[step][i] = rr;
+    }
+  }
+  int worst = 0;
+  for (int i = 0; i < nprob; ++i) {
+    worst = std::max(worst, status[i]);
+    if (stats) {
+      ufg_solve_stats& q = stats[i];
+      std::memset(&q, 0, sizeof(q));
+      q.iters[0] = iters_step[0][i];
+      q.iters[1] = iters_step[1][i];
+      q.mv = 2LL * (q.iters[0] + q.iters[1]);
+      q.relres[0] = relres_step[0][i];
+      q.relres[1] = relres_step[1][i];
+      q.relres_normal = -1.0;
+      q.paper_mv = 2.0 * (q.iters[0] + q.iters[1]);
+      q.status = status[i];
+    }
+  }
+  return worst;
+}
+
+}  // namespace
+
+int solve_batched_impl(const ufg_lattice* Ls, int nprob, const void* const* b, void* const* x,
+                       const int* nrhs, const ufg_precond* p, const ufg_solve_opts* o,
+                       ufg_solve_stats* st) {
+  UFG_CHECK(Ls && b && x && nrhs && nprob >= 1, "solve_batched: bad arguments");
+  UFG_CHECK(o != nullptr, "solve_batched: options are required");
+  UFG_CHECK(o->tol > 0 && o->tol < 1 && o->maxit >= 1, "solve_batched: bad tol or maxit");
+  UFG_CHECK(o->delta > 0 && o->delta < 1, "solve_batched: delta must be in (0, 1)");
+  UFG_CHECK(!o->use_x0, "solve_batched: starts from x = 0");
+  UFG_CHECK(!p || p->kind == UFG_PC_NONE, "solve_batched: no preconditioner in batched solves");
+  std::vector<Lattice*> L(nprob);
+  for (int i = 0; i < nprob; ++i) {
+    L[i] = reinterpret_cast<Lattice*>(Ls[i]);
+    UFG_CHECK(L[i] != nullptr, "solve_batched: NULL lattice");
+    UFG_CHECK(L[i]->dtype == UFG_C128, "solve_batched: lattices must be complex128");
+    UFG_CHECK(nrhs[i] >= 1, "solve_batched: nrhs must be >= 1");
+    UFG_CHECK(b[i] && x[i] && b[i] != x[i], "solve_batched: bad vectors");
+    UFG_CHECK(L[i]->device == L[0]->device, "solve_batched: lattices on different devices");
+    UFG_HIP(hipStreamSynchronize(L[i]->stream));
+  }
+  const auto t0 = std::chrono::steady_clock::now();
+  const int rc = o->mixed ? run_batched<float>(L, b, x, nrhs, *o, st)
+                          : run_batched<double>(L, b, x, nrhs, *o, st);
+  if (rc >= 0 && st) {
+    const double sec = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    for (int i = 0; i < nprob; ++i) st[i].seconds = sec;
+  }
+  return rc;
+}
+
+int batched_tune(int hop_blocks_per_cu, int vec_blocks_per_cu, long long chunk) {
+  UFG_CHECK(hop_blocks_per_cu >= 0 && hop_blocks_per_cu <= 64, "bad hop blocks per CU");
+  UFG_CHECK(vec_blocks_per_cu >= 0 && vec_blocks_per_cu <= 64, "bad vector blocks per CU");
+  UFG_CHECK(chunk == 0 || (chunk >= 256 && chunk <= (1 << 22)), "bad chunk");
+  g_hop_blocks_per_cu = hop_blocks_per_cu ? hop_blocks_per_cu : 4;
+  g_vec_blocks_per_cu = vec_blocks_per_cu ? vec_blocks_per_cu : 8;
+  g_chunk = chunk ? chunk : 4096;
+  return UFG_OK;
+}
+
+}  // namespace ufg

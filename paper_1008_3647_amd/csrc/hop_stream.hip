@@ -259,7 +259,7 @@ __global__ void __launch_bounds__(NX * NX)
   const long long rbase = (long long)r * ntau * V;
   const SrcScal<R> q = src_scalars<R, SRC>(a, r);
 
-  double acc0 = 0, acc1 = 0, acc2 = 0;
+  double acc0 = 0, acc1 = 0, acc2 = 0, acc3 = 0;
   const int count = t1 - t0;
   // Both directions walk t upwards (ascending addresses stream best).
   //   M  : W holds T^3(b_{t-1} x_{t-1}); X = x_t is loaded, used as the
@@ -352,10 +352,12 @@ __global__ void __launch_bounds__(NX * NX)
         acc0 += double(out.x) * u.x + double(out.y) * u.y;
         acc1 += double(out.x) * u.y - double(out.y) * u.x;
         acc2 += double(out.x) * out.x + double(out.y) * out.y;
-      } else if (a.red_mode == 3) {  // <out, source>, |out|^2
+        acc3 += double(u.x) * u.x + double(u.y) * u.y;
+      } else if (a.red_mode == 3) {  // <out, source>, |out|^2, |source|^2
         acc0 += double(out.x) * id.x + double(out.y) * id.y;
         acc1 += double(out.x) * id.y - double(out.y) * id.x;
         acc2 += double(out.x) * out.x + double(out.y) * out.y;
+        acc3 += double(id.x) * id.x + double(id.y) * id.y;
       }
     }
     if (DIR > 0) {
@@ -382,6 +384,7 @@ __global__ void __launch_bounds__(NX * NX)
     acc0 = wsum(acc0);
     acc1 = wsum(acc1);
     acc2 = wsum(acc2);
+    acc3 = wsum(acc3);
     __syncthreads();
     double* sm = reinterpret_cast<double*>(smem_raw);
     const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
@@ -389,20 +392,22 @@ __global__ void __launch_bounds__(NX * NX)
       sm[wid * 4 + 0] = acc0;
       sm[wid * 4 + 1] = acc1;
       sm[wid * 4 + 2] = acc2;
+      sm[wid * 4 + 3] = acc3;
     }
     __syncthreads();
     if (threadIdx.x == 0) {
-      double s0 = 0, s1 = 0, s2 = 0;
+      double s0 = 0, s1 = 0, s2 = 0, s3 = 0;
       for (int w = 0; w < (P + 63) / 64; ++w) {
         s0 += sm[w * 4 + 0];
         s1 += sm[w * 4 + 1];
         s2 += sm[w * 4 + 2];
+        s3 += sm[w * 4 + 3];
       }
       double* out = a.red_out + ((long long)r * nslab + sb) * 4;
       out[0] = s0;
       out[1] = s1;
       out[2] = s2;
-      out[3] = 0.0;
+      out[3] = s3;
     }
   }
 }

@@ -13,6 +13,7 @@ struct RhsState {
   double b2;     // |b|^2
   double maxr2;  // largest |r|^2 since the last reliable update
   double tol2;   // tol^2 |b|^2
+  double rhat2;  // |rhat|^2 (shadow residual, fixed between restarts)
   int iters, updates, conv, status;
 };
 
@@ -22,6 +23,7 @@ struct KrylovParams {
   int mixed;
   int bicg;       // 1: BiCGStab (rho = <rhat, r> refreshed at updates)
   int unprec;     // CG without preconditioner: <r, z> = |r|^2
+  int limit_omega;  // BiCGStab: keep |cos(t, s)| >= 0.7 (complex spectra)
 };
 
 struct KrylovState {
@@ -81,5 +83,8 @@ template <typename R>
 int k_restart(const Lattice& L, const C2<R>* r, C2<R>* rhat, C2<R>* p, C2<R>* v,
               const KrylovState& K);
 int k_finalize(const Lattice& L, int op, int nblk, const int* gate, const KrylovState& K);
+// Partials of rhs (segment) k are part[first[k] .. first[k] + count[k]) (4 doubles each).
+int k_finalize_seg(hipStream_t stream, int op, const double* part, const int* first,
+                   const int* count, const int* gate, const KrylovState& K);
 
 }  // namespace ufg

@@ -304,26 +304,9 @@ __global__ void __launch_bounds__(256) restart_kernel(const C2<R>* r, C2<R>* rha
   }
 }
 
-// One block per rhs: sum `nblk` partials (fixed order) and apply `op` to the state.
-__global__ void __launch_bounds__(256) finalize_kernel(int op, const double* part, int nblk,
-                                                       RhsState* st, int* active, int* update,
-                                                       int* restart, const int* gate,
-                                                       KrylovParams prm) {
-  const int k = blockIdx.x;
-  if (gate && !gate[k]) return;
-  double s0 = 0, s1 = 0, s2 = 0;
-  for (int b = threadIdx.x; b < nblk; b += 256) {
-    const double* q = part + ((long long)k * nblk + b) * 4;
-    s0 += q[0];
-    s1 += q[1];
-    s2 += q[2];
-  }
-  __shared__ double out[4];
-  bsum4(s0, s1, s2, 0.0, out);
-  if (threadIdx.x != 0) return;
-  s0 = out[0];
-  s1 = out[1];
-  s2 = out[2];
+// Scalar update of one rhs from its summed partials (s0, s1, s2).
+__device__ void apply_fin(int op, int k, double s0, double s1, double s2, double s3, RhsState* st,
+                          int* active, int* update, int* restart, const KrylovParams& prm) {
   RhsState q = st[k];
   const double2 d01 = double2{s0, s1};
   switch (op) {
@@ -333,6 +316,7 @@ __global__ void __launch_bounds__(256) finalize_kernel(int op, const double* par
       break;
     case FIN_INIT_R:  // rhat = r: rho = <r, r>, r2
       q.rho = double2{s2, 0.0};
+      q.rhat2 = s2;
       q.rho_old = q.alpha = q.omega = double2{1.0, 0.0};
       q.r2 = q.maxr2 = s2;
       q.iters = 0;
@@ -351,9 +335,23 @@ __global__ void __launch_bounds__(256) finalize_kernel(int op, const double* par
         q.alpha = cdiv(q.rho, d01);
       }
       break;
-    case FIN_OMEGA:  // omega = <t, s> / <t, t>
-      q.omega = (s2 > 0.0) ? double2{s0 / s2, s1 / s2} : double2{0.0, 0.0};
+    case FIN_OMEGA: {  // omega = <t, s> / <t, t>, s3 = |s|^2
+      // Sleijpen and van der Vorst's limited omega: when t and s are nearly
+      // orthogonal the minimal-residual omega stalls the bi-orthogonal part;
+      // enlarge it so that |cos(t, s)| counts as at least 0.7.
+      if (s2 > 0.0) {
+        double2 w = double2{s0 / s2, s1 / s2};
+        const double c = std::sqrt((s0 * s0 + s1 * s1) / (s2 * s3));
+        if (prm.limit_omega && s3 > 0.0 && c < 0.7 && c > 0.0) {
+          w.x *= 0.7 / c;
+          w.y *= 0.7 / c;
+        }
+        q.omega = w;
+      } else {
+        q.omega = double2{0.0, 0.0};
+      }
       break;
+    }
     case FIN_RHO: {  // after x, r update: rho_old = rho; rho = <rhat, r>
       q.rho_old = q.rho;
       q.rho = d01;
@@ -371,7 +369,8 @@ __global__ void __launch_bounds__(256) finalize_kernel(int op, const double* par
         update[k] = 1;
       }
       if (s2 > q.maxr2) q.maxr2 = s2;
-      if (!update[k] && d01.x == 0.0 && d01.y == 0.0) restart[k] = 1;
+      // near breakdown of the bi-orthogonality: restart with rhat = r
+      if (!update[k] && (d01.x * d01.x + d01.y * d01.y) < 1e-28 * q.rhat2 * s2) restart[k] = 1;
       break;
     }
     case FIN_UPDATE:  // reliable update done: r is b - A x
@@ -387,6 +386,7 @@ __global__ void __launch_bounds__(256) finalize_kernel(int op, const double* par
       break;
     case FIN_RESTART:  // rhat = r: rho = |r|^2, scalars reset
       q.rho = double2{q.r2, 0.0};
+      q.rhat2 = q.r2;
       q.rho_old = q.alpha = q.omega = double2{1.0, 0.0};
       restart[k] = 0;
       break;
@@ -428,6 +428,49 @@ __global__ void __launch_bounds__(256) finalize_kernel(int op, const double* par
       break;
   }
   st[k] = q;
+}
+// One block per rhs: sum `nblk` partials (fixed order) and apply `op` to the state.
+__global__ void __launch_bounds__(256) finalize_kernel(int op, const double* part, int nblk,
+                                                       RhsState* st, int* active, int* update,
+                                                       int* restart, const int* gate,
+                                                       KrylovParams prm) {
+  const int k = blockIdx.x;
+  if (gate && !gate[k]) return;
+  double s0 = 0, s1 = 0, s2 = 0, s3 = 0;
+  for (int b = threadIdx.x; b < nblk; b += 256) {
+    const double* q = part + ((long long)k * nblk + b) * 4;
+    s0 += q[0];
+    s1 += q[1];
+    s2 += q[2];
+    s3 += q[3];
+  }
+  __shared__ double out[4];
+  bsum4(s0, s1, s2, s3, out);
+  if (threadIdx.x != 0) return;
+  apply_fin(op, k, out[0], out[1], out[2], out[3], st, active, update, restart, prm);
+}
+
+// Segmented variant: rhs (segment) k owns partials [first[k], first[k] + count[k]).
+__global__ void __launch_bounds__(256) finalize_seg_kernel(int op, const double* part,
+                                                           const int* first, const int* count,
+                                                           RhsState* st, int* active,
+                                                           int* update, int* restart,
+                                                           const int* gate, KrylovParams prm) {
+  const int k = blockIdx.x;
+  if (gate && !gate[k]) return;
+  double s0 = 0, s1 = 0, s2 = 0, s3 = 0;
+  const int f = first[k], c = count[k];
+  for (int b = threadIdx.x; b < c; b += 256) {
+    const double* q = part + ((long long)f + b) * 4;
+    s0 += q[0];
+    s1 += q[1];
+    s2 += q[2];
+    s3 += q[3];
+  }
+  __shared__ double out[4];
+  bsum4(s0, s1, s2, s3, out);
+  if (threadIdx.x != 0) return;
+  apply_fin(op, k, out[0], out[1], out[2], out[3], st, active, update, restart, prm);
 }
 
 }  // namespace
@@ -525,6 +568,12 @@ int k_restart(const Lattice& L, const C2<R>* r, C2<R>* rhat, C2<R>* p, C2<R>* v,
               const KrylovState& K) {
   hipLaunchKernelGGL((restart_kernel<R>), vgrid(L.N, K.nrhs), dim3(256), 0, L.stream, r, rhat, p, v,
                      K.restart, L.N);
+  return UFG_OK;
+}
+int k_finalize_seg(hipStream_t stream, int op, const double* part, const int* first,
+                   const int* count, const int* gate, const KrylovState& K) {
+  hipLaunchKernelGGL(finalize_seg_kernel, dim3(K.nrhs), dim3(256), 0, stream, op, part, first,
+                     count, K.st, K.active, K.update, K.restart, gate, K.prm);
   return UFG_OK;
 }
 int k_finalize(const Lattice& L, int op, int nblk, const int* gate, const KrylovState& K) {

@@ -127,6 +127,10 @@ int bicgstab_step(Lattice& L, const PcPlan& pc, int op, const C2<RO>* b, C2<RO>*
   K.prm.mixed = kMixed ? 1 : 0;
   K.prm.bicg = 1;
   K.prm.unprec = need_pc ? 0 : 1;
+  // The operator itself, and M with the weak-coupling series, have complex
+  // spectra; the Q-type preconditioners composed with M^T or M make the
+  // preconditioned operator Hermitian-like, where the limit only slows it.
+  K.prm.limit_omega = (pc.kind == UFG_PC_NONE || pc.kind == UFG_PC_WCE) ? 1 : 0;
   const int nvb = vec_blocks(L, nrhs);
   const int nhb = hop_blocks_per_rhs(L);
   const double2 one{1.0, 0.0}, zero{0.0, 0.0};

@@ -188,3 +188,34 @@ def transfer_matrix(nx, tau):
     out = (C.c_double * (nx * nx))()
     L.check(lib.ufg_transfer_matrix(nx, tau, out), "ufg_transfer_matrix")
     return [[out[i * nx + j] for j in range(nx)] for i in range(nx)]
+
+
+def solve_batched(lattices, bs, tol=1e-10, maxit=10000, mixed=True, delta=0.1, check_every=10):
+    """Two-step BiCGStab for many lattices at once (C ABI solve_batched).
+
+    lattices: list of complex128 Lattice objects (fields installed); bs: list of
+    complex128 tensors [nrhs_i][Ntau_i][Nx_i]^3. Returns (xs, stats)."""
+    lib = L.load()
+    n = len(lattices)
+    if n != len(bs) or n == 0:
+        raise ValueError("need one right-hand-side tensor per lattice")
+    xs, nr = [], []
+    for lat, b in zip(lattices, bs):
+        if lat.dtype != torch.complex128:
+            raise TypeError("batched solves need complex128 lattices")
+        nr.append(lat._vec(b, "b", torch.complex128))
+        xs.append(torch.empty_like(b))
+    handles = (C.c_void_p * n)(*[lat._h.value for lat in lattices])
+    bp = (C.c_void_p * n)(*[b.data_ptr() for b in bs])
+    xp = (C.c_void_p * n)(*[x.data_ptr() for x in xs])
+    nrhs = (C.c_int * n)(*nr)
+    o = L.solve_opts(tol, maxit, mixed, delta, check_every, False)
+    st = (L.ufg_solve_stats * n)()
+    L.check(lib.solve_batched(handles, n, bp, xp, nrhs, None, C.byref(o), st), "solve_batched")
+    return xs, [s.as_dict() for s in st]
+
+
+def solve_batched_tune(hop_blocks_per_cu=0, vec_blocks_per_cu=0, chunk=0):
+    """Launch shape of batched solves (0 = default); see ufg.h."""
+    L.check(L.load().solve_batched_tune(int(hop_blocks_per_cu), int(vec_blocks_per_cu),
+                                        int(chunk)), "solve_batched_tune")

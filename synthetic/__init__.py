@@ -83,6 +83,9 @@ WORKLOADS = {
     # precision comparison at Nx=16, Ntau=400, 8 RHS
     "lattice_16x400": dict(nx=16, ntau=400, sigma_seed=3001,
                            rhs_seeds=list(range(3002, 3010))),
+    # 64 uneven lattices (shapes from batched_problem_shapes(64, 4000)), sigma
+    # seed 4001 + i and right-hand-side seeds 4101 + 2 i, 4102 + 2 i for problem i
+    "batched_64": dict(count=64, shape_seed=4000, sigma_seed0=4001, rhs_seed0=4101, nrhs=2),
     # force / molecular dynamics at Nx=12, Ntau=200
     "lattice_12x200": dict(nx=12, ntau=200, sigma_seed=5001, eta_seed=5002,
                            site_seed=5003, momentum_seed=5004),
