@@ -342,7 +342,10 @@ __global__ void __launch_bounds__(NX * NX)
           out.y += br * u.y + bi * u.x;
         }
       }
-      a.dst[idx] = out;
+      // streaming store: y is not re-read by this launch, keep L2 for the
+      // halo slices and the field
+      __builtin_nontemporal_store(out.x, &a.dst[idx].x);
+      __builtin_nontemporal_store(out.y, &a.dst[idx].y);
       if (a.red_mode == 1) {
         const C2<R> u = a.red_w[idx];
         acc0 += double(u.x) * out.x + double(u.y) * out.y;
@@ -457,7 +460,7 @@ int launch_nx(const Lattice& L, const HopArgs<R>& a) {
 
 int stream_slab(const Lattice& L) {
   if (L.slab > 0) return std::min(L.slab, L.ntau);
-  return std::min(4, L.ntau);
+  return std::min(2, L.ntau);  // best measured for 16^3 slices with HBM-resident data
 }
 
 bool stream_supported(const Lattice& L) {
