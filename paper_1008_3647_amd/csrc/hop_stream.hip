@@ -1,10 +1,11 @@
 // Streaming slice operator for M and M^T (paper, Sec. 1, Eq. MatrixM) on gfx950.
 //
 // One workgroup owns a slab of S consecutive time slices of one right-hand
-// side and walks it in the direction of the time shift, so every input slice
-// is loaded from HBM once: the slice x_t loaded for the identity term of y_t
-// is the slice whose transform feeds y_{t+1} (M) or y_{t-1} (M^T); only one
-// halo slice per slab is loaded twice, and it is usually an L2 hit.
+// side and walks it in the direction that reuses loads: upwards for M (output
+// t reads source t-1), downwards for M^T (output t reads source t+1). The
+// slice loaded for the identity term of output t is the source of the next
+// output, so every input slice of the slab is loaded from HBM once; only one
+// halo slice per slab is loaded twice, and it is often a cache hit.
 //
 // Workgroups are numbered so that each XCD receives a contiguous run of
 // (slab, rhs) pairs with the rhs index fastest: the eight right-hand sides of
@@ -17,6 +18,12 @@
 // block diagonal with blocks of sizes Nx/4+1, Nx/4, Nx/4, Nx/4-1. A line of Nx
 // values then costs 4 (Nx-2) additions for the butterflies and sum(block^2)
 // multiply-adds (56 + 66 for Nx = 16) instead of Nx^2 = 256 multiply-adds.
+//
+// Memory access: raw buffer instructions with one resource per array (base =
+// the rhs block), the lane offset in a VGPR and the slice / z offset in an
+// SGPR, so a z-line costs no 64-bit address arithmetic. The operands of an
+// output slice (field, aux, reduction weights) are loaded before its stores
+// start, because loads cannot be moved across buffer stores.
 //
 // Fused BiCGStab sources: the kernel can build its source on the fly from the
 // Krylov vectors (p = r + beta (p_old - omega v_old), or s = r - alpha v) so
@@ -140,39 +147,51 @@ __device__ __forceinline__ void split_line(const SplitCoef<R, NX>& c, C2<R> (&a)
   }
 }
 
+// LDS slot of element (row, col) of a slice stored as NX*NX rows of NX:
+// power-of-two NX uses an XOR swizzle (no padding), else one pad column.
+template <int NX>
+__device__ __forceinline__ int lds_at(int row, int col) {
+  if constexpr ((NX & (NX - 1)) == 0)
+    return row * NX + (col ^ (row & (NX - 1)));
+  else
+    return row * (NX + 1) + col;
+}
+template <int NX>
+constexpr int lds_slice_elems() {
+  return ((NX & (NX - 1)) == 0) ? NX * NX * NX : NX * NX * (NX + 1);
+}
+
 // T^3 of the slice held as z-lines in v (thread (y, x)); result left in v.
 template <typename R, int NX>
 __device__ __forceinline__ void slice_T3(const SplitCoef<R, NX>& c, C2<R>* lds, int l,
                                          C2<R> (&v)[NX]) {
-  constexpr int LD = NX + 1;
   const int y = l / NX, x = l - (l / NX) * NX;
   split_line<R, NX>(c, v);  // along z
   __syncthreads();          // the previous slice's readers are done with lds
 #pragma unroll
-  for (int z = 0; z < NX; ++z) lds[(z * NX + y) * LD + x] = v[z];
+  for (int z = 0; z < NX; ++z) lds[lds_at<NX>(z * NX + y, x)] = v[z];
   __syncthreads();
   C2<R> w[NX];
   {
     const int z = l / NX, xx = l - (l / NX) * NX;
 #pragma unroll
-    for (int yy = 0; yy < NX; ++yy) w[yy] = lds[(z * NX + yy) * LD + xx];
+    for (int yy = 0; yy < NX; ++yy) w[yy] = lds[lds_at<NX>(z * NX + yy, xx)];
     split_line<R, NX>(c, w);  // along y
 #pragma unroll
-    for (int yy = 0; yy < NX; ++yy) lds[(z * NX + yy) * LD + xx] = w[yy];
+    for (int yy = 0; yy < NX; ++yy) lds[lds_at<NX>(z * NX + yy, xx)] = w[yy];
   }
   __syncthreads();
   {
     const int z = l / NX, yy = l - (l / NX) * NX;
-    C2<R>* row = lds + (z * NX + yy) * LD;
 #pragma unroll
-    for (int xx = 0; xx < NX; ++xx) w[xx] = row[xx];
+    for (int xx = 0; xx < NX; ++xx) w[xx] = lds[lds_at<NX>(z * NX + yy, xx)];
     split_line<R, NX>(c, w);  // along x
 #pragma unroll
-    for (int xx = 0; xx < NX; ++xx) row[xx] = w[xx];
+    for (int xx = 0; xx < NX; ++xx) lds[lds_at<NX>(z * NX + yy, xx)] = w[xx];
   }
   __syncthreads();
 #pragma unroll
-  for (int z = 0; z < NX; ++z) v[z] = lds[(z * NX + y) * LD + x];
+  for (int z = 0; z < NX; ++z) v[z] = lds[lds_at<NX>(z * NX + y, x)];
 }
 
 // Per-rhs scalars of the fused BiCGStab sources.
@@ -205,27 +224,99 @@ __device__ __forceinline__ SrcScal<R> src_scalars(const HopArgs<R>& a, int r) {
   return q;
 }
 
-// z-line of the source vector at element offset o (already includes rhs, slice, lane).
+// Raw buffer access: one 128-bit resource per array (base = the rhs block),
+// a 32-bit lane offset in a VGPR and the slice / z offset in an SGPR.
+// Out-of-range accesses are dropped by the hardware (loads return 0).
+typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+constexpr int kRsrcWord3 = 0x00020000;  // gfx9 raw buffer, 32-bit data format
+constexpr int kAuxNT = 2;               // non-temporal
+
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t make_rsrc(const void* p, unsigned bytes) {
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(p), 0, (int)bytes, kRsrcWord3);
+}
+
+template <typename R>
+__device__ __forceinline__ C2<R> bload(__amdgpu_buffer_rsrc_t rs, int vo, int so) {
+  if constexpr (sizeof(R) == 4) {
+    const u32x2 v = __builtin_amdgcn_raw_buffer_load_b64(rs, vo, so, 0);
+    return __builtin_bit_cast(C2<R>, v);
+  } else {
+    const u32x4 v = __builtin_amdgcn_raw_buffer_load_b128(rs, vo, so, 0);
+    return __builtin_bit_cast(C2<R>, v);
+  }
+}
+
+// Store of one element at byte offset so + vo from base (rsrc describes the
+// same block). 16-byte elements go through a FLAT store: the compiler's
+// wait-state handling for a VALU overwrite of store-data registers does not
+// cover buffer stores with an SGPR offset, and 128-bit buffer stores were
+// seen to write registers already overwritten by the next instruction.
+template <typename R, bool NT>
+__device__ __forceinline__ void bstore(C2<R> v, C2<R>* base, __amdgpu_buffer_rsrc_t rs, int vo,
+                                       int so) {
+  if constexpr (sizeof(R) == 4) {
+    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, v), rs, vo, so,
+                                          NT ? kAuxNT : 0);
+  } else {
+    C2<R>* p = reinterpret_cast<C2<R>*>(reinterpret_cast<char*>(base) + so + vo);
+    if (NT) {
+      __builtin_nontemporal_store(v.x, &p->x);
+      __builtin_nontemporal_store(v.y, &p->y);
+    } else {
+      *p = v;
+    }
+  }
+}
+
+template <typename R>
+__device__ __forceinline__ R bload_real(__amdgpu_buffer_rsrc_t rs, int vo, int so) {
+  if constexpr (sizeof(R) == 4) {
+    return __builtin_bit_cast(R, __builtin_amdgcn_raw_buffer_load_b32(rs, vo, so, 0));
+  } else {
+    return __builtin_bit_cast(R, __builtin_amdgcn_raw_buffer_load_b64(rs, vo, so, 0));
+  }
+}
+
+struct Rsrc {
+  __amdgpu_buffer_rsrc_t src, fr, fp, fv, fpnew, dst, aux, rw, pre, post;
+};
+
+// z-line of the source slice at byte offset so (uniform); vo = lane byte offset.
 template <typename R, int NX, int SRC>
-__device__ __forceinline__ void load_source(const HopArgs<R>& a, const SrcScal<R>& q, long long o,
+__device__ __forceinline__ void load_source(const Rsrc& b, const SrcScal<R>& q, int so, int vo,
                                             C2<R> (&X)[NX]) {
-  constexpr int P = NX * NX;
+  constexpr int ZB = NX * NX * (int)sizeof(C2<R>);
 #pragma unroll
   for (int z = 0; z < NX; ++z) {
-    const long long i = o + z * P;
+    const int s = so + z * ZB;
     if (SRC == 0) {
-      X[z] = a.src[i];
+      X[z] = bload<R>(b.src, vo, s);
     } else if (SRC == 1) {
-      const C2<R> rv = a.fr[i], pv = a.fp[i], vv = a.fv[i];
+      const C2<R> rv = bload<R>(b.fr, vo, s), pv = bload<R>(b.fp, vo, s),
+                  vv = bload<R>(b.fv, vo, s);
       const R dx = pv.x - (q.wr * vv.x - q.wi * vv.y);
       const R dy = pv.y - (q.wr * vv.y + q.wi * vv.x);
       X[z].x = rv.x + q.br * dx - q.bi * dy;
       X[z].y = rv.y + q.br * dy + q.bi * dx;
     } else {
-      const C2<R> rv = a.fr[i], vv = a.fv[i];
+      const C2<R> rv = bload<R>(b.fr, vo, s), vv = bload<R>(b.fv, vo, s);
       X[z].x = rv.x - (q.ar * vv.x - q.ai * vv.y);
       X[z].y = rv.y - (q.ar * vv.y + q.ai * vv.x);
     }
+  }
+}
+
+// z-line of a real field slice times X (in place).
+template <typename R, int NX>
+__device__ __forceinline__ void scale_field(__amdgpu_buffer_rsrc_t f, int so, int vo,
+                                            C2<R> (&X)[NX]) {
+  constexpr int ZB = NX * NX * (int)sizeof(R);
+#pragma unroll
+  for (int z = 0; z < NX; ++z) {
+    const R fz = bload_real<R>(f, vo, so + z * ZB);
+    X[z].x *= fz;
+    X[z].y *= fz;
   }
 }
 
@@ -235,12 +326,16 @@ __device__ __forceinline__ double wsum(double v) {
   return v;
 }
 
-// DIR = -1: M-type (output t reads source t-1, walk t upwards)
-// DIR = +1: M^T-type (output t reads source t+1, walk t upwards with lookahead)
-template <typename R, int NX, int DIR, bool GENERAL, int SRC>
+// DIR = -1: M-type, output t reads source t-1; the slab is walked upwards.
+// DIR = +1: M^T-type, output t reads source t+1; the slab is walked downwards.
+// Either way the slice loaded for the identity term of output t is the source
+// of the next output, so each thread holds two z-lines: X (current source)
+// and W (transform of the previous one).
+template <typename R, int NX, int DIR, bool GENERAL, int SRC, int RED>
 __global__ void __launch_bounds__(NX * NX)
     hop_stream_kernel(HopArgs<R> a, SplitCoef<R, NX> c, int ntau, int slab, int nslab) {
   constexpr int P = NX * NX, V = NX * NX * NX;
+  constexpr int ES = sizeof(C2<R>), FS = sizeof(R);
   extern __shared__ __align__(16) unsigned char smem_raw[];
   C2<R>* lds = reinterpret_cast<C2<R>*>(smem_raw);
 
@@ -257,58 +352,39 @@ __global__ void __launch_bounds__(NX * NX)
   const int t0 = sb * slab;
   const int t1 = min(t0 + slab, ntau);  // exclusive
   const long long rbase = (long long)r * ntau * V;
+  const unsigned vbytes = (unsigned)ntau * V * ES;
+  const unsigned fbytes = (unsigned)ntau * V * FS;
+  Rsrc b;
+  b.src = make_rsrc(a.src + rbase, vbytes);
+  b.fr = make_rsrc(a.fr + rbase, vbytes);
+  b.fp = make_rsrc(a.fp + rbase, vbytes);
+  b.fv = make_rsrc(a.fv + rbase, vbytes);
+  b.fpnew = make_rsrc(a.fpnew + rbase, vbytes);
+  b.dst = make_rsrc(a.dst + rbase, vbytes);
+  b.aux = make_rsrc(a.aux + rbase, vbytes);
+  b.rw = make_rsrc(a.red_w + rbase, vbytes);
+  b.pre = make_rsrc(a.pre, fbytes);
+  b.post = make_rsrc(a.post, fbytes);
+  const int vo = l * ES, fo = l * FS;
   const SrcScal<R> q = src_scalars<R, SRC>(a, r);
+  const int count = t1 - t0;
+  // first output slice, step, and the halo slice that feeds it
+  const int tfirst = (DIR < 0) ? t0 : t1 - 1;
+  const int step = (DIR < 0) ? 1 : -1;
+  const int th = (DIR < 0) ? ((t0 == 0) ? ntau - 1 : t0 - 1) : ((t1 == ntau) ? 0 : t1);
 
   double acc0 = 0, acc1 = 0, acc2 = 0, acc3 = 0;
-  const int count = t1 - t0;
-  // Both directions walk t upwards (ascending addresses stream best).
-  //   M  : W holds T^3(b_{t-1} x_{t-1}); X = x_t is loaded, used as the
-  //        identity term, then becomes the next W.
-  //   M^T: X = x_t was loaded one step earlier; Xn = x_{t+1} is loaded and its
-  //        transform W = T^3 x_{t+1} combines with X into y_t; Xn becomes X.
   C2<R> W[NX], X[NX];
-  if (DIR < 0) {
-    const int th = (t0 == 0) ? ntau - 1 : t0 - 1;
-    load_source<R, NX, SRC>(a, q, rbase + (long long)th * V + l, W);
-    if (a.pre) {
-      const R* f = a.pre + (long long)th * V + l;
-#pragma unroll
-      for (int z = 0; z < NX; ++z) {
-        const R fz = f[z * P];
-        W[z].x *= fz;
-        W[z].y *= fz;
-      }
-    }
-    slice_T3<R, NX>(c, lds, l, W);
-  } else {
-    const long long o = rbase + (long long)t0 * V + l;
-    load_source<R, NX, SRC>(a, q, o, X);
+  load_source<R, NX, SRC>(b, q, th * V * ES, vo, W);
+  if (DIR < 0) scale_field<R, NX>(b.pre, th * V * FS, fo, W);
+  slice_T3<R, NX>(c, lds, l, W);
+  for (int k = 0; k < count; ++k) {
+    const int t = tfirst + k * step;
+    const int so = t * V * ES;  // slice byte offset (uniform)
+    load_source<R, NX, SRC>(b, q, so, vo, X);
     if (SRC == 1) {
 #pragma unroll
-      for (int z = 0; z < NX; ++z) a.fpnew[o + z * P] = X[z];
-    }
-  }
-  for (int k = 0; k < count; ++k) {
-    const int t = t0 + k;
-    const long long o = rbase + (long long)t * V + l;
-    C2<R> Xn[NX];
-    if (DIR < 0) {
-      load_source<R, NX, SRC>(a, q, o, X);
-      if (SRC == 1) {
-#pragma unroll
-        for (int z = 0; z < NX; ++z) a.fpnew[o + z * P] = X[z];
-      }
-    } else {
-      const int tn = (t + 1 == ntau) ? 0 : t + 1;
-      const long long on = rbase + (long long)tn * V + l;
-      load_source<R, NX, SRC>(a, q, on, Xn);
-      if (SRC == 1 && k + 1 < count) {  // x_{t+1} belongs to this slab
-#pragma unroll
-        for (int z = 0; z < NX; ++z) a.fpnew[on + z * P] = Xn[z];
-      }
-#pragma unroll
-      for (int z = 0; z < NX; ++z) W[z] = Xn[z];
-      slice_T3<R, NX>(c, lds, l, W);
+      for (int z = 0; z < NX; ++z) bstore<R, false>(X[z], a.fpnew + rbase, b.fpnew, vo, so + z * P * ES);
     }
     // sign of the block that connects the source slice to slice t
     R sgn;
@@ -316,74 +392,84 @@ __global__ void __launch_bounds__(NX * NX)
       sgn = (t == 0) ? R(1) : R(-1);
     else
       sgn = (t == ntau - 1) ? R(1) : R(-1);
-    const R* post = a.post ? a.post + (long long)t * V + l : nullptr;
+    // The output slice is written in chunks of ZC z-planes; the operands of a
+    // chunk (field, aux, reduction weights) are loaded ahead of its stores
+    // (loads cannot be moved across buffer stores). complex128 with a
+    // reduction uses half-slice chunks to stay within the register file.
+    constexpr int ZC = (sizeof(R) == 8 && (GENERAL || RED != 0)) ? NX / 2 : NX;
 #pragma unroll
-    for (int z = 0; z < NX; ++z) {
-      const long long idx = o + z * P;
-      const C2<R> id = X[z];
-      R f = sgn;
-      if (post) f *= post[z * P];
-      C2<R> base;
-      base.x = f * W[z].x;
-      base.y = f * W[z].y;
-      if (a.id) {
-        base.x += id.x;
-        base.y += id.y;
+    for (int z0 = 0; z0 < NX; z0 += ZC) {
+      R F[DIR > 0 ? ZC : 1];
+      if (DIR > 0) {  // M^T-type: the field multiplies the output slice
+#pragma unroll
+        for (int j = 0; j < ZC; ++j)
+          F[j] = sgn * bload_real<R>(b.post, fo, t * V * FS + (z0 + j) * P * FS);
       }
-      C2<R> out = base;
-      if (GENERAL) {
-        const R ar = R(a.alpha.x), ai = R(a.alpha.y);
-        out.x = ar * base.x - ai * base.y;
-        out.y = ar * base.y + ai * base.x;
-        if (a.aux) {
-          const C2<R> u = a.aux[idx];
-          const R br = R(a.beta.x), bi = R(a.beta.y);
-          out.x += br * u.x - bi * u.y;
-          out.y += br * u.y + bi * u.x;
+      C2<R> U[GENERAL ? ZC : 1];
+      if (GENERAL && a.aux) {
+#pragma unroll
+        for (int j = 0; j < ZC; ++j) U[j] = bload<R>(b.aux, vo, so + (z0 + j) * P * ES);
+      }
+      C2<R> Wr[(RED == 1 || RED == 2) ? ZC : 1];
+      if (RED == 1 || RED == 2) {
+#pragma unroll
+        for (int j = 0; j < ZC; ++j) Wr[j] = bload<R>(b.rw, vo, so + (z0 + j) * P * ES);
+      }
+#pragma unroll
+      for (int j = 0; j < ZC; ++j) {
+        const int z = z0 + j;
+        const int s = so + z * P * ES;
+        const C2<R> id = X[z];
+        C2<R> base;
+        const R f = (DIR > 0) ? F[DIR > 0 ? j : 0] : sgn;
+        base.x = f * W[z].x;
+        base.y = f * W[z].y;
+        if (a.id) {
+          base.x += id.x;
+          base.y += id.y;
+        }
+        C2<R> out = base;
+        if (GENERAL) {
+          const R ar = R(a.alpha.x), ai = R(a.alpha.y);
+          out.x = ar * base.x - ai * base.y;
+          out.y = ar * base.y + ai * base.x;
+          if (a.aux) {
+            const C2<R> u = U[GENERAL ? j : 0];
+            const R br = R(a.beta.x), bi = R(a.beta.y);
+            out.x += br * u.x - bi * u.y;
+            out.y += br * u.y + bi * u.x;
+          }
+        }
+        // streaming store: y is not re-read by this launch, keep L2 for the
+        // halo slices and the field
+        bstore<R, true>(out, a.dst + rbase, b.dst, vo, s);
+        if (RED == 1) {  // <w, out>
+          const C2<R> u = Wr[RED == 1 ? j : 0];
+          acc0 += double(u.x) * out.x + double(u.y) * out.y;
+          acc1 += double(u.x) * out.y - double(u.y) * out.x;
+        } else if (RED == 2) {  // <out, w>, |out|^2, |w|^2
+          const C2<R> u = Wr[RED == 2 ? j : 0];
+          acc0 += double(out.x) * u.x + double(out.y) * u.y;
+          acc1 += double(out.x) * u.y - double(out.y) * u.x;
+          acc2 += double(out.x) * out.x + double(out.y) * out.y;
+          acc3 += double(u.x) * u.x + double(u.y) * u.y;
+        } else if (RED == 3) {  // <out, source>, |out|^2, |source|^2
+          acc0 += double(out.x) * id.x + double(out.y) * id.y;
+          acc1 += double(out.x) * id.y - double(out.y) * id.x;
+          acc2 += double(out.x) * out.x + double(out.y) * out.y;
+          acc3 += double(id.x) * id.x + double(id.y) * id.y;
         }
       }
-      // streaming store: y is not re-read by this launch, keep L2 for the
-      // halo slices and the field
-      __builtin_nontemporal_store(out.x, &a.dst[idx].x);
-      __builtin_nontemporal_store(out.y, &a.dst[idx].y);
-      if (a.red_mode == 1) {
-        const C2<R> u = a.red_w[idx];
-        acc0 += double(u.x) * out.x + double(u.y) * out.y;
-        acc1 += double(u.x) * out.y - double(u.y) * out.x;
-      } else if (a.red_mode == 2) {
-        const C2<R> u = a.red_w[idx];
-        acc0 += double(out.x) * u.x + double(out.y) * u.y;
-        acc1 += double(out.x) * u.y - double(out.y) * u.x;
-        acc2 += double(out.x) * out.x + double(out.y) * out.y;
-        acc3 += double(u.x) * u.x + double(u.y) * u.y;
-      } else if (a.red_mode == 3) {  // <out, source>, |out|^2, |source|^2
-        acc0 += double(out.x) * id.x + double(out.y) * id.y;
-        acc1 += double(out.x) * id.y - double(out.y) * id.x;
-        acc2 += double(out.x) * out.x + double(out.y) * out.y;
-        acc3 += double(id.x) * id.x + double(id.y) * id.y;
-      }
     }
-    if (DIR > 0) {
-#pragma unroll
-      for (int z = 0; z < NX; ++z) X[z] = Xn[z];
-    }
-    if (DIR < 0 && k + 1 < count) {
-      // transform slice t for the next output slice
-      if (a.pre) {
-        const R* f = a.pre + (long long)t * V + l;
-#pragma unroll
-        for (int z = 0; z < NX; ++z) {
-          const R fz = f[z * P];
-          X[z].x *= fz;
-          X[z].y *= fz;
-        }
-      }
+    if (k + 1 < count) {
+      // transform source slice t for the next output slice
+      if (DIR < 0) scale_field<R, NX>(b.pre, t * V * FS, fo, X);
 #pragma unroll
       for (int z = 0; z < NX; ++z) W[z] = X[z];
       slice_T3<R, NX>(c, lds, l, W);
     }
   }
-  if (a.red_mode) {
+  if (RED != 0) {
     acc0 = wsum(acc0);
     acc1 = wsum(acc1);
     acc2 = wsum(acc2);
@@ -415,17 +501,17 @@ __global__ void __launch_bounds__(NX * NX)
   }
 }
 
-template <typename R, int NX, int DIR, bool GENERAL, int SRC>
+template <typename R, int NX, int DIR, bool GENERAL, int SRC, int RED>
 int launch_one(const Lattice& L, const HopArgs<R>& a, const SplitCoef<R, NX>& c, dim3 grid,
                size_t lds, int slab, int nslab) {
   static bool attr = false;
   if (!attr) {
-    UFG_HIP(hipFuncSetAttribute((const void*)hop_stream_kernel<R, NX, DIR, GENERAL, SRC>,
+    UFG_HIP(hipFuncSetAttribute((const void*)hop_stream_kernel<R, NX, DIR, GENERAL, SRC, RED>,
                                 hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
     attr = true;
   }
-  hipLaunchKernelGGL((hop_stream_kernel<R, NX, DIR, GENERAL, SRC>), grid, dim3(NX * NX), lds,
-                     L.stream, a, c, L.ntau, slab, nslab);
+  hipLaunchKernelGGL((hop_stream_kernel<R, NX, DIR, GENERAL, SRC, RED>), grid, dim3(NX * NX),
+                     lds, L.stream, a, c, L.ntau, slab, nslab);
   UFG_HIP(hipGetLastError());
   return UFG_OK;
 }
@@ -434,13 +520,28 @@ template <typename R, int NX, int DIR>
 int launch_dir(const Lattice& L, const HopArgs<R>& a, const SplitCoef<R, NX>& c) {
   const int slab = stream_slab(L);
   const int nslab = (L.ntau + slab - 1) / slab;
-  const size_t lds = size_t(NX) * NX * (NX + 1) * sizeof(C2<R>);
+  const size_t lds = size_t(lds_slice_elems<NX>()) * sizeof(C2<R>);
   const bool general = (a.alpha.x != 1.0 || a.alpha.y != 0.0 || a.aux != nullptr);
   const dim3 grid(nslab * a.nrhs);
-  if (a.src_mode == 1) return launch_one<R, NX, DIR, false, 1>(L, a, c, grid, lds, slab, nslab);
-  if (a.src_mode == 2) return launch_one<R, NX, DIR, false, 2>(L, a, c, grid, lds, slab, nslab);
-  if (general) return launch_one<R, NX, DIR, true, 0>(L, a, c, grid, lds, slab, nslab);
-  return launch_one<R, NX, DIR, false, 0>(L, a, c, grid, lds, slab, nslab);
+  // instantiated combinations: plain apply (any reduction), the residual form
+  // b - A x, and the two fused BiCGStab sources with their reductions
+  if (a.src_mode == 1 && a.red_mode == 1 && !general)
+    return launch_one<R, NX, DIR, false, 1, 1>(L, a, c, grid, lds, slab, nslab);
+  if (a.src_mode == 2 && a.red_mode == 3 && !general)
+    return launch_one<R, NX, DIR, false, 2, 3>(L, a, c, grid, lds, slab, nslab);
+  if (a.src_mode == 0 && general && a.red_mode == 0)
+    return launch_one<R, NX, DIR, true, 0, 0>(L, a, c, grid, lds, slab, nslab);
+  if (a.src_mode == 0 && !general) {
+    switch (a.red_mode) {
+      case 0: return launch_one<R, NX, DIR, false, 0, 0>(L, a, c, grid, lds, slab, nslab);
+      case 1: return launch_one<R, NX, DIR, false, 0, 1>(L, a, c, grid, lds, slab, nslab);
+      case 2: return launch_one<R, NX, DIR, false, 0, 2>(L, a, c, grid, lds, slab, nslab);
+      case 3: return launch_one<R, NX, DIR, false, 0, 3>(L, a, c, grid, lds, slab, nslab);
+      default: break;
+    }
+  }
+  set_error("streaming kernel: unsupported combination of source, reduction and scaling");
+  return UFG_EINVAL;
 }
 
 template <typename R, int NX>
@@ -464,13 +565,23 @@ int stream_slab(const Lattice& L) {
 }
 
 bool stream_supported(const Lattice& L) {
-  return (L.nx == 8 || L.nx == 12 || L.nx == 16) && !L.split_host.empty();
+  // buffer offsets are 32-bit: one rhs block of complex128 must stay below 2 GiB
+  const long long block = (long long)L.ntau * L.nx * L.nx * L.nx * (long long)sizeof(double2);
+  return (L.nx == 8 || L.nx == 12 || L.nx == 16) && !L.split_host.empty() &&
+         block < (1ll << 31);
 }
 
 template <typename R>
 int launch_hop_stream(const Lattice& L, const HopArgs<R>& args) {
   HopArgs<R> a = args;
   if (a.beta.x == 0.0 && a.beta.y == 0.0) a.aux = nullptr;
+  // M-type applies the field to the source slice, M^T-type to the output slice
+  const bool fields_ok = (a.shift < 0) ? (a.pre != nullptr && a.post == nullptr)
+                                       : (a.post != nullptr && a.pre == nullptr);
+  if (!fields_ok) {
+    set_error("streaming kernel: field must multiply the source (M) or the output (M^T)");
+    return UFG_EINVAL;
+  }
   switch (L.nx) {
     case 8: return launch_nx<R, 8>(L, a);
     case 12: return launch_nx<R, 12>(L, a);

@@ -99,3 +99,28 @@ def test_invalid_arguments_are_rejected():
         L.apply_M(torch.zeros((1, 4, 4, 4, 4), dtype=torch.complex64, device="cuda"))
     with pytest.raises(ValueError):
         L.apply_M(torch.zeros((1, 5, 4, 4, 4), dtype=torch.complex128, device="cuda"))
+
+
+@pytest.mark.parametrize("dtype", [torch.complex128, torch.complex64])
+@pytest.mark.parametrize("nx", [8, 12, 16])
+def test_apply_every_slab_size(nx, dtype):
+    """The streaming kernel's slab size (slices per workgroup) changes the walk,
+    the halo and the tail slab; every size from 1 to 6 must give the same
+    operator, on a lattice whose Ntau (23) leaves a ragged last slab for all of
+    them."""
+    require_gpu()
+    from paper_1008_3647_amd import Lattice
+    ntau, nrhs = 23, 3
+    sigma = sigma_field(nx, ntau, 410 + nx)
+    x = gaussian_rhs(nx, ntau, range(420, 420 + nrhs))
+    xin = x.astype(np.complex64).astype(np.complex128) if dtype == torch.complex64 else x
+    ref = _oracle(oracle.apply_M, xin, sigma)
+    refd = _oracle(oracle.apply_Mdag, xin, sigma)
+    L = Lattice(nx, ntau, TAU, G, dtype)
+    L.set_aux_field(to_dev(sigma))
+    xd = to_dev(x, dtype)
+    for slab in range(1, 7):
+        say(f"slab parity nx={nx} slab={slab} {dtype}")
+        L.tune(slab, 0)
+        assert rel_err(to_host(L.apply_M(xd)), ref) < TOL[dtype], slab
+        assert rel_err(to_host(L.apply_Mdag(xd)), refd) < TOL[dtype], slab
