@@ -229,7 +229,7 @@ def main():
             roofline = dict(bound="hbm", achieved=r["GBs"], peak=HBM_PEAK_GBS,
                             unit="GB/s", frac=round(r["GBs"] / HBM_PEAK_GBS, 4),
                             traffic=measured_traffic(),
-                            kernel="hop_stream_kernel<float,16> (apply_M, complex64, 8 rhs)",
+                            kernel="hop_stream_kernel<float,16,-1,false,0,0> (apply_M, complex64, 8 rhs)",
                             alg_bytes_per_launch=alg, launch_us=r["us"],
                             working_set="6 rotating (x, y) pairs, 1.3 GB > 256 MB Infinity Cache")
         del xs, ys
