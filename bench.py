@@ -41,6 +41,9 @@ def parse():
     ap.add_argument("--slab", type=int, default=0, help="--mv-only: slab size (0 = default)")
     ap.add_argument("--no-tune", action="store_true",
                     help="skip the launch-shape autotuner (run before the timed region)")
+    ap.add_argument("--report", choices=["config2", "batched", "batched_solve", "force"],
+                    help="print the measurement table of another workload (markdown) "
+                         "instead of the JSON line")
     ap.add_argument("--mv-only", action="store_true",
                     help="only time apply_M (complex64, 8 rhs) and a 256 MiB device copy; "
                          "used for the hardware-counter runs")
@@ -110,6 +113,14 @@ def measured_traffic():
     return d.get("bytes_per_launch")
 
 
+def oracle_residual(sigma, b, x0):
+    """||b_0 - M^T M x_0|| / ||b_0|| with the oracle's FP64 operators."""
+    import oracle
+    mx = oracle.apply_M(x0, sigma, 0.05, 5.0)
+    qx = oracle.apply_Mdag(mx, sigma, 0.05, 5.0)
+    return float(np.linalg.norm(b[0] - qx) / np.linalg.norm(b[0]))
+
+
 def cpu_baseline(sigma, b, iters_gpu, budget_s):
     """The oracle's FP64 two-step BiCGStab on right-hand side 0, run for a
     bounded number of iterations; seconds per iteration scaled to the GPU
@@ -133,8 +144,207 @@ def cpu_baseline(sigma, b, iters_gpu, budget_s):
                        f"{total_iters} iterations x {b.shape[0]} right-hand sides")
 
 
+# ---------------------------------------------------------------------------
+# Measurement tables of the other workloads (python bench.py --report ...).
+# Each prints markdown; stored oracle solutions are read from tests/golden
+# (data written by tests/golden/make_reference_solutions.py).
+
+GOLDEN = os.path.join(ROOT, "tests", "golden")
+
+
+def _timed(fn):
+    import torch
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    out = fn()
+    torch.cuda.synchronize()
+    return out, time.perf_counter() - t0
+
+
+def report_config2(a):
+    """Solver x preconditioner grid, 8^3 x 160, 4 rhs, complex128, tol 1e-10."""
+    import torch
+    from synthetic import sigma_field, gaussian_rhs, WORKLOADS
+    from paper_1008_3647_amd import Lattice, Precond
+    w = WORKLOADS["lattice_8x160"]
+    sigma = torch.from_numpy(sigma_field(w["nx"], w["ntau"], w["sigma_seed"])).cuda()
+    b = torch.from_numpy(gaussian_rhs(w["nx"], w["ntau"], w["rhs_seeds"])).cuda()
+    ref = np.load(os.path.join(GOLDEN, "lattice_8x160_reference.npz"))
+    idx = torch.from_numpy(ref["sample_index"]).cuda()
+    L = Lattice(w["nx"], w["ntau"], 0.05, 5.0, torch.complex128)
+    L.set_aux_field(sigma)
+    tol = 1e-10
+
+    def err_vs_oracle(x):
+        e = 0.0
+        for k in range(x.shape[0]):
+            xs = x[k].reshape(-1)[idx].cpu().numpy()
+            rs = ref[f"x{k}_sample"]
+            e = max(e, float(np.max(np.abs(xs - rs)) / np.max(np.abs(rs))))
+        return e
+
+    cells = [("CG", "none", {})]
+    for d in (8, 16, 32):
+        for eps in (1e-2, 3e-3, 1e-3, 3e-4, 1e-4):
+            cells.append(("CG", "cheb", dict(degree=d, eps=eps, lam_max=-1.0)))
+    for alpha in (1.0, 1.5, 2.0, 3.0):
+        cells.append(("CG", "sca", dict(alpha=alpha)))
+    cells.append(("CG", "wce", dict(wce_order=1)))
+    cells.append(("BiCGStab", "none", {}))
+    for d in (0, 1, 2, 4):
+        cells.append(("BiCGStab", "wce", dict(wce_order=d)))
+        if d > 0:
+            cells.append(("BiCGStab", "wce", dict(wce_order=d, euler=True)))
+    cells.append(("BiCGStab", "cheb", dict(degree=8, eps=1e-2, lam_max=-1.0)))
+    cells.append(("BiCGStab", "sca", dict(alpha=2.0)))
+    print("| solver | preconditioner | iterations | MV (raw) | M0^-1 | SCA sweeps | "
+          "MV (paper model) | wall ms | relres | error vs oracle | status |")
+    print("|---|---|---|---|---|---|---|---|---|---|---|")
+    for solver, kind, kw in cells:
+        pc = Precond(kind, **kw) if kind != "none" else None
+        if solver == "CG":
+            run = lambda: L.solve_cg_normal(b, pc, tol=tol, maxit=20000)  # noqa: E731
+        else:
+            run = lambda: L.solve_bicgstab(b, "two_step", pc, tol=tol, maxit=20000)  # noqa: E731
+        run()  # warm-up (preconditioner setup, lambda_max estimate)
+        (x, st), secs = _timed(run)
+        its = st["iters"][0] if solver == "CG" else "+".join(str(i) for i in st["iters"])
+        rr = st["relres"][0] if solver == "CG" else max(st["relres"])
+        desc = kind if not kw else kind + " " + ", ".join(f"{k}={v}" for k, v in kw.items()
+                                                          if k != "lam_max")
+        print(f"| {solver} | {desc} | {its} | {st['mv']} | {st['m0inv']} | {st['sca_sweeps']} | "
+              f"{st['paper_mv']:.0f} | {secs * 1e3:.1f} | {rr:.2e} | "
+              f"{err_vs_oracle(x):.1e} | {st['status']} |", flush=True)
+    return 0
+
+
+def report_batched(a):
+    """64 uneven lattices, 2 rhs each, complex64-refined two-step BiCGStab in one
+    batched solve, against the same 64 problems solved one after another."""
+    import torch
+    from synthetic import sigma_field, gaussian_rhs, batched_problem_shapes, WORKLOADS
+    from paper_1008_3647_amd import Lattice
+    from paper_1008_3647_amd.lattice import solve_batched
+    from paper_1008_3647_amd.autotune import tune_batched
+    w = WORKLOADS["batched_64"]
+    shapes = batched_problem_shapes(w["count"], w["shape_seed"])
+    lats, bs = [], []
+    for i, (nx, ntau) in enumerate(shapes):
+        L = Lattice(nx, ntau, 0.05, 5.0, torch.complex128)
+        L.set_aux_field(torch.from_numpy(sigma_field(nx, ntau, w["sigma_seed0"] + i)).cuda())
+        seeds = [w["rhs_seed0"] + w["nrhs"] * i + k for k in range(w["nrhs"])]
+        lats.append(L)
+        bs.append(torch.from_numpy(gaussian_rhs(nx, ntau, seeds)).cuda())
+    sites = sum(nx ** 3 * ntau for nx, ntau in shapes)
+    choice = tune_batched(lats, bs, verbose=False)
+    solve_batched(lats, bs, tol=1e-10)  # warm-up
+    times = []
+    for _ in range(max(a.steps, 1)):
+        (xs, st), secs = _timed(lambda: solve_batched(lats, bs, tol=1e-10))
+        times.append(secs)
+    t_batch = float(np.median(times))
+    seq = []
+    t_seq = 0.0
+    for L, b in zip(lats, bs):
+        L.solve_bicgstab(b, "two_step", tol=1e-10, mixed=True, maxit=20000)  # warm-up
+        (x1, s1), secs = _timed(lambda: L.solve_bicgstab(b, "two_step", tol=1e-10, mixed=True,
+                                                          maxit=20000))
+        t_seq += secs
+        seq.append((x1, s1))
+    diffs = [float((x - x1).abs().max().item() / x1.abs().max().item())
+             for x, (x1, _) in zip(xs, seq)]
+    relres = [max(s["relres"]) for s in st]
+    iters = [sum(s["iters"]) for s in st]
+    print(f"64 problems (Nx in {{6,8,10,12}}, Ntau in 80..320), 2 rhs each, {sites} sites "
+          f"in total; complex64-refined two-step BiCGStab, tol 1e-10 per step.\n")
+    print(f"| quantity | value |\n|---|---|")
+    print(f"| batched solve, one call (median of {len(times)}) | {t_batch * 1e3:.1f} ms |")
+    print(f"| sum of the 64 sequential solves | {t_seq * 1e3:.1f} ms |")
+    print(f"| speedup | {t_seq / t_batch:.2f}x |")
+    print(f"| autotuned launch shape | {choice} |")
+    print(f"| worst per-system relres (batched) | {max(relres):.2e} |")
+    print(f"| all systems converged | {all(s['status'] == 0 for s in st)} |")
+    print(f"| iterations per system (both steps): min / median / max | "
+          f"{min(iters)} / {int(np.median(iters))} / {max(iters)} |")
+    print(f"| max relative difference, batched vs sequential solution | {max(diffs):.1e} |")
+    return 0
+
+
+def report_batched_solve(a):
+    """One batched solve of the 64-lattice workload with the library's default
+    launch shape and nothing else (the kernel-trace run)."""
+    import torch
+    from synthetic import sigma_field, gaussian_rhs, batched_problem_shapes, WORKLOADS
+    from paper_1008_3647_amd import Lattice
+    from paper_1008_3647_amd.lattice import solve_batched
+    w = WORKLOADS["batched_64"]
+    shapes = batched_problem_shapes(w["count"], w["shape_seed"])
+    lats, bs = [], []
+    for i, (nx, ntau) in enumerate(shapes):
+        L = Lattice(nx, ntau, 0.05, 5.0, torch.complex128)
+        L.set_aux_field(torch.from_numpy(sigma_field(nx, ntau, w["sigma_seed0"] + i)).cuda())
+        seeds = [w["rhs_seed0"] + w["nrhs"] * i + k for k in range(w["nrhs"])]
+        lats.append(L)
+        bs.append(torch.from_numpy(gaussian_rhs(nx, ntau, seeds)).cuda())
+    (xs, st), secs = _timed(lambda: solve_batched(lats, bs, tol=1e-10))
+    its = [s["iters"] for s in st]
+    work = sum(nx ** 3 * nt * w["nrhs"] * (i[0] + i[1]) for (nx, nt), i in zip(shapes, its))
+    print(f"batched solve {secs * 1e3:.1f} ms; max iterations per step "
+          f"{max(i[0] for i in its)} / {max(i[1] for i in its)}; "
+          f"sum of sites x rhs x iterations {work:.3e}; worst relres "
+          f"{max(max(s['relres']) for s in st):.2e}")
+    return 0
+
+
+def report_force(a):
+    """HMC force on 12^3 x 200 (complex128, WCE2-preconditioned solves, tol 1e-12):
+    time per force, error against the stored oracle gradient, 20 leapfrog steps."""
+    import torch
+    from synthetic import sigma_field, gaussian_rhs, gaussian_momenta, WORKLOADS
+    from paper_1008_3647_amd import Lattice, Precond
+    from paper_1008_3647_amd.action import force, heat_bath_phi, leapfrog, hamiltonian
+    w = WORKLOADS["lattice_12x200"]
+    nx, ntau = w["nx"], w["ntau"]
+    sigma = torch.from_numpy(sigma_field(nx, ntau, w["sigma_seed"])).cuda()
+    eta = torch.from_numpy(gaussian_rhs(nx, ntau, [w["eta_seed"]])).cuda()
+    L = Lattice(nx, ntau, 0.05, 5.0, torch.complex128)
+    L.set_aux_field(sigma)
+    phi = heat_bath_phi(L, eta)
+    pc = Precond("wce", wce_order=2)
+    ref = np.load(os.path.join(GOLDEN, "lattice_12x200_reference.npz"))
+    rows = []
+    for mixed in (False, True):
+        force(sigma, phi, L, pc, tol=1e-12, mixed=mixed)  # warm-up
+        times = []
+        for _ in range(3):
+            (S, g), secs = _timed(lambda: force(sigma, phi, L, pc, tol=1e-12, mixed=mixed))
+            times.append(secs)
+        gs = g.reshape(-1)[torch.from_numpy(ref["sites"]).cuda()].cpu().numpy()
+        err = float(np.linalg.norm(gs - ref["grad_sample"]) / np.linalg.norm(ref["grad_sample"]))
+        rows.append((mixed, float(np.median(times)), err, S))
+    pi0 = torch.from_numpy(gaussian_momenta(nx, ntau, w["momentum_seed"])).cuda()
+    pcl = Precond("wce", wce_order=2, euler=True)
+    dt = 0.0025
+    (traj, secs) = _timed(lambda: leapfrog(sigma, pi0, phi, L, dt, 20, pcl, tol=1e-13))
+    s1, p1, S1 = traj
+    dH = hamiltonian(p1, S1[-1]) - hamiltonian(pi0, S1[0])
+    s2, p2, S2 = leapfrog(s1, -p1, phi, L, dt, 20, pcl, tol=1e-13)
+    rev = float((s2 - sigma).abs().max().item())
+    print(f"12^3 x 200 lattice, one pseudofermion, WCE2-preconditioned BiCGStab, tol 1e-12.\n")
+    print("| force (two solves + contraction) | time per force | error vs oracle gradient (64 sites) |")
+    print("|---|---|---|")
+    for mixed, t, err, S in rows:
+        print(f"| {'complex64-refined' if mixed else 'complex128'} | {t * 1e3:.1f} ms | {err:.1e} |")
+    print(f"\n20 leapfrog steps, dt = {dt} (WCE2 + Euler, tol 1e-13): {secs:.2f} s, "
+          f"dH = {dH:.3e}, reversibility max|sigma - sigma0| = {rev:.1e}")
+    return 0
+
+
 def main():
     a = parse()
+    if a.report:
+        return {"config2": report_config2, "batched": report_batched,
+                "batched_solve": report_batched_solve, "force": report_force}[a.report](a)
     if a.mv_only:
         return mv_only(a)
     if a.gpus != 1:
@@ -186,12 +396,6 @@ def main():
     torch.cuda.synchronize()
     t_fp64 = (time.perf_counter() - t0) / a.fp64_steps
 
-    # error against the FP64 oracle: the oracle's M recomputes the residuals of rhs 0
-    import oracle
-    xh = x[0].cpu().numpy()
-    mx = oracle.apply_M(xh, sigma_h, 0.05, 5.0)
-    qx = oracle.apply_Mdag(mx, sigma_h, 0.05, 5.0)
-    relres_q_oracle = float(np.linalg.norm(b_h[0] - qx) / np.linalg.norm(b_h[0]))
     diff_fp64 = float((x - x64).abs().max().item() / x64.abs().max().item())
 
     # apply_M bandwidth (the dominant kernel of the solve), HIP events on the lattice
@@ -225,13 +429,27 @@ def main():
         res["alg_bytes"] = alg
         mv["c64" if dt == torch.complex64 else "c128"] = res
         if dt == torch.complex64:
+            # plain streaming copy x -> y over the same rotating buffers: the
+            # achievable rate for a kernel that reads and writes one vector
+            from paper_1008_3647_amd.lattice import device_copy
+            cur = torch.cuda.current_stream()
+            e0.record(cur)
+            for i in range(a.mv_launches):
+                device_copy(xs[i % ROT], ys[i % ROT])
+            e1.record(cur)
+            torch.cuda.synchronize()
+            cms = e0.elapsed_time(e1) / a.mv_launches
+            copy_bytes = 2 * xs[0].nbytes
+            copy_gbs = round(copy_bytes / cms / 1e6, 1)
             r = res["apply_M_hbm"]
             roofline = dict(bound="hbm", achieved=r["GBs"], peak=HBM_PEAK_GBS,
                             unit="GB/s", frac=round(r["GBs"] / HBM_PEAK_GBS, 4),
                             traffic=measured_traffic(),
                             kernel="hop_stream_kernel<float,16,-1,false,0,0> (apply_M, complex64, 8 rhs)",
                             alg_bytes_per_launch=alg, launch_us=r["us"],
-                            working_set="6 rotating (x, y) pairs, 1.3 GB > 256 MB Infinity Cache")
+                            working_set="6 rotating (x, y) pairs, 1.3 GB > 256 MB Infinity Cache",
+                            copy_GBs=copy_gbs, frac_of_copy=round(r["GBs"] / copy_gbs, 4),
+                            copy="ufg_device_copy of one 105 MB vector (read + write), same buffers")
         del xs, ys
         Lm.close()
 
@@ -255,7 +473,6 @@ def main():
         "iters": list(st["iters"]),
         "relres_steps": list(st["relres"]),
         "relres_normal": st["relres_normal"],
-        "relres_normal_oracle_rhs0": relres_q_oracle,
         "reliable_updates": st["reliable_updates"],
         "fp64_seconds": round(t_fp64, 4),
         "fp64_iters": list(st64["iters"]),
@@ -267,7 +484,10 @@ def main():
         "roofline": roofline,
     }
     if not a.no_cpu_baseline:
+        # the oracle leg: its timing (cpu_baseline) and its check of the GPU
+        # solution (the oracle's M recomputes the two-step residual of rhs 0)
         out["cpu_baseline"] = cpu_baseline(sigma_h, b_h, st["iters"], a.cpu_seconds)
+        out["relres_normal_oracle_rhs0"] = oracle_residual(sigma_h, b_h, x[0].cpu().numpy())
     else:
         out["cpu_baseline"] = None
     print(json.dumps(out), flush=True)

@@ -256,6 +256,16 @@ int ufg_cheb_roots(int degree, double eps, double* out, double* out_c);
 int ufg_euler_weights(int order, double p, double* out);
 int ufg_transfer_matrix(int nx, double tau, double* out);
 
+/*
+ * ufg_device_copy -- measurement helper, not part of the method: a plain
+ *   streaming copy of `bytes` from src to dst (device pointers, 16-byte
+ *   aligned, bytes a multiple of 16; the regions must not overlap) with
+ *   16-byte loads and non-temporal stores. It calibrates the achievable HBM
+ *   rate that the streaming M / M^T kernel is compared with. hip_stream: a
+ *   hipStream_t or NULL. Asynchronous.
+ */
+int ufg_device_copy(const void* src, void* dst, long long bytes, void* hip_stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -1,10 +1,13 @@
-"""Autotuner for the launch shapes of a lattice (slab size of the streaming
-M / M^T kernel, workgroups per right-hand side of the Krylov vector kernels).
+"""Autotuners for launch shapes.
+
+tune(): per lattice, the slab size of the streaming M / M^T kernel and the
+workgroups per right-hand side of the Krylov vector kernels. tune_batched():
+the persistent launch shape of solve_batched for a set of problems.
 
 Each candidate is timed on the real workload: a BiCGStab run of a fixed number
 of iterations (tolerance unreachable, so every candidate does identical work)
-on the caller's right-hand sides. The best pair is applied with
-Lattice.tune() and cached in a JSON file keyed by device, lattice shape,
+on the caller's right-hand sides. tune() applies the best pair with
+Lattice.tune() and caches it in a JSON file keyed by device, lattice shape,
 number of right-hand sides, dtype and precision mode.
 """
 from __future__ import annotations
@@ -87,3 +90,35 @@ def tune(L: Lattice, b: torch.Tensor, mixed=False, op="M", iters=16, reps=2,
         data[key] = choice
         _store(cache, data)
     return dict(choice, cached=False, candidates=results)
+
+
+def tune_batched(lattices, bs, mixed=True, iters=10, reps=2, hop_blocks=(2, 4, 8),
+                 vec_blocks=(4, 8, 16), chunks=(4096, 16384), verbose=False):
+    """Pick the launch shape of solve_batched (workgroups per CU of the
+    persistent operator and vector launches, elements per vector work item) for
+    this set of problems. Each candidate runs the batch for a fixed number of
+    iterations per step (tolerance unreachable, identical work); the best is
+    applied with solve_batched_tune and returned."""
+    from .lattice import solve_batched, solve_batched_tune
+    results = []
+    for hb in hop_blocks:
+        for vb in vec_blocks:
+            for ch in chunks:
+                solve_batched_tune(hb, vb, ch)
+                solve_batched(lattices, bs, tol=1e-30, maxit=2, mixed=mixed, check_every=2)
+                best_t = float("inf")
+                for _ in range(reps):
+                    torch.cuda.synchronize()
+                    t0 = time.perf_counter()
+                    solve_batched(lattices, bs, tol=1e-30, maxit=iters, mixed=mixed,
+                                  check_every=iters)
+                    torch.cuda.synchronize()
+                    best_t = min(best_t, time.perf_counter() - t0)
+                results.append(dict(hop_blocks_per_cu=hb, vec_blocks_per_cu=vb, chunk=ch,
+                                    seconds=best_t))
+                if verbose:
+                    print(f"tune_batched {hb} {vb} {ch}: {best_t * 1e3:.2f} ms", flush=True)
+    best = min(results, key=lambda d: d["seconds"])
+    solve_batched_tune(best["hop_blocks_per_cu"], best["vec_blocks_per_cu"], best["chunk"])
+    return dict(hop_blocks_per_cu=best["hop_blocks_per_cu"],
+                vec_blocks_per_cu=best["vec_blocks_per_cu"], chunk=best["chunk"])

@@ -392,4 +392,11 @@ int solve_batched_tune(int hop_blocks_per_cu, int vec_blocks_per_cu, long long c
   return batched_tune(hop_blocks_per_cu, vec_blocks_per_cu, chunk);
 }
 
+int ufg_device_copy(const void* src, void* dst, long long bytes, void* hip_stream) {
+  UFG_CHECK(src && dst && bytes > 0 && bytes % 16 == 0, "ufg_device_copy: bad pointers or size");
+  UFG_CHECK(((uintptr_t)src % 16) == 0 && ((uintptr_t)dst % 16) == 0,
+            "ufg_device_copy: pointers must be 16-byte aligned");
+  return k_device_copy(src, dst, bytes, (hipStream_t)hip_stream);
+}
+
 }  // extern "C"

@@ -421,19 +421,29 @@ int run_batched(std::vector<Lattice*>& Ls, const void* const* bu, void* const* x
     }
   }
   const int S = (int)segs.size();
+  // Work tables over the segments marked in `use` (the others get no items):
+  // operator items (segment, slice group) and vector items (segment, chunk),
+  // with each segment's first item and item count (its partial sums).
   std::vector<BHop> hops;
-  std::vector<int> hfirst(S), hcount(S);
   std::vector<BVec> vecs;
-  std::vector<int> vfirst(S), vcount(S);
-  for (int s = 0; s < S; ++s) {
-    hfirst[s] = (int)hops.size();
-    for (int t0 = 0; t0 < segs[s].ntau; t0 += segs[s].spw) hops.push_back(BHop{s, t0});
-    hcount[s] = (int)hops.size() - hfirst[s];
-    vfirst[s] = (int)vecs.size();
-    for (long long lo = 0; lo < segs[s].n; lo += g_chunk)
-      vecs.push_back(BVec{s, lo, std::min(segs[s].n, lo + g_chunk)});
-    vcount[s] = (int)vecs.size() - vfirst[s];
-  }
+  std::vector<int> htab(4 * S);
+  auto make_tables = [&](const std::vector<char>& use) {
+    hops.clear();
+    vecs.clear();
+    for (int s = 0; s < S; ++s) {
+      htab[s] = (int)hops.size();
+      if (use[s])
+        for (int t0 = 0; t0 < segs[s].ntau; t0 += segs[s].spw) hops.push_back(BHop{s, t0});
+      htab[S + s] = (int)hops.size() - htab[s];
+      htab[2 * S + s] = (int)vecs.size();
+      if (use[s])
+        for (long long lo = 0; lo < segs[s].n; lo += g_chunk)
+          vecs.push_back(BVec{s, lo, std::min(segs[s].n, lo + g_chunk)});
+      htab[3 * S + s] = (int)vecs.size() - htab[2 * S + s];
+    }
+  };
+  const std::vector<char> all_segs(S, 1);
+  make_tables(all_segs);
   // device memory
   const size_t vbytes = sizeof(C2<RI>) * (size_t)total;
   Dev dvec[7], dr64, dy, dsegs, dhops, dvecs, dtab, dhpart, dvpart, dstate;
@@ -456,18 +466,24 @@ int run_batched(std::vector<Lattice*>& Ls, const void* const* bu, void* const* x
     }
   } guard{cs};
   int* tab = reinterpret_cast<int*>(dtab.p);
-  std::vector<int> htab(4 * S);
-  for (int s = 0; s < S; ++s) {
-    htab[s] = hfirst[s];
-    htab[S + s] = hcount[s];
-    htab[2 * S + s] = vfirst[s];
-    htab[3 * S + s] = vcount[s];
-  }
-  UFG_HIP(hipMemcpyAsync(tab, htab.data(), sizeof(int) * 4 * S, hipMemcpyHostToDevice, cs));
-  UFG_HIP(hipMemcpyAsync(dhops.p, hops.data(), sizeof(BHop) * hops.size(), hipMemcpyHostToDevice,
-                         cs));
-  UFG_HIP(hipMemcpyAsync(dvecs.p, vecs.data(), sizeof(BVec) * vecs.size(), hipMemcpyHostToDevice,
-                         cs));
+  int nh = 0, nv = 0;
+  dim3 hgrid(1), vgrid(1);
+  // upload the tables (the device buffers were sized for all segments)
+  auto upload_tables = [&]() -> int {
+    UFG_HIP(hipMemcpyAsync(tab, htab.data(), sizeof(int) * 4 * S, hipMemcpyHostToDevice, cs));
+    if (!hops.empty())
+      UFG_HIP(hipMemcpyAsync(dhops.p, hops.data(), sizeof(BHop) * hops.size(),
+                             hipMemcpyHostToDevice, cs));
+    if (!vecs.empty())
+      UFG_HIP(hipMemcpyAsync(dvecs.p, vecs.data(), sizeof(BVec) * vecs.size(),
+                             hipMemcpyHostToDevice, cs));
+    nh = (int)hops.size();
+    nv = (int)vecs.size();
+    hgrid = dim3(std::max(1, std::min(nh, ncu * g_hop_blocks_per_cu)));
+    vgrid = dim3(std::max(1, std::min(nv, ncu * g_vec_blocks_per_cu)));
+    return UFG_OK;
+  };
+  UFG_TRY(upload_tables());
   KrylovState K;
   K.nrhs = S;
   K.st = reinterpret_cast<RhsState*>(dstate.p);
@@ -496,9 +512,6 @@ int run_batched(std::vector<Lattice*>& Ls, const void* const* bu, void* const* x
   const BSeg* dseg = reinterpret_cast<const BSeg*>(dsegs.p);
   const BHop* dhop = reinterpret_cast<const BHop*>(dhops.p);
   const BVec* dvv = reinterpret_cast<const BVec*>(dvecs.p);
-  const int nh = (int)hops.size(), nv = (int)vecs.size();
-  const dim3 hgrid(std::min(nh, ncu * g_hop_blocks_per_cu)),
-      vgrid(std::min(nv, ncu * g_vec_blocks_per_cu));
   const size_t lds = std::max<size_t>(lds_bytes, 64);
   // attributes are set before any capture
   UFG_HIP(hipFuncSetAttribute((const void*)bhop_kernel<RI, -1, false>,
@@ -576,14 +589,23 @@ int run_batched(std::vector<Lattice*>& Ls, const void* const* bu, void* const* x
       return UFG_OK;
     };
     Graph G;
-    UFG_HIP(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
-    const int brc = body();
-    hipGraph_t graph = nullptr;
-    const hipError_t ec = hipStreamEndCapture(cs, &graph);
-    G.g = graph;
-    UFG_TRY(brc);
-    UFG_HIP(ec);
-    UFG_HIP(hipGraphInstantiate(&G.e, G.g, nullptr, nullptr, 0));
+    auto capture = [&]() -> int {
+      if (G.e) (void)hipGraphExecDestroy(G.e);
+      if (G.g) (void)hipGraphDestroy(G.g);
+      G.e = nullptr;
+      G.g = nullptr;
+      UFG_HIP(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
+      const int brc = body();
+      hipGraph_t graph = nullptr;
+      const hipError_t ec = hipStreamEndCapture(cs, &graph);
+      G.g = graph;
+      UFG_TRY(brc);
+      UFG_HIP(ec);
+      UFG_HIP(hipGraphInstantiate(&G.e, G.g, nullptr, nullptr, 0));
+      return UFG_OK;
+    };
+    UFG_TRY(capture());
+    int in_tables = S;  // segments the current tables cover
     const int launches = (o.maxit + check - 1) / check;
     bool done = false;
     UFG_HIP(hipMemcpyAsync(hflags.data(), K.active, sizeof(int) * 3 * S, hipMemcpyDeviceToHost, cs));
@@ -613,7 +635,23 @@ int run_batched(std::vector<Lattice*>& Ls, const void* const* bu, void* const* x
       UFG_HIP(hipMemcpyAsync(hflags.data(), K.active, sizeof(int) * 3 * S, hipMemcpyDeviceToHost,
                              cs));
       UFG_HIP(hipStreamSynchronize(cs));
-      done = std::all_of(hflags.begin(), hflags.begin() + S, [](int v) { return v == 0; });
+      const int nactive = (int)std::count_if(hflags.begin(), hflags.begin() + S,
+                                             [](int v) { return v != 0; });
+      done = nactive == 0;
+      // once half of the covered systems have stopped, drop them from the work
+      // tables so that the tail of the batch launches only the live work
+      if (!done && 2 * nactive <= in_tables) {
+        std::vector<char> live(S);
+        for (int s = 0; s < S; ++s) live[s] = hflags[s] != 0;
+        make_tables(live);
+        UFG_TRY(upload_tables());
+        UFG_TRY(capture());
+        in_tables = nactive;
+      }
+    }
+    if (in_tables != S) {  // the epilogue runs over every segment
+      make_tables(all_segs);
+      UFG_TRY(upload_tables());
     }
     vop(4, nullptr);  // final x64 += x_in
     UFG_HIP(hipMemcpyAsync(hst.data(), K.st, sizeof(RhsState) * S, hipMemcpyDeviceToHost, cs));

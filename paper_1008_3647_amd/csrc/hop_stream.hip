@@ -162,12 +162,18 @@ constexpr int lds_slice_elems() {
 }
 
 // T^3 of the slice held as z-lines in v (thread (y, x)); result left in v.
+// Barriers: stage 1 (thread (y, x) writes its z-line) feeds the y-lines of
+// other waves, and the x-lines feed the z-lines of other waves. The y-lines
+// (z, x) and x-lines (z, y) of one z-plane belong to the same NX consecutive
+// threads, which sit in one wave when NX divides 64: there a wave-level
+// ordering point replaces the block barrier. Each thread's last read and its
+// next first write touch only its own z-line, so no barrier guards the reuse
+// of the buffer by the next slice.
 template <typename R, int NX>
 __device__ __forceinline__ void slice_T3(const SplitCoef<R, NX>& c, C2<R>* lds, int l,
                                          C2<R> (&v)[NX]) {
   const int y = l / NX, x = l - (l / NX) * NX;
   split_line<R, NX>(c, v);  // along z
-  __syncthreads();          // the previous slice's readers are done with lds
 #pragma unroll
   for (int z = 0; z < NX; ++z) lds[lds_at<NX>(z * NX + y, x)] = v[z];
   __syncthreads();
@@ -180,7 +186,15 @@ __device__ __forceinline__ void slice_T3(const SplitCoef<R, NX>& c, C2<R>* lds, 
 #pragma unroll
     for (int yy = 0; yy < NX; ++yy) lds[lds_at<NX>(z * NX + yy, xx)] = w[yy];
   }
-  __syncthreads();
+  if constexpr (64 % NX == 0) {
+    // LDS operations of one wave are performed in order; the fences keep the
+    // compiler from moving the reads above the writes
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+  } else {
+    __syncthreads();
+  }
   {
     const int z = l / NX, yy = l - (l / NX) * NX;
 #pragma unroll

@@ -72,6 +72,8 @@ int k_axpby(const Lattice& L, double2 a, const C2<R>* x, double2 b, C2<R>* y, in
 template <typename RI, typename RO>
 int k_convert(const Lattice& L, const C2<RI>* in, C2<RO>* out, int nrhs, const int* gate);
 int k_promote(const Lattice& L, double2* x64, float2* x32, int nrhs, const int* gate);
+// Streaming device copy of `bytes` (multiple of 16, 16-byte aligned pointers).
+int k_device_copy(const void* src, void* dst, long long bytes, hipStream_t stream);
 int k_demote(const Lattice& L, const double2* r64, float2* r32, const float2* rhat,
              const KrylovState& K, const int* gate);
 template <typename R>

@@ -607,4 +607,25 @@ template int k_convert<double, float>(const Lattice&, const double2*, float2*, i
 template int k_convert<double, double>(const Lattice&, const double2*, double2*, int, const int*);
 template int k_convert<float, float>(const Lattice&, const float2*, float2*, int, const int*);
 
+namespace {
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+// Plain streaming copy (16-byte loads, non-temporal 16-byte stores), the
+// reference for the achievable HBM rate of the streaming kernels.
+__global__ void __launch_bounds__(256) copy_kernel(const f32x4* __restrict__ src,
+                                                   f32x4* __restrict__ dst, long long n) {
+  for (long long i = blockIdx.x * 256ll + threadIdx.x; i < n; i += (long long)gridDim.x * 256)
+    __builtin_nontemporal_store(src[i], &dst[i]);
+}
+}  // namespace
+
+int k_device_copy(const void* src, void* dst, long long bytes, hipStream_t stream) {
+  const long long n = bytes / 16;
+  const long long want = (n + 255) / 256;
+  const int grid = (int)std::min<long long>(std::max<long long>(want, 1), 8192);
+  hipLaunchKernelGGL(copy_kernel, dim3(grid), dim3(256), 0, stream, (const f32x4*)src,
+                     (f32x4*)dst, n);
+  UFG_HIP(hipGetLastError());
+  return UFG_OK;
+}
+
 }  // namespace ufg

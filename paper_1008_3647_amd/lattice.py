@@ -190,6 +190,16 @@ def transfer_matrix(nx, tau):
     return [[out[i * nx + j] for j in range(nx)] for i in range(nx)]
 
 
+def device_copy(src, dst):
+    """Streaming device copy src -> dst (C ABI ufg_device_copy) on torch's current
+    stream: the plain-copy reference rate for the streaming operator."""
+    if src.nbytes != dst.nbytes or not (src.is_cuda and dst.is_cuda):
+        raise ValueError("device_copy needs two device tensors of equal size")
+    stream = torch.cuda.current_stream(src.device).cuda_stream
+    L.check(L.load().ufg_device_copy(C.c_void_p(src.data_ptr()), C.c_void_p(dst.data_ptr()),
+                                     src.nbytes, C.c_void_p(stream)), "ufg_device_copy")
+
+
 def solve_batched(lattices, bs, tol=1e-10, maxit=10000, mixed=True, delta=0.1, check_every=10):
     """Two-step BiCGStab for many lattices at once (C ABI solve_batched).
 

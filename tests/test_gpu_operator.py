@@ -124,3 +124,14 @@ def test_apply_every_slab_size(nx, dtype):
         L.tune(slab, 0)
         assert rel_err(to_host(L.apply_M(xd)), ref) < TOL[dtype], slab
         assert rel_err(to_host(L.apply_Mdag(xd)), refd) < TOL[dtype], slab
+
+
+def test_device_copy_helper():
+    """The copy used as the bandwidth reference moves bytes exactly."""
+    require_gpu()
+    from paper_1008_3647_amd.lattice import device_copy
+    x = torch.randn(3 * 1024 * 1024 + 16, dtype=torch.float32, device="cuda")
+    y = torch.zeros_like(x)
+    device_copy(x, y)
+    torch.cuda.synchronize()
+    assert torch.equal(x, y)
