@@ -206,10 +206,13 @@ int solve_batched(const ufg_lattice* Ls, int nprob, const void* const* b,
 /*
  * solve_batched_tune -- launch shape of solve_batched chosen by the autotuner
  *   (0 keeps the default): workgroups per compute unit of the persistent
- *   operator and vector launches (1..64) and elements per vector work item
- *   (256..4194304). Process-wide; not thread safe against concurrent solves.
+ *   operator and vector launches (1..64; defaults 4 and 8), elements per vector
+ *   work item (256..4194304; default 4096) and time slices per slab of the
+ *   batched streaming operator (1..64; default 2). Process-wide; not thread
+ *   safe against concurrent solves. Results do not depend on them beyond
+ *   floating-point summation order.
  */
-int solve_batched_tune(int hop_blocks_per_cu, int vec_blocks_per_cu, long long chunk);
+int solve_batched_tune(int hop_blocks_per_cu, int vec_blocks_per_cu, long long chunk, int slab);
 
 /*
  * force_dS_dsigma -- gradient of S = sum_r phi_r^dagger (M^dagger M)^{-1} phi_r

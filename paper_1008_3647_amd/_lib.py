@@ -62,7 +62,7 @@ _SIGNATURES = {
     "solve_batched": (C.c_int, [C.POINTER(_P), C.c_int, C.POINTER(_P), C.POINTER(_P),
                                 C.POINTER(C.c_int), C.POINTER(ufg_precond),
                                 C.POINTER(ufg_solve_opts), C.POINTER(ufg_solve_stats)]),
-    "solve_batched_tune": (C.c_int, [C.c_int, C.c_int, C.c_longlong]),
+    "solve_batched_tune": (C.c_int, [C.c_int, C.c_int, C.c_longlong, C.c_int]),
     "force_dS_dsigma": (C.c_int, [_P, _P, _P, C.c_int, _P]),
     "lattice_tune": (C.c_int, [_P, C.c_int, C.c_int]),
     "lattice_norm2": (C.c_int, [_P, _P, C.c_int, C.POINTER(C.c_double)]),

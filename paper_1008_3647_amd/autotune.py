@@ -12,6 +12,7 @@ number of right-hand sides, dtype and precision mode.
 """
 from __future__ import annotations
 
+import itertools
 import json
 import os
 import time
@@ -93,32 +94,30 @@ def tune(L: Lattice, b: torch.Tensor, mixed=False, op="M", iters=16, reps=2,
 
 
 def tune_batched(lattices, bs, mixed=True, iters=10, reps=2, hop_blocks=(2, 4, 8),
-                 vec_blocks=(4, 8, 16), chunks=(4096, 16384), verbose=False):
+                 vec_blocks=(8, 16), chunks=(4096, 16384), slabs=(1, 2, 4), verbose=False):
     """Pick the launch shape of solve_batched (workgroups per CU of the
-    persistent operator and vector launches, elements per vector work item) for
+    persistent operator and vector launches, elements per vector work item,
+    slices per slab of the batched operator) for
     this set of problems. Each candidate runs the batch for a fixed number of
     iterations per step (tolerance unreachable, identical work); the best is
     applied with solve_batched_tune and returned."""
     from .lattice import solve_batched, solve_batched_tune
     results = []
-    for hb in hop_blocks:
-        for vb in vec_blocks:
-            for ch in chunks:
-                solve_batched_tune(hb, vb, ch)
-                solve_batched(lattices, bs, tol=1e-30, maxit=2, mixed=mixed, check_every=2)
-                best_t = float("inf")
-                for _ in range(reps):
-                    torch.cuda.synchronize()
-                    t0 = time.perf_counter()
-                    solve_batched(lattices, bs, tol=1e-30, maxit=iters, mixed=mixed,
-                                  check_every=iters)
-                    torch.cuda.synchronize()
-                    best_t = min(best_t, time.perf_counter() - t0)
-                results.append(dict(hop_blocks_per_cu=hb, vec_blocks_per_cu=vb, chunk=ch,
-                                    seconds=best_t))
-                if verbose:
-                    print(f"tune_batched {hb} {vb} {ch}: {best_t * 1e3:.2f} ms", flush=True)
+    for hb, vb, ch, sl in itertools.product(hop_blocks, vec_blocks, chunks, slabs):
+        solve_batched_tune(hb, vb, ch, sl)
+        solve_batched(lattices, bs, tol=1e-30, maxit=2, mixed=mixed, check_every=2)
+        best_t = float("inf")
+        for _ in range(reps):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            solve_batched(lattices, bs, tol=1e-30, maxit=iters, mixed=mixed, check_every=iters)
+            torch.cuda.synchronize()
+            best_t = min(best_t, time.perf_counter() - t0)
+        results.append(dict(hop_blocks_per_cu=hb, vec_blocks_per_cu=vb, chunk=ch, slab=sl,
+                            seconds=best_t))
+        if verbose:
+            print(f"tune_batched {hb} {vb} {ch} {sl}: {best_t * 1e3:.2f} ms", flush=True)
     best = min(results, key=lambda d: d["seconds"])
-    solve_batched_tune(best["hop_blocks_per_cu"], best["vec_blocks_per_cu"], best["chunk"])
-    return dict(hop_blocks_per_cu=best["hop_blocks_per_cu"],
-                vec_blocks_per_cu=best["vec_blocks_per_cu"], chunk=best["chunk"])
+    solve_batched_tune(best["hop_blocks_per_cu"], best["vec_blocks_per_cu"], best["chunk"],
+                       best["slab"])
+    return {k: best[k] for k in ("hop_blocks_per_cu", "vec_blocks_per_cu", "chunk", "slab")}

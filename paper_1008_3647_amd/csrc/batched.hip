@@ -16,14 +16,16 @@
 #include <cstring>
 
 #include "hop_common.h"
+#include "hop_stream.h"
 #include "ops.h"
+#include "split_line.h"
 
 namespace ufg {
 namespace {
 using namespace hopc;
 
 struct BSeg {
-  int nx, ntau, V, spw;
+  int nx, ntau, V;
   long long n;    // elements of one vector of this system
   long long off;  // offset of the segment in the concatenated inner vectors
   const double2* b64;
@@ -45,6 +47,7 @@ struct BVec {
 int g_hop_blocks_per_cu = 4;
 int g_vec_blocks_per_cu = 8;
 long long g_chunk = 4096;
+int g_bop_slab = 2;
 
 template <typename R>
 __device__ __forceinline__ const R* fld(const BSeg& g);
@@ -82,7 +85,7 @@ __device__ void bsum4b(double a0, double a1, double a2, double a3, double* out, 
   __syncthreads();
   if (threadIdx.x == 0) {
     double s0 = 0, s1 = 0, s2 = 0, s3 = 0;
-    for (int w = 0; w < (int)(blockDim.x >> 6); ++w) {
+    for (int w = 0; w < (int)((blockDim.x + 63) >> 6); ++w) {
       s0 += scratch[w * 4 + 0];
       s1 += scratch[w * 4 + 1];
       s2 += scratch[w * 4 + 2];
@@ -96,119 +99,106 @@ __device__ void bsum4b(double a0, double a1, double a2, double a3, double* out, 
   __syncthreads();
 }
 
-// Transform of one slice held as z-lines (thread (y,x) of its slice); threads
-// with act == false take part in the barriers only.
+// ---------------------------------------------------------------------------
+// Batched operator. One launch per class of segments that share Nx and T (the
+// same Nx and tau): the class's transform coefficients travel as kernel
+// arguments. A workgroup holds SG sub-groups of Nx^2 threads (one z-line per
+// thread); a work item is SG consecutive slabs of `slab` time slices of one
+// segment, and each sub-group walks its slab like the single-lattice streaming
+// kernel (M upwards, M^T downwards): the slice loaded for the identity term of
+// one output is the source of the next, so only one halo slice per slab is
+// loaded twice. Nx in {8, 12, 16} use the reflection-symmetry block form of T;
+// the other Nx apply T as a dense Nx x Nx matrix.
+
+__host__ __device__ constexpr int bop_groups(int nx) {
+  return (nx * nx >= 576) ? 1 : 576 / (nx * nx);
+}
+__host__ __device__ constexpr int bop_threads(int nx) {
+  return ((bop_groups(nx) * nx * nx + 63) / 64) * 64;
+}
+__host__ __device__ constexpr bool bop_split(int nx) { return nx == 8 || nx == 12 || nx == 16; }
+
+template <typename R, int NX, bool SPLIT>
+struct BCoef;
 template <typename R, int NX>
-__device__ __forceinline__ void guarded_transform(const R* __restrict__ mat, C2<R>* my, int l,
-                                                  bool act, C2<R> (&v)[NX], C2<R> (&w)[NX]) {
+struct BCoef<R, NX, true> {
+  SplitCoef<R, NX> s;
+};
+template <typename R, int NX>
+struct BCoef<R, NX, false> {
+  R t[NX * NX];
+};
+
+template <typename R, int NX, bool SPLIT>
+__device__ __forceinline__ void bline(const BCoef<R, NX, SPLIT>& c, C2<R> (&v)[NX]) {
+  if constexpr (SPLIT) {
+    splitk::split_line<R, NX>(c.s, v);
+  } else {
+    C2<R> w[NX];
+    line_transform<R, NX>(c.t, v, w);
+#pragma unroll
+    for (int i = 0; i < NX; ++i) v[i] = w[i];
+  }
+}
+
+// T^3 of one slice per sub-group (z-lines in v, thread l of the sub-group);
+// sub-groups with act == false take part in the barriers only. A thread's
+// last read and next first write touch only its own z-line, so the buffer
+// needs no barrier before its reuse by the next slice.
+template <typename R, int NX, bool SPLIT>
+__device__ __forceinline__ void bslice_T3(const BCoef<R, NX, SPLIT>& c, C2<R>* my, int l,
+                                          bool act, C2<R> (&v)[NX]) {
   constexpr int LD = NX + 1;
   const int y = l / NX, x = l - (l / NX) * NX;
   if (act) {
-    line_transform<R, NX>(mat, v, w);
+    bline<R, NX, SPLIT>(c, v);  // along z
 #pragma unroll
-    for (int z = 0; z < NX; ++z) my[(z * NX + y) * LD + x] = w[z];
+    for (int z = 0; z < NX; ++z) my[(z * NX + y) * LD + x] = v[z];
   }
   __syncthreads();
-  if (act) {
+  C2<R> w[NX];
+  if (act) {  // along y: thread (z, x)
     const int z = l / NX, xx = l - (l / NX) * NX;
 #pragma unroll
-    for (int yy = 0; yy < NX; ++yy) v[yy] = my[(z * NX + yy) * LD + xx];
-    line_transform<R, NX>(mat, v, w);
+    for (int yy = 0; yy < NX; ++yy) w[yy] = my[(z * NX + yy) * LD + xx];
+    bline<R, NX, SPLIT>(c, w);
 #pragma unroll
     for (int yy = 0; yy < NX; ++yy) my[(z * NX + yy) * LD + xx] = w[yy];
   }
   __syncthreads();
-  if (act) {
+  if (act) {  // along x: thread (z, y)
     const int z = l / NX, yy = l - (l / NX) * NX;
     C2<R>* row = my + (z * NX + yy) * LD;
 #pragma unroll
-    for (int xx = 0; xx < NX; ++xx) v[xx] = row[xx];
-    line_transform<R, NX>(mat, v, w);
+    for (int xx = 0; xx < NX; ++xx) w[xx] = row[xx];
+    bline<R, NX, SPLIT>(c, w);
 #pragma unroll
     for (int xx = 0; xx < NX; ++xx) row[xx] = w[xx];
   }
   __syncthreads();
   if (act) {
 #pragma unroll
-    for (int z = 0; z < NX; ++z) w[z] = my[(z * NX + y) * LD + x];
+    for (int z = 0; z < NX; ++z) v[z] = my[(z * NX + y) * LD + x];
   }
 }
 
-// One operator work item: y_t = x_t + sgn T^3(...) for the item's slices.
-// RES: y = b - (M x) on the outer FP64 vectors of the segment.
-template <typename R, int NX, int DIR, bool RES>
-__device__ void hop_item(const BSeg& g, int t0, const C2<R>* src, C2<R>* dst, const C2<R>* aux,
-                         int red_mode, const C2<R>* redw, double* part_out, C2<R>* lds,
-                         double* scratch) {
-  constexpr int P = NX * NX, V = NX * NX * NX, SPW = (256 / P) > 0 ? 256 / P : 1;
-  constexpr int SL = NX * NX * (NX + 1);
+// y_t = x_t + s T^3(...) over the items [i0, i1) of one class.
+// RES: y = b - M x on the outer FP64 vectors of the segment (R = double).
+// red_mode 1: <w, y>; 2: <y, w>, |y|^2, |w|^2 (per item partials).
+template <typename R, int NX, int DIR, bool RES, bool SPLIT>
+__global__ void __launch_bounds__(bop_threads(NX))
+    bop_kernel(BCoef<R, NX, SPLIT> c, const BSeg* __restrict__ segs,
+               const BHop* __restrict__ items, int i0, int i1, const C2<R>* src_cat,
+               C2<R>* dst_cat, int red_mode, const C2<R>* redw_cat, double* part,
+               const int* gate, int slab) {
+  constexpr int P = NX * NX, V = NX * NX * NX, SL = NX * NX * (NX + 1), SG = bop_groups(NX);
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  __shared__ double scratch[4 * (bop_threads(NX) / 64)];
   const int tid = threadIdx.x;
   const int sub = tid / P, l = tid - (tid / P) * P;
-  const bool inb = sub < SPW;
-  const int t = t0 + (inb ? sub : 0);
-  const bool valid = inb && t < g.ntau;
-  int ts = t + (DIR < 0 ? -1 : 1);
-  if (ts < 0) ts += g.ntau;
-  if (ts >= g.ntau) ts -= g.ntau;
-  const R* f = fld<R>(g);
-  C2<R> v[NX], w[NX];
-  if (valid) {
-#pragma unroll
-    for (int z = 0; z < NX; ++z) v[z] = src[(long long)ts * V + z * P + l];
-    if (DIR < 0) {
-#pragma unroll
-      for (int z = 0; z < NX; ++z) {
-        const R fz = f[(long long)ts * V + z * P + l];
-        v[z].x *= fz;
-        v[z].y *= fz;
-      }
-    }
-  }
-  guarded_transform<R, NX>(tmat<R>(g), lds + (inb ? sub : 0) * SL, l, valid, v, w);
-  double a0 = 0, a1 = 0, a2 = 0, a3 = 0;
-  if (valid) {
-    R sgn;
-    if (DIR < 0)
-      sgn = (ts == g.ntau - 1) ? R(1) : R(-1);
-    else
-      sgn = (t == g.ntau - 1) ? R(1) : R(-1);
-#pragma unroll
-    for (int z = 0; z < NX; ++z) {
-      const long long idx = (long long)t * V + z * P + l;
-      R c = sgn;
-      if (DIR > 0) c *= f[idx];
-      const C2<R> xi = src[idx];
-      C2<R> out = mk<R>(xi.x + c * w[z].x, xi.y + c * w[z].y);
-      if (RES) {
-        const C2<R> bb = aux[idx];
-        out = mk<R>(bb.x - out.x, bb.y - out.y);
-      }
-      dst[idx] = out;
-      if (red_mode == 1) {
-        const C2<R> q = redw[idx];
-        a0 += double(q.x) * out.x + double(q.y) * out.y;
-        a1 += double(q.x) * out.y - double(q.y) * out.x;
-      } else if (red_mode == 2) {
-        const C2<R> q = redw[idx];
-        a0 += double(out.x) * q.x + double(out.y) * q.y;
-        a1 += double(out.x) * q.y - double(out.y) * q.x;
-        a2 += double(out.x) * out.x + double(out.y) * out.y;
-        a3 += double(q.x) * q.x + double(q.y) * q.y;
-      }
-    }
-  }
-  if (red_mode) bsum4b(a0, a1, a2, a3, part_out, scratch);
-}
-
-template <typename R, int DIR, bool RES>
-__global__ void __launch_bounds__(256)
-    bhop_kernel(const BSeg* __restrict__ segs, const BHop* __restrict__ items, int nitems,
-                const C2<R>* src_cat, C2<R>* dst_cat, int red_mode, const C2<R>* redw_cat,
-                double* part, const int* gate) {
-  extern __shared__ __align__(16) unsigned char smem_raw[];
-  C2<R>* lds = reinterpret_cast<C2<R>*>(smem_raw);
-  __shared__ double scratch[16];
-  for (int it = blockIdx.x; it < nitems; it += gridDim.x) {
+  const bool member = sub < SG;
+  C2<R>* my = reinterpret_cast<C2<R>*>(smem_raw) + (member ? sub : 0) * SL;
+  for (int it = i0 + blockIdx.x; it < i1; it += gridDim.x) {
     const BHop h = items[it];
     if (gate && gate[h.seg] == 0) continue;
     const BSeg g = segs[h.seg];
@@ -224,18 +214,91 @@ __global__ void __launch_bounds__(256)
       dst = dst_cat + g.off;
     }
     const C2<R>* redw = redw_cat ? redw_cat + g.off : nullptr;
-    double* po = part + (long long)it * 4;
-    switch (g.nx) {
-#define BH(NXV)                                                                              \
-  case NXV:                                                                                  \
-    hop_item<R, NXV, DIR, RES>(g, h.t0, src, dst, aux, red_mode, redw, po, lds, scratch);    \
-    break;
-      BH(2) BH(4) BH(6) BH(8) BH(10) BH(12) BH(14) BH(16)
-#undef BH
-      default:
-        break;
+    const R* f = fld<R>(g);
+    const int ntau = g.ntau;
+    const int ts0 = h.t0 + (member ? sub : SG) * slab;
+    const int ts1 = min(ts0 + slab, ntau);
+    const int count = (member && ts1 > ts0) ? ts1 - ts0 : 0;
+    const bool live = count > 0;
+    const int tfirst = (DIR < 0) ? ts0 : ts1 - 1;
+    const int step = (DIR < 0) ? 1 : -1;
+    // halo slice feeding the first output
+    const int th = (DIR < 0) ? ((ts0 == 0) ? ntau - 1 : ts0 - 1) : ((ts1 == ntau) ? 0 : ts1);
+    C2<R> W[NX], X[NX];
+    if (live) {
+#pragma unroll
+      for (int z = 0; z < NX; ++z) W[z] = src[(long long)th * V + z * P + l];
+      if (DIR < 0) {
+#pragma unroll
+        for (int z = 0; z < NX; ++z) {
+          const R fz = f[(long long)th * V + z * P + l];
+          W[z].x *= fz;
+          W[z].y *= fz;
+        }
+      }
     }
-    __syncthreads();  // LDS is reused by the next item
+    bslice_T3<R, NX, SPLIT>(c, my, l, live, W);
+    double a0 = 0, a1 = 0, a2 = 0, a3 = 0;
+    for (int k = 0; k < slab; ++k) {
+      const bool act = k < count;
+      const int t = tfirst + k * step;
+      if (act) {
+        R sgn;
+        if (DIR < 0)
+          sgn = (t == 0) ? R(1) : R(-1);
+        else
+          sgn = (t == ntau - 1) ? R(1) : R(-1);
+        const long long o = (long long)t * V + l;
+#pragma unroll
+        for (int z = 0; z < NX; ++z) X[z] = src[o + z * P];
+        R F[NX];
+#pragma unroll
+        for (int z = 0; z < NX; ++z) F[z] = (DIR > 0) ? sgn * f[o + z * P] : sgn;
+        C2<R> B[RES ? NX : 1], Q[NX];
+        if (RES) {
+#pragma unroll
+          for (int z = 0; z < NX; ++z) B[RES ? z : 0] = aux[o + z * P];
+        }
+        if (red_mode) {
+#pragma unroll
+          for (int z = 0; z < NX; ++z) Q[z] = redw[o + z * P];
+        }
+#pragma unroll
+        for (int z = 0; z < NX; ++z) {
+          C2<R> out = mk<R>(X[z].x + F[z] * W[z].x, X[z].y + F[z] * W[z].y);
+          if (RES) {
+            const C2<R> bb = B[RES ? z : 0];
+            out = mk<R>(bb.x - out.x, bb.y - out.y);
+          }
+          dst[o + z * P] = out;
+          if (red_mode == 1) {
+            a0 += double(Q[z].x) * out.x + double(Q[z].y) * out.y;
+            a1 += double(Q[z].x) * out.y - double(Q[z].y) * out.x;
+          } else if (red_mode == 2) {
+            a0 += double(out.x) * Q[z].x + double(out.y) * Q[z].y;
+            a1 += double(out.x) * Q[z].y - double(out.y) * Q[z].x;
+            a2 += double(out.x) * out.x + double(out.y) * out.y;
+            a3 += double(Q[z].x) * Q[z].x + double(Q[z].y) * Q[z].y;
+          }
+        }
+      }
+      if (k + 1 < slab) {  // transform source slice t for the next output
+        const bool tr = act && k + 1 < count;
+        if (tr) {
+#pragma unroll
+          for (int z = 0; z < NX; ++z) {
+            W[z] = X[z];
+            if (DIR < 0) {
+              const R fz = f[(long long)t * V + z * P + l];
+              W[z].x *= fz;
+              W[z].y *= fz;
+            }
+          }
+        }
+        bslice_T3<R, NX, SPLIT>(c, my, l, tr, W);
+      }
+    }
+    if (red_mode) bsum4b(a0, a1, a2, a3, part + (long long)it * 4, scratch);
   }
 }
 
@@ -380,6 +443,61 @@ struct Dev {
   }
 };
 
+// Operator class: segments with the same Nx and T share one launch.
+struct BClass {
+  int nx = 0;
+  std::vector<double> T, coef;  // coef: block form (Nx in {8, 12, 16}) or T
+  int i0 = 0, i1 = 0;           // item range in the operator table
+};
+
+template <typename R, int NX, int DIR, bool RES>
+int launch_bop_nx(const BClass& k, int ncu, hipStream_t cs, bool prepare, const BSeg* dseg,
+                  const BHop* dhop, const C2<R>* src, C2<R>* dst, int red_mode,
+                  const C2<R>* redw, double* part, const int* gate, int slab) {
+  constexpr bool SPLIT = bop_split(NX);
+  constexpr int SG = bop_groups(NX);
+  const size_t lds = size_t(SG) * NX * NX * (NX + 1) * sizeof(C2<R>);
+  const void* fn = (const void*)bop_kernel<R, NX, DIR, RES, SPLIT>;
+  if (prepare) {  // before any capture
+    UFG_HIP(hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+    return UFG_OK;
+  }
+  const int n = k.i1 - k.i0;
+  if (n <= 0) return UFG_OK;
+  BCoef<R, NX, SPLIT> c;
+  if constexpr (SPLIT) {
+    int j = 0;
+    for (auto& v : c.s.es) v = R(k.coef[j++]);
+    for (auto& v : c.s.ea) v = R(k.coef[j++]);
+    for (auto& v : c.s.os) v = R(k.coef[j++]);
+    for (auto& v : c.s.oa) v = R(k.coef[j++]);
+  } else {
+    for (int j = 0; j < NX * NX; ++j) c.t[j] = R(k.coef[j]);
+  }
+  const dim3 grid(std::max(1, std::min(n, ncu * g_hop_blocks_per_cu)));
+  hipLaunchKernelGGL((bop_kernel<R, NX, DIR, RES, SPLIT>), grid, dim3(bop_threads(NX)), lds, cs,
+                     c, dseg, dhop, k.i0, k.i1, src, dst, red_mode, redw, part, gate, slab);
+  UFG_HIP(hipGetLastError());
+  return UFG_OK;
+}
+
+template <typename R, int DIR, bool RES>
+int launch_bop(const BClass& k, int ncu, hipStream_t cs, bool prepare, const BSeg* dseg,
+               const BHop* dhop, const C2<R>* src, C2<R>* dst, int red_mode, const C2<R>* redw,
+               double* part, const int* gate, int slab) {
+  switch (k.nx) {
+#define BOP(NXV)                                                                            \
+  case NXV:                                                                                 \
+    return launch_bop_nx<R, NXV, DIR, RES>(k, ncu, cs, prepare, dseg, dhop, src, dst,       \
+                                           red_mode, redw, part, gate, slab);
+    BOP(2) BOP(4) BOP(6) BOP(8) BOP(10) BOP(12) BOP(14) BOP(16)
+#undef BOP
+    default:
+      set_error("solve_batched: unsupported nx");
+      return UFG_EINVAL;
+  }
+}
+
 struct Graph {
   hipGraph_t g = nullptr;
   hipGraphExec_t e = nullptr;
@@ -395,19 +513,27 @@ int run_batched(std::vector<Lattice*>& Ls, const void* const* bu, void* const* x
   const int nprob = (int)Ls.size();
   int ncu = 256;
   (void)hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, Ls[0]->device);
-  // segments and work tables
+  // segments, their operator classes (same Nx and T) and the work tables
   std::vector<BSeg> segs;
-  std::vector<int> seg_prob;
+  std::vector<int> seg_prob, seg_cls;
+  std::vector<BClass> cls;
   long long total = 0;
-  size_t lds_bytes = 0;
   for (int i = 0; i < nprob; ++i) {
     Lattice& L = *Ls[i];
+    int c = 0;
+    while (c < (int)cls.size() && !(cls[c].nx == L.nx && cls[c].T == L.T_host)) ++c;
+    if (c == (int)cls.size()) {
+      BClass k;
+      k.nx = L.nx;
+      k.T = L.T_host;
+      k.coef = bop_split(L.nx) ? L.split_host : L.T_host;
+      cls.push_back(k);
+    }
     for (int r = 0; r < nrhs[i]; ++r) {
       BSeg g{};
       g.nx = L.nx;
       g.ntau = L.ntau;
       g.V = L.V;
-      g.spw = std::max(1, 256 / (L.nx * L.nx));
       g.n = L.N;
       g.off = total;
       g.f32 = L.f32.b;
@@ -417,24 +543,35 @@ int run_batched(std::vector<Lattice*>& Ls, const void* const* bu, void* const* x
       total += L.N;
       segs.push_back(g);
       seg_prob.push_back(i);
-      lds_bytes = std::max(lds_bytes, size_t(g.spw) * L.nx * L.nx * (L.nx + 1) * sizeof(double2));
+      seg_cls.push_back(c);
     }
   }
   const int S = (int)segs.size();
+  const int C = (int)cls.size();
+  const int slab = g_bop_slab;
   // Work tables over the segments marked in `use` (the others get no items):
-  // operator items (segment, slice group) and vector items (segment, chunk),
-  // with each segment's first item and item count (its partial sums).
+  // operator items (segment, first slice of SG slabs), grouped by class, and
+  // vector items (segment, chunk), with each segment's first item and item
+  // count (its partial sums).
   std::vector<BHop> hops;
   std::vector<BVec> vecs;
   std::vector<int> htab(4 * S);
   auto make_tables = [&](const std::vector<char>& use) {
     hops.clear();
     vecs.clear();
+    for (int c = 0; c < C; ++c) {
+      cls[c].i0 = (int)hops.size();
+      const int span = bop_groups(cls[c].nx) * slab;
+      for (int s = 0; s < S; ++s) {
+        if (seg_cls[s] != c) continue;
+        htab[s] = (int)hops.size();
+        if (use[s])
+          for (int t0 = 0; t0 < segs[s].ntau; t0 += span) hops.push_back(BHop{s, t0});
+        htab[S + s] = (int)hops.size() - htab[s];
+      }
+      cls[c].i1 = (int)hops.size();
+    }
     for (int s = 0; s < S; ++s) {
-      htab[s] = (int)hops.size();
-      if (use[s])
-        for (int t0 = 0; t0 < segs[s].ntau; t0 += segs[s].spw) hops.push_back(BHop{s, t0});
-      htab[S + s] = (int)hops.size() - htab[s];
       htab[2 * S + s] = (int)vecs.size();
       if (use[s])
         for (long long lo = 0; lo < segs[s].n; lo += g_chunk)
@@ -466,8 +603,8 @@ int run_batched(std::vector<Lattice*>& Ls, const void* const* bu, void* const* x
     }
   } guard{cs};
   int* tab = reinterpret_cast<int*>(dtab.p);
-  int nh = 0, nv = 0;
-  dim3 hgrid(1), vgrid(1);
+  int nv = 0;
+  dim3 vgrid(1);
   // upload the tables (the device buffers were sized for all segments)
   auto upload_tables = [&]() -> int {
     UFG_HIP(hipMemcpyAsync(tab, htab.data(), sizeof(int) * 4 * S, hipMemcpyHostToDevice, cs));
@@ -477,9 +614,7 @@ int run_batched(std::vector<Lattice*>& Ls, const void* const* bu, void* const* x
     if (!vecs.empty())
       UFG_HIP(hipMemcpyAsync(dvecs.p, vecs.data(), sizeof(BVec) * vecs.size(),
                              hipMemcpyHostToDevice, cs));
-    nh = (int)hops.size();
     nv = (int)vecs.size();
-    hgrid = dim3(std::max(1, std::min(nh, ncu * g_hop_blocks_per_cu)));
     vgrid = dim3(std::max(1, std::min(nv, ncu * g_vec_blocks_per_cu)));
     return UFG_OK;
   };
@@ -512,16 +647,17 @@ int run_batched(std::vector<Lattice*>& Ls, const void* const* bu, void* const* x
   const BSeg* dseg = reinterpret_cast<const BSeg*>(dsegs.p);
   const BHop* dhop = reinterpret_cast<const BHop*>(dhops.p);
   const BVec* dvv = reinterpret_cast<const BVec*>(dvecs.p);
-  const size_t lds = std::max<size_t>(lds_bytes, 64);
-  // attributes are set before any capture
-  UFG_HIP(hipFuncSetAttribute((const void*)bhop_kernel<RI, -1, false>,
-                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
-  UFG_HIP(hipFuncSetAttribute((const void*)bhop_kernel<RI, 1, false>,
-                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
-  UFG_HIP(hipFuncSetAttribute((const void*)bhop_kernel<double, -1, true>,
-                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
-  UFG_HIP(hipFuncSetAttribute((const void*)bhop_kernel<double, 1, true>,
-                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+  // dynamic LDS limits of every operator instance, set before any capture
+  for (const BClass& k : cls) {
+    UFG_TRY((launch_bop<RI, -1, false>(k, ncu, cs, true, nullptr, nullptr, nullptr, nullptr, 0,
+                                       nullptr, nullptr, nullptr, slab)));
+    UFG_TRY((launch_bop<RI, 1, false>(k, ncu, cs, true, nullptr, nullptr, nullptr, nullptr, 0,
+                                      nullptr, nullptr, nullptr, slab)));
+    UFG_TRY((launch_bop<double, -1, true>(k, ncu, cs, true, nullptr, nullptr, nullptr, nullptr,
+                                          0, nullptr, nullptr, nullptr, slab)));
+    UFG_TRY((launch_bop<double, 1, true>(k, ncu, cs, true, nullptr, nullptr, nullptr, nullptr, 0,
+                                         nullptr, nullptr, nullptr, slab)));
+  }
   const int check = o.check_every > 0 ? o.check_every : 10;
   std::vector<RhsState> hst(S);
   std::vector<int> hflags(3 * S);
@@ -547,23 +683,27 @@ int run_batched(std::vector<Lattice*>& Ls, const void* const* bu, void* const* x
       segs[s].r64 = reinterpret_cast<double2*>(dr64.p) + segs[s].off;
     }
     UFG_HIP(hipMemcpyAsync(dsegs.p, segs.data(), sizeof(BSeg) * S, hipMemcpyHostToDevice, cs));
-    auto hop = [&](int red_mode, const C2<RI>* src, C2<RI>* dst, const C2<RI>* redw) {
-      if (dir < 0)
-        hipLaunchKernelGGL((bhop_kernel<RI, -1, false>), hgrid, dim3(256), lds, cs, dseg, dhop, nh,
-                           src, dst, red_mode, redw, hpart, K.active);
-      else
-        hipLaunchKernelGGL((bhop_kernel<RI, 1, false>), hgrid, dim3(256), lds, cs, dseg, dhop, nh,
-                           src, dst, red_mode, redw, hpart, K.active);
+    auto hop = [&](int red_mode, const C2<RI>* src, C2<RI>* dst, const C2<RI>* redw) -> int {
+      for (const BClass& k : cls) {
+        if (dir < 0)
+          UFG_TRY((launch_bop<RI, -1, false>(k, ncu, cs, false, dseg, dhop, src, dst, red_mode,
+                                             redw, hpart, K.active, slab)));
+        else
+          UFG_TRY((launch_bop<RI, 1, false>(k, ncu, cs, false, dseg, dhop, src, dst, red_mode,
+                                            redw, hpart, K.active, slab)));
+      }
+      return UFG_OK;
     };
-    auto residual = [&](const int* gate) {
-      if (dir < 0)
-        hipLaunchKernelGGL((bhop_kernel<double, -1, true>), hgrid, dim3(256), lds, cs, dseg, dhop,
-                           nh, (const double2*)nullptr, (double2*)nullptr, 0,
-                           (const double2*)nullptr, hpart, gate);
-      else
-        hipLaunchKernelGGL((bhop_kernel<double, 1, true>), hgrid, dim3(256), lds, cs, dseg, dhop,
-                           nh, (const double2*)nullptr, (double2*)nullptr, 0,
-                           (const double2*)nullptr, hpart, gate);
+    auto residual = [&](const int* gate) -> int {
+      for (const BClass& k : cls) {
+        if (dir < 0)
+          UFG_TRY((launch_bop<double, -1, true>(k, ncu, cs, false, dseg, dhop, nullptr, nullptr,
+                                                0, nullptr, hpart, gate, slab)));
+        else
+          UFG_TRY((launch_bop<double, 1, true>(k, ncu, cs, false, dseg, dhop, nullptr, nullptr, 0,
+                                               nullptr, hpart, gate, slab)));
+      }
+      return UFG_OK;
     };
     auto vop = [&](int op, const int* gate) {
       hipLaunchKernelGGL((bvec_kernel<RI>), vgrid, dim3(256), 0, cs, op, dseg, dvv, nv, VA, K.st,
@@ -578,10 +718,10 @@ int run_batched(std::vector<Lattice*>& Ls, const void* const* bu, void* const* x
     auto body = [&]() -> int {
       for (int k = 0; k < check; ++k) {
         vop(0, K.active);
-        hop(1, vp, vv, vrh);
+        UFG_TRY(hop(1, vp, vv, vrh));
         UFG_TRY(k_finalize_seg(cs, FIN_ALPHA, hpart, hf, hc, K.active, K));
         vop(1, K.active);
-        hop(2, vs, vt, vs);
+        UFG_TRY(hop(2, vs, vt, vs));
         UFG_TRY(k_finalize_seg(cs, FIN_OMEGA, hpart, hf, hc, K.active, K));
         vop(2, K.active);
         UFG_TRY(k_finalize_seg(cs, FIN_RHO, vpart, vf, vc, K.active, K));
@@ -623,7 +763,7 @@ int run_batched(std::vector<Lattice*>& Ls, const void* const* bu, void* const* x
       }
       if (any_update) {  // reliable update: x64 += x_in, r64 = b - A x64, r = r64
         vop(4, K.update);
-        residual(K.update);
+        UFG_TRY(residual(K.update));
         vop(5, K.update);
         UFG_TRY(k_finalize_seg(cs, FIN_UPDATE, vpart, vf, vc, K.update, K));
       }
@@ -664,7 +804,7 @@ int run_batched(std::vector<Lattice*>& Ls, const void* const* bu, void* const* x
       else if (!hst[s].conv) status[i] = std::max(status[i], (int)UFG_NOT_CONVERGED);
     }
     // true residuals of this step, FP64
-    residual(nullptr);
+    UFG_TRY(residual(nullptr));
     vop(7, nullptr);
     UFG_TRY(k_finalize_seg(cs, FIN_INIT_B, vpart, vf, vc, nullptr, K));
     vop(8, nullptr);
@@ -728,13 +868,15 @@ int solve_batched_impl(const ufg_lattice* Ls, int nprob, const void* const* b, v
   return rc;
 }
 
-int batched_tune(int hop_blocks_per_cu, int vec_blocks_per_cu, long long chunk) {
+int batched_tune(int hop_blocks_per_cu, int vec_blocks_per_cu, long long chunk, int slab) {
   UFG_CHECK(hop_blocks_per_cu >= 0 && hop_blocks_per_cu <= 64, "bad hop blocks per CU");
   UFG_CHECK(vec_blocks_per_cu >= 0 && vec_blocks_per_cu <= 64, "bad vector blocks per CU");
   UFG_CHECK(chunk == 0 || (chunk >= 256 && chunk <= (1 << 22)), "bad chunk");
+  UFG_CHECK(slab >= 0 && slab <= 64, "bad slab");
   g_hop_blocks_per_cu = hop_blocks_per_cu ? hop_blocks_per_cu : 4;
   g_vec_blocks_per_cu = vec_blocks_per_cu ? vec_blocks_per_cu : 8;
   g_chunk = chunk ? chunk : 4096;
+  g_bop_slab = slab ? slab : 2;
   return UFG_OK;
 }
 
