@@ -2,14 +2,15 @@
 //
 // All systems (problem, right-hand side) of the batch are "segments" of one
 // set of concatenated Krylov vectors, each with its own device-resident
-// scalars and flags. Every phase of an iteration is ONE launch over the whole
-// batch: a persistent grid (compute units x occupancy) walks a work table of
-// (segment, slice group) items for the operator and (segment, chunk) items for
-// the vector updates, so small lattices share the GPU instead of each paying
-// its own launches. The iteration body of one check interval is captured once
-// in a hipGraph and replayed; between replays the host reads the flags and
-// runs the reliable updates (FP64 residual of the outer complex128 vectors)
-// and restarts for the segments that asked for them.
+// scalars and flags. Every phase of an iteration covers the whole batch with
+// persistent grids (compute units x occupancy) that walk work tables: one
+// operator launch per class of segments sharing Nx and T, over (segment, slab
+// group) items, with BiCGStab's p- and s-updates fused into it, and one vector
+// launch over (segment, chunk) items, so small lattices share the GPU instead
+// of each paying its own launches. The iteration body of one check interval is
+// captured once in a hipGraph and replayed; between replays the host reads the
+// flags and runs the reliable updates (FP64 residual of the outer complex128
+// vectors) and restarts for the segments that asked for them.
 #include <algorithm>
 #include <chrono>
 #include <cmath>
@@ -182,15 +183,81 @@ __device__ __forceinline__ void bslice_T3(const BCoef<R, NX, SPLIT>& c, C2<R>* m
   }
 }
 
+__device__ __forceinline__ double2 cmul(double2 a, double2 b) {
+  return double2{a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x};
+}
+__device__ __forceinline__ double2 cdiv(double2 a, double2 b) {
+  const double d = b.x * b.x + b.y * b.y;
+  return double2{(a.x * b.x + a.y * b.y) / d, (a.y * b.x - a.x * b.y) / d};
+}
+
+// Fused BiCGStab sources of the batched operator (per segment, like the
+// single-lattice streaming kernel): SRC 1 builds p = r + beta (p - omega v)
+// while loading and stores it to pout for the sub-group's own slices; SRC 2
+// builds s = r - alpha v (not stored). The scalars come from the segment's
+// device state. The vectors are the concatenated inner vectors.
+template <typename R>
+struct BSrc {
+  const C2<R>* r;
+  const C2<R>* p;
+  const C2<R>* v;
+  C2<R>* pout;
+  const RhsState* st;
+};
+
+template <typename R>
+struct BScal {
+  R br, bi, wr, wi, ar, ai;
+};
+
+template <typename R, int SRC>
+__device__ __forceinline__ BScal<R> bsrc_scalars(const BSrc<R>& b, int seg) {
+  BScal<R> q{};
+  if (SRC == 0) return q;
+  const RhsState s = b.st[seg];
+  if (SRC == 1) {  // beta = (rho / rho_old)(alpha / omega)
+    const double2 beta = cmul(cdiv(s.rho, s.rho_old), cdiv(s.alpha, s.omega));
+    q.br = R(beta.x);
+    q.bi = R(beta.y);
+    q.wr = R(s.omega.x);
+    q.wi = R(s.omega.y);
+  } else {
+    q.ar = R(s.alpha.x);
+    q.ai = R(s.alpha.y);
+  }
+  return q;
+}
+
+// z-line of the source at element offset o (segment offset included)
+template <typename R, int NX, int SRC>
+__device__ __forceinline__ void bsource(const C2<R>* src, const BSrc<R>& b, const BScal<R>& q,
+                                        long long o, C2<R> (&X)[NX]) {
+  constexpr int P = NX * NX;
+#pragma unroll
+  for (int z = 0; z < NX; ++z) {
+    const long long i = o + z * P;
+    if (SRC == 0) {
+      X[z] = src[i];
+    } else if (SRC == 1) {
+      const C2<R> rv = b.r[i], pv = b.p[i], vv = b.v[i];
+      const R dx = pv.x - (q.wr * vv.x - q.wi * vv.y);
+      const R dy = pv.y - (q.wr * vv.y + q.wi * vv.x);
+      X[z] = mk<R>(rv.x + q.br * dx - q.bi * dy, rv.y + q.br * dy + q.bi * dx);
+    } else {
+      const C2<R> rv = b.r[i], vv = b.v[i];
+      X[z] = mk<R>(rv.x - (q.ar * vv.x - q.ai * vv.y), rv.y - (q.ar * vv.y + q.ai * vv.x));
+    }
+  }
+}
+
 // y_t = x_t + s T^3(...) over the items [i0, i1) of one class.
-// RES: y = b - M x on the outer FP64 vectors of the segment (R = double).
-// red_mode 1: <w, y>; 2: <y, w>, |y|^2, |w|^2 (per item partials).
-template <typename R, int NX, int DIR, bool RES, bool SPLIT>
+// RES (SRC 0, R = double): y = b - M x on the outer FP64 vectors of the segment.
+// red_mode 1: <w, y>; 3: <y, source>, |y|^2, |source|^2 (per item partials).
+template <typename R, int NX, int DIR, bool RES, bool SPLIT, int SRC>
 __global__ void __launch_bounds__(bop_threads(NX))
     bop_kernel(BCoef<R, NX, SPLIT> c, const BSeg* __restrict__ segs,
-               const BHop* __restrict__ items, int i0, int i1, const C2<R>* src_cat,
-               C2<R>* dst_cat, int red_mode, const C2<R>* redw_cat, double* part,
-               const int* gate, int slab) {
+               const BHop* __restrict__ items, int i0, int i1, BSrc<R> bs, C2<R>* dst_cat,
+               int red_mode, const C2<R>* redw_cat, double* part, const int* gate, int slab) {
   constexpr int P = NX * NX, V = NX * NX * NX, SL = NX * NX * (NX + 1), SG = bop_groups(NX);
   extern __shared__ __align__(16) unsigned char smem_raw[];
   __shared__ double scratch[4 * (bop_threads(NX) / 64)];
@@ -202,18 +269,20 @@ __global__ void __launch_bounds__(bop_threads(NX))
     const BHop h = items[it];
     if (gate && gate[h.seg] == 0) continue;
     const BSeg g = segs[h.seg];
-    const C2<R>* src;
+    const C2<R>* src = nullptr;  // SRC 0
     C2<R>* dst;
     const C2<R>* aux = nullptr;
+    long long so = 0;  // offset of the segment in the inner vectors
     if (RES) {
       src = reinterpret_cast<const C2<R>*>(g.x64);
       dst = reinterpret_cast<C2<R>*>(g.r64);
       aux = reinterpret_cast<const C2<R>*>(g.b64);
     } else {
-      src = src_cat + g.off;
-      dst = dst_cat + g.off;
+      so = g.off;
+      dst = dst_cat + so;
     }
-    const C2<R>* redw = redw_cat ? redw_cat + g.off : nullptr;
+    const BScal<R> q = bsrc_scalars<R, SRC>(bs, h.seg);
+    const C2<R>* redw = redw_cat ? redw_cat + so : nullptr;
     const R* f = fld<R>(g);
     const int ntau = g.ntau;
     const int ts0 = h.t0 + (member ? sub : SG) * slab;
@@ -226,8 +295,7 @@ __global__ void __launch_bounds__(bop_threads(NX))
     const int th = (DIR < 0) ? ((ts0 == 0) ? ntau - 1 : ts0 - 1) : ((ts1 == ntau) ? 0 : ts1);
     C2<R> W[NX], X[NX];
     if (live) {
-#pragma unroll
-      for (int z = 0; z < NX; ++z) W[z] = src[(long long)th * V + z * P + l];
+      bsource<R, NX, SRC>(src, bs, q, so + (long long)th * V + l, W);
       if (DIR < 0) {
 #pragma unroll
         for (int z = 0; z < NX; ++z) {
@@ -249,8 +317,11 @@ __global__ void __launch_bounds__(bop_threads(NX))
         else
           sgn = (t == ntau - 1) ? R(1) : R(-1);
         const long long o = (long long)t * V + l;
+        bsource<R, NX, SRC>(src, bs, q, so + o, X);
+        if (SRC == 1) {
 #pragma unroll
-        for (int z = 0; z < NX; ++z) X[z] = src[o + z * P];
+          for (int z = 0; z < NX; ++z) bs.pout[so + o + z * P] = X[z];
+        }
         R F[NX];
 #pragma unroll
         for (int z = 0; z < NX; ++z) F[z] = (DIR > 0) ? sgn * f[o + z * P] : sgn;
@@ -259,7 +330,7 @@ __global__ void __launch_bounds__(bop_threads(NX))
 #pragma unroll
           for (int z = 0; z < NX; ++z) B[RES ? z : 0] = aux[o + z * P];
         }
-        if (red_mode) {
+        if (red_mode == 1) {
 #pragma unroll
           for (int z = 0; z < NX; ++z) Q[z] = redw[o + z * P];
         }
@@ -271,14 +342,14 @@ __global__ void __launch_bounds__(bop_threads(NX))
             out = mk<R>(bb.x - out.x, bb.y - out.y);
           }
           dst[o + z * P] = out;
-          if (red_mode == 1) {
+          if (red_mode == 1) {  // <w, y>
             a0 += double(Q[z].x) * out.x + double(Q[z].y) * out.y;
             a1 += double(Q[z].x) * out.y - double(Q[z].y) * out.x;
-          } else if (red_mode == 2) {
-            a0 += double(out.x) * Q[z].x + double(out.y) * Q[z].y;
-            a1 += double(out.x) * Q[z].y - double(out.y) * Q[z].x;
+          } else if (red_mode == 3) {  // <y, source>, |y|^2, |source|^2
+            a0 += double(out.x) * X[z].x + double(out.y) * X[z].y;
+            a1 += double(out.x) * X[z].y - double(out.y) * X[z].x;
             a2 += double(out.x) * out.x + double(out.y) * out.y;
-            a3 += double(Q[z].x) * Q[z].x + double(Q[z].y) * Q[z].y;
+            a3 += double(X[z].x) * X[z].x + double(X[z].y) * X[z].y;
           }
         }
       }
@@ -304,15 +375,9 @@ __global__ void __launch_bounds__(bop_threads(NX))
 
 #define BV_LOOP(v) for (long long i = v.lo + threadIdx.x; i < v.hi; i += blockDim.x)
 
-__device__ __forceinline__ double2 cmul(double2 a, double2 b) {
-  return double2{a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x};
-}
-__device__ __forceinline__ double2 cdiv(double2 a, double2 b) {
-  const double d = b.x * b.x + b.y * b.y;
-  return double2{(a.x * b.x + a.y * b.y) / d, (a.y * b.x - a.x * b.y) / d};
-}
 
-// Vector phases. op: 0 p-update, 1 s-update, 2 x/r update (+partials),
+// Vector phases (the p and s updates ride on the operator launches). op:
+// 9 x/r update with s = r - alpha v recomputed (+partials),
 // 3 init (x_in = 0, r = b, rhat = r, p = v = 0; |b|^2 partials, x64 = 0),
 // 4 promote (x64 += x_in, x_in = 0), 5 demote (r = r64; <rhat, r>, |r64|^2),
 // 6 restart (rhat = r, p = v = 0), 7 |b64|^2 partials, 8 |r64|^2 partials.
@@ -322,7 +387,6 @@ struct BVecArgs {
   void* rhat;
   void* p;
   void* v;
-  void* s;
   void* t;
 };
 
@@ -336,7 +400,6 @@ __global__ void __launch_bounds__(256)
   C2<R>* Rh = reinterpret_cast<C2<R>*>(A.rhat);
   C2<R>* Pp = reinterpret_cast<C2<R>*>(A.p);
   C2<R>* Vv = reinterpret_cast<C2<R>*>(A.v);
-  C2<R>* Ss = reinterpret_cast<C2<R>*>(A.s);
   C2<R>* Tt = reinterpret_cast<C2<R>*>(A.t);
   for (int it = blockIdx.x; it < nitems; it += gridDim.x) {
     const BVec item = items[it];
@@ -345,24 +408,12 @@ __global__ void __launch_bounds__(256)
     const long long o = g.off;
     const RhsState q = st[item.seg];
     double a0 = 0, a1 = 0, a2 = 0;
-    if (op == 0) {
-      const double2 beta = cmul(cdiv(q.rho, q.rho_old), cdiv(q.alpha, q.omega));
-      const R br = R(beta.x), bi = R(beta.y), wr = R(q.omega.x), wi = R(q.omega.y);
-      BV_LOOP(item) {
-        const C2<R> rv = Rr[o + i], pv = Pp[o + i], vv = Vv[o + i];
-        const R dx = pv.x - (wr * vv.x - wi * vv.y), dy = pv.y - (wr * vv.y + wi * vv.x);
-        Pp[o + i] = mk<R>(rv.x + br * dx - bi * dy, rv.y + br * dy + bi * dx);
-      }
-    } else if (op == 1) {
-      const R ar = R(q.alpha.x), ai = R(q.alpha.y);
-      BV_LOOP(item) {
-        const C2<R> rv = Rr[o + i], vv = Vv[o + i];
-        Ss[o + i] = mk<R>(rv.x - (ar * vv.x - ai * vv.y), rv.y - (ar * vv.y + ai * vv.x));
-      }
-    } else if (op == 2) {
+    if (op == 9) {  // x += alpha p + omega s, r = s - omega t, s = r - alpha v
       const R ar = R(q.alpha.x), ai = R(q.alpha.y), wr = R(q.omega.x), wi = R(q.omega.y);
       BV_LOOP(item) {
-        const C2<R> pv = Pp[o + i], sv = Ss[o + i], tv = Tt[o + i], h = Rh[o + i];
+        const C2<R> pv = Pp[o + i], rv = Rr[o + i], vv = Vv[o + i], tv = Tt[o + i],
+                    h = Rh[o + i];
+        const C2<R> sv = mk<R>(rv.x - (ar * vv.x - ai * vv.y), rv.y - (ar * vv.y + ai * vv.x));
         C2<R> xv = X[o + i];
         xv.x += (ar * pv.x - ai * pv.y) + (wr * sv.x - wi * sv.y);
         xv.y += (ar * pv.y + ai * pv.x) + (wr * sv.y + wi * sv.x);
@@ -420,7 +471,7 @@ __global__ void __launch_bounds__(256)
         a2 += v.x * v.x + v.y * v.y;
       }
     }
-    if (op == 2 || op == 3 || op == 5 || op >= 7)
+    if (op == 3 || op == 5 || op >= 7)
       bsum4b(a0, a1, a2, 0.0, part + (long long)it * 4, scratch);
   }
 }
@@ -450,14 +501,14 @@ struct BClass {
   int i0 = 0, i1 = 0;           // item range in the operator table
 };
 
-template <typename R, int NX, int DIR, bool RES>
+template <typename R, int NX, int DIR, bool RES, int SRC>
 int launch_bop_nx(const BClass& k, int ncu, hipStream_t cs, bool prepare, const BSeg* dseg,
-                  const BHop* dhop, const C2<R>* src, C2<R>* dst, int red_mode,
+                  const BHop* dhop, const BSrc<R>& bsrc, C2<R>* dst, int red_mode,
                   const C2<R>* redw, double* part, const int* gate, int slab) {
   constexpr bool SPLIT = bop_split(NX);
   constexpr int SG = bop_groups(NX);
   const size_t lds = size_t(SG) * NX * NX * (NX + 1) * sizeof(C2<R>);
-  const void* fn = (const void*)bop_kernel<R, NX, DIR, RES, SPLIT>;
+  const void* fn = (const void*)bop_kernel<R, NX, DIR, RES, SPLIT, SRC>;
   if (prepare) {  // before any capture
     UFG_HIP(hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
     return UFG_OK;
@@ -475,21 +526,23 @@ int launch_bop_nx(const BClass& k, int ncu, hipStream_t cs, bool prepare, const 
     for (int j = 0; j < NX * NX; ++j) c.t[j] = R(k.coef[j]);
   }
   const dim3 grid(std::max(1, std::min(n, ncu * g_hop_blocks_per_cu)));
-  hipLaunchKernelGGL((bop_kernel<R, NX, DIR, RES, SPLIT>), grid, dim3(bop_threads(NX)), lds, cs,
-                     c, dseg, dhop, k.i0, k.i1, src, dst, red_mode, redw, part, gate, slab);
+  hipLaunchKernelGGL((bop_kernel<R, NX, DIR, RES, SPLIT, SRC>), grid, dim3(bop_threads(NX)), lds,
+                     cs, c, dseg, dhop, k.i0, k.i1, bsrc, dst, red_mode, redw, part, gate, slab);
   UFG_HIP(hipGetLastError());
   return UFG_OK;
 }
 
-template <typename R, int DIR, bool RES>
+// One class, one phase: DIR -1 (M) / +1 (M^T); RES: FP64 residual b - A x;
+// else SRC 1 (p-update fused, red 1) or 2 (s on the fly, red 3).
+template <typename R, int DIR, bool RES, int SRC>
 int launch_bop(const BClass& k, int ncu, hipStream_t cs, bool prepare, const BSeg* dseg,
-               const BHop* dhop, const C2<R>* src, C2<R>* dst, int red_mode, const C2<R>* redw,
-               double* part, const int* gate, int slab) {
+               const BHop* dhop, const BSrc<R>& bsrc, C2<R>* dst, int red_mode,
+               const C2<R>* redw, double* part, const int* gate, int slab) {
   switch (k.nx) {
-#define BOP(NXV)                                                                            \
-  case NXV:                                                                                 \
-    return launch_bop_nx<R, NXV, DIR, RES>(k, ncu, cs, prepare, dseg, dhop, src, dst,       \
-                                           red_mode, redw, part, gate, slab);
+#define BOP(NXV)                                                                           \
+  case NXV:                                                                                \
+    return launch_bop_nx<R, NXV, DIR, RES, SRC>(k, ncu, cs, prepare, dseg, dhop, bsrc, dst, \
+                                                red_mode, redw, part, gate, slab);
     BOP(2) BOP(4) BOP(6) BOP(8) BOP(10) BOP(12) BOP(14) BOP(16)
 #undef BOP
     default:
@@ -583,7 +636,7 @@ int run_batched(std::vector<Lattice*>& Ls, const void* const* bu, void* const* x
   make_tables(all_segs);
   // device memory
   const size_t vbytes = sizeof(C2<RI>) * (size_t)total;
-  Dev dvec[7], dr64, dy, dsegs, dhops, dvecs, dtab, dhpart, dvpart, dstate;
+  Dev dvec[8], dr64, dy, dsegs, dhops, dvecs, dtab, dhpart, dvpart, dstate;
   for (auto& d : dvec) UFG_TRY(d.alloc(vbytes));
   UFG_TRY(dr64.alloc(sizeof(double2) * (size_t)total));
   UFG_TRY(dy.alloc(sizeof(double2) * (size_t)total));
@@ -638,27 +691,35 @@ int run_batched(std::vector<Lattice*>& Ls, const void* const* bu, void* const* x
   const int* vc = tab + 3 * S;
   double* hpart = reinterpret_cast<double*>(dhpart.p);
   double* vpart = reinterpret_cast<double*>(dvpart.p);
-  BVecArgs VA{dvec[0].p, dvec[1].p, dvec[2].p, dvec[3].p, dvec[4].p, dvec[5].p, dvec[6].p};
-  C2<RI>* vp = reinterpret_cast<C2<RI>*>(dvec[3].p);
-  C2<RI>* vv = reinterpret_cast<C2<RI>*>(dvec[4].p);
-  C2<RI>* vs = reinterpret_cast<C2<RI>*>(dvec[5].p);
-  C2<RI>* vt = reinterpret_cast<C2<RI>*>(dvec[6].p);
+  // inner vectors: x, r, rhat, p (two, alternating), v (two, alternating), t
+  BVecArgs VA{dvec[0].p, dvec[1].p, dvec[2].p, dvec[3].p, dvec[4].p, dvec[6].p};
+  C2<RI>* vr = reinterpret_cast<C2<RI>*>(dvec[1].p);
   C2<RI>* vrh = reinterpret_cast<C2<RI>*>(dvec[2].p);
+  C2<RI>* vt = reinterpret_cast<C2<RI>*>(dvec[6].p);
+  C2<RI>* pbuf[2] = {reinterpret_cast<C2<RI>*>(dvec[3].p), reinterpret_cast<C2<RI>*>(dvec[5].p)};
+  C2<RI>* vbuf[2] = {reinterpret_cast<C2<RI>*>(dvec[4].p), reinterpret_cast<C2<RI>*>(dvec[7].p)};
   const BSeg* dseg = reinterpret_cast<const BSeg*>(dsegs.p);
   const BHop* dhop = reinterpret_cast<const BHop*>(dhops.p);
   const BVec* dvv = reinterpret_cast<const BVec*>(dvecs.p);
   // dynamic LDS limits of every operator instance, set before any capture
+  const BSrc<RI> nosrc{};
+  const BSrc<double> nosrc64{};
   for (const BClass& k : cls) {
-    UFG_TRY((launch_bop<RI, -1, false>(k, ncu, cs, true, nullptr, nullptr, nullptr, nullptr, 0,
-                                       nullptr, nullptr, nullptr, slab)));
-    UFG_TRY((launch_bop<RI, 1, false>(k, ncu, cs, true, nullptr, nullptr, nullptr, nullptr, 0,
-                                      nullptr, nullptr, nullptr, slab)));
-    UFG_TRY((launch_bop<double, -1, true>(k, ncu, cs, true, nullptr, nullptr, nullptr, nullptr,
-                                          0, nullptr, nullptr, nullptr, slab)));
-    UFG_TRY((launch_bop<double, 1, true>(k, ncu, cs, true, nullptr, nullptr, nullptr, nullptr, 0,
+    UFG_TRY((launch_bop<RI, -1, false, 1>(k, ncu, cs, true, nullptr, nullptr, nosrc, nullptr, 0,
+                                          nullptr, nullptr, nullptr, slab)));
+    UFG_TRY((launch_bop<RI, 1, false, 1>(k, ncu, cs, true, nullptr, nullptr, nosrc, nullptr, 0,
                                          nullptr, nullptr, nullptr, slab)));
+    UFG_TRY((launch_bop<RI, -1, false, 2>(k, ncu, cs, true, nullptr, nullptr, nosrc, nullptr, 0,
+                                          nullptr, nullptr, nullptr, slab)));
+    UFG_TRY((launch_bop<RI, 1, false, 2>(k, ncu, cs, true, nullptr, nullptr, nosrc, nullptr, 0,
+                                         nullptr, nullptr, nullptr, slab)));
+    UFG_TRY((launch_bop<double, -1, true, 0>(k, ncu, cs, true, nullptr, nullptr, nosrc64, nullptr,
+                                             0, nullptr, nullptr, nullptr, slab)));
+    UFG_TRY((launch_bop<double, 1, true, 0>(k, ncu, cs, true, nullptr, nullptr, nosrc64, nullptr,
+                                            0, nullptr, nullptr, nullptr, slab)));
   }
-  const int check = o.check_every > 0 ? o.check_every : 10;
+  int check = o.check_every > 0 ? o.check_every : 10;
+  check += check & 1;
   std::vector<RhsState> hst(S);
   std::vector<int> hflags(3 * S);
   std::vector<int> iters_step[2];
@@ -683,47 +744,64 @@ int run_batched(std::vector<Lattice*>& Ls, const void* const* bu, void* const* x
       segs[s].r64 = reinterpret_cast<double2*>(dr64.p) + segs[s].off;
     }
     UFG_HIP(hipMemcpyAsync(dsegs.p, segs.data(), sizeof(BSeg) * S, hipMemcpyHostToDevice, cs));
-    auto hop = [&](int red_mode, const C2<RI>* src, C2<RI>* dst, const C2<RI>* redw) -> int {
+    // p_new = r + beta (p - omega v) fused into v_new = A p_new (+ <rhat, v_new>), or
+    // s = r - alpha v fused into t = A s (+ <t, s>, |t|^2, |s|^2); p and v alternate
+    // between two buffers so that halo reads never see this launch's writes
+    auto hop = [&](int src_mode, const C2<RI>* pin, C2<RI>* pout, const C2<RI>* vin,
+                   C2<RI>* dst) -> int {
+      const BSrc<RI> b{vr, pin, vin, pout, K.st};
       for (const BClass& k : cls) {
-        if (dir < 0)
-          UFG_TRY((launch_bop<RI, -1, false>(k, ncu, cs, false, dseg, dhop, src, dst, red_mode,
-                                             redw, hpart, K.active, slab)));
+        if (src_mode == 1 && dir < 0)
+          UFG_TRY((launch_bop<RI, -1, false, 1>(k, ncu, cs, false, dseg, dhop, b, dst, 1, vrh,
+                                                hpart, K.active, slab)));
+        else if (src_mode == 1)
+          UFG_TRY((launch_bop<RI, 1, false, 1>(k, ncu, cs, false, dseg, dhop, b, dst, 1, vrh,
+                                               hpart, K.active, slab)));
+        else if (dir < 0)
+          UFG_TRY((launch_bop<RI, -1, false, 2>(k, ncu, cs, false, dseg, dhop, b, dst, 3,
+                                                nullptr, hpart, K.active, slab)));
         else
-          UFG_TRY((launch_bop<RI, 1, false>(k, ncu, cs, false, dseg, dhop, src, dst, red_mode,
-                                            redw, hpart, K.active, slab)));
+          UFG_TRY((launch_bop<RI, 1, false, 2>(k, ncu, cs, false, dseg, dhop, b, dst, 3, nullptr,
+                                               hpart, K.active, slab)));
       }
       return UFG_OK;
     };
     auto residual = [&](const int* gate) -> int {
       for (const BClass& k : cls) {
         if (dir < 0)
-          UFG_TRY((launch_bop<double, -1, true>(k, ncu, cs, false, dseg, dhop, nullptr, nullptr,
-                                                0, nullptr, hpart, gate, slab)));
+          UFG_TRY((launch_bop<double, -1, true, 0>(k, ncu, cs, false, dseg, dhop, nosrc64,
+                                                   nullptr, 0, nullptr, hpart, gate, slab)));
         else
-          UFG_TRY((launch_bop<double, 1, true>(k, ncu, cs, false, dseg, dhop, nullptr, nullptr, 0,
-                                               nullptr, hpart, gate, slab)));
+          UFG_TRY((launch_bop<double, 1, true, 0>(k, ncu, cs, false, dseg, dhop, nosrc64,
+                                                  nullptr, 0, nullptr, hpart, gate, slab)));
       }
       return UFG_OK;
     };
-    auto vop = [&](int op, const int* gate) {
-      hipLaunchKernelGGL((bvec_kernel<RI>), vgrid, dim3(256), 0, cs, op, dseg, dvv, nv, VA, K.st,
+    auto vop = [&](int op, const int* gate, const BVecArgs& args) {
+      hipLaunchKernelGGL((bvec_kernel<RI>), vgrid, dim3(256), 0, cs, op, dseg, dvv, nv, args, K.st,
                          gate, vpart);
     };
     // initial state: x = 0, r = b, rhat = r
-    vop(3, nullptr);
+    vop(3, nullptr, VA);
     UFG_TRY(k_finalize_seg(cs, FIN_INIT_B, vpart, vf, vc, nullptr, K));
     UFG_TRY(k_finalize_seg(cs, FIN_INIT_R, vpart, vf, vc, nullptr, K));
     UFG_HIP(hipGetLastError());
-    // one check interval of iterations, captured once
+    // one check interval of iterations (an even count, so that p and v are back
+    // in their first buffers at every check point), captured once
     auto body = [&]() -> int {
       for (int k = 0; k < check; ++k) {
-        vop(0, K.active);
-        UFG_TRY(hop(1, vp, vv, vrh));
+        C2<RI>* pin = pbuf[k & 1];
+        C2<RI>* pout = pbuf[(k + 1) & 1];
+        C2<RI>* vin = vbuf[k & 1];
+        C2<RI>* vout = vbuf[(k + 1) & 1];
+        UFG_TRY(hop(1, pin, pout, vin, vout));
         UFG_TRY(k_finalize_seg(cs, FIN_ALPHA, hpart, hf, hc, K.active, K));
-        vop(1, K.active);
-        UFG_TRY(hop(2, vs, vt, vs));
+        UFG_TRY(hop(2, nullptr, nullptr, vout, vt));
         UFG_TRY(k_finalize_seg(cs, FIN_OMEGA, hpart, hf, hc, K.active, K));
-        vop(2, K.active);
+        BVecArgs A = VA;
+        A.p = pout;
+        A.v = vout;
+        vop(9, K.active, A);
         UFG_TRY(k_finalize_seg(cs, FIN_RHO, vpart, vf, vc, K.active, K));
       }
       return UFG_OK;
@@ -762,13 +840,13 @@ int run_batched(std::vector<Lattice*>& Ls, const void* const* bu, void* const* x
         any_restart |= hflags[2 * S + s] != 0;
       }
       if (any_update) {  // reliable update: x64 += x_in, r64 = b - A x64, r = r64
-        vop(4, K.update);
+        vop(4, K.update, VA);
         UFG_TRY(residual(K.update));
-        vop(5, K.update);
+        vop(5, K.update, VA);
         UFG_TRY(k_finalize_seg(cs, FIN_UPDATE, vpart, vf, vc, K.update, K));
       }
       if (any_restart) {
-        vop(6, K.restart);
+        vop(6, K.restart, VA);
         UFG_TRY(k_finalize_seg(cs, FIN_RESTART, vpart, vf, vc, K.restart, K));
       }
       UFG_HIP(hipGetLastError());
@@ -793,7 +871,7 @@ int run_batched(std::vector<Lattice*>& Ls, const void* const* bu, void* const* x
       make_tables(all_segs);
       UFG_TRY(upload_tables());
     }
-    vop(4, nullptr);  // final x64 += x_in
+    vop(4, nullptr, VA);  // final x64 += x_in
     UFG_HIP(hipMemcpyAsync(hst.data(), K.st, sizeof(RhsState) * S, hipMemcpyDeviceToHost, cs));
     UFG_HIP(hipStreamSynchronize(cs));
     iters_step[step].assign(nprob, 0);
@@ -805,9 +883,9 @@ int run_batched(std::vector<Lattice*>& Ls, const void* const* bu, void* const* x
     }
     // true residuals of this step, FP64
     UFG_TRY(residual(nullptr));
-    vop(7, nullptr);
+    vop(7, nullptr, VA);
     UFG_TRY(k_finalize_seg(cs, FIN_INIT_B, vpart, vf, vc, nullptr, K));
-    vop(8, nullptr);
+    vop(8, nullptr, VA);
     UFG_TRY(k_finalize_seg(cs, FIN_NORM, vpart, vf, vc, nullptr, K));
     UFG_HIP(hipMemcpyAsync(hst.data(), K.st, sizeof(RhsState) * S, hipMemcpyDeviceToHost, cs));
     UFG_HIP(hipStreamSynchronize(cs));
