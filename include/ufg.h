@@ -244,8 +244,11 @@ int lattice_tune(ufg_lattice L, int slab, int vec_blocks);
 /* lattice_info -- nx, ntau, dtype, A of a handle (host pointers, any may be NULL). */
 int lattice_info(ufg_lattice L, int* nx, int* ntau, int* dtype, double* A);
 
-/* ufg_last_error -- message for the last failing call on this thread. */
+/* ufg_last_error -- message for the last failing call on this thread.
+ * last_error is the same function under its short name. The returned string
+ * is owned by the library and valid until the thread's next failing call. */
 const char* ufg_last_error(void);
+const char* last_error(void);
 
 /*
  * Host helpers (no device work; usable without a GPU):

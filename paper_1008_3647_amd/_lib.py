@@ -70,6 +70,7 @@ _SIGNATURES = {
     "lattice_info": (C.c_int, [_P, C.POINTER(C.c_int), C.POINTER(C.c_int),
                                C.POINTER(C.c_int), C.POINTER(C.c_double)]),
     "ufg_last_error": (C.c_char_p, []),
+    "last_error": (C.c_char_p, []),
     "ufg_cheb_roots": (C.c_int, [C.c_int, C.c_double, C.POINTER(C.c_double),
                                  C.POINTER(C.c_double)]),
     "ufg_euler_weights": (C.c_int, [C.c_int, C.c_double, C.POINTER(C.c_double)]),

@@ -142,6 +142,7 @@ using namespace ufg;
 extern "C" {
 
 const char* ufg_last_error(void) { return g_err.c_str(); }
+const char* last_error(void) { return g_err.c_str(); }
 
 int create_lattice(int nx, int ntau, double tau, double g, int dtype, void* hip_stream,
                    ufg_lattice* out) {
