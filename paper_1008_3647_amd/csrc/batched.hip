@@ -215,10 +215,9 @@ __device__ __forceinline__ BScal<R> bsrc_scalars(const BSrc<R>& b, int seg) {
   BScal<R> q{};
   if (SRC == 0) return q;
   const RhsState s = b.st[seg];
-  if (SRC == 1) {  // beta = (rho / rho_old)(alpha / omega)
-    const double2 beta = cmul(cdiv(s.rho, s.rho_old), cdiv(s.alpha, s.omega));
-    q.br = R(beta.x);
-    q.bi = R(beta.y);
+  if (SRC == 1) {  // beta = (rho / rho_old)(alpha / omega), set by the finalize
+    q.br = R(s.beta.x);
+    q.bi = R(s.beta.y);
     q.wr = R(s.omega.x);
     q.wi = R(s.omega.y);
   } else {

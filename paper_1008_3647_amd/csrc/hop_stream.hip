@@ -109,15 +109,8 @@ __device__ __forceinline__ SrcScal<R> src_scalars(const HopArgs<R>& a, int r) {
   if (SRC == 0) return q;
   const RhsState s = reinterpret_cast<const RhsState*>(a.st)[r];
   if (SRC == 1) {
-    // beta = (rho / rho_old)(alpha / omega)
-    const double d1 = s.rho_old.x * s.rho_old.x + s.rho_old.y * s.rho_old.y;
-    const double q1x = (s.rho.x * s.rho_old.x + s.rho.y * s.rho_old.y) / d1;
-    const double q1y = (s.rho.y * s.rho_old.x - s.rho.x * s.rho_old.y) / d1;
-    const double d2 = s.omega.x * s.omega.x + s.omega.y * s.omega.y;
-    const double q2x = (s.alpha.x * s.omega.x + s.alpha.y * s.omega.y) / d2;
-    const double q2y = (s.alpha.y * s.omega.x - s.alpha.x * s.omega.y) / d2;
-    q.br = R(q1x * q2x - q1y * q2y);
-    q.bi = R(q1x * q2y + q1y * q2x);
+    q.br = R(s.beta.x);  // beta = (rho / rho_old)(alpha / omega), set by the finalize
+    q.bi = R(s.beta.y);
     q.wr = R(s.omega.x);
     q.wi = R(s.omega.y);
   } else {

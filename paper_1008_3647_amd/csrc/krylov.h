@@ -9,6 +9,7 @@ namespace ufg {
 // Scalars of one right-hand side, resident on the device.
 struct RhsState {
   double2 rho, rho_old, alpha, omega;  // BiCGStab; CG uses rho = <r,z>, alpha, omega = beta
+  double2 beta;  // BiCGStab: (rho / rho_old)(alpha / omega), 0 when undefined
   double r2;     // |r|^2 of the iterated residual
   double b2;     // |b|^2
   double maxr2;  // largest |r|^2 since the last reliable update

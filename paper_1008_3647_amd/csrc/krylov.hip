@@ -62,7 +62,7 @@ __device__ void bsum4(double a0, double a1, double a2, double a3, double* out) {
 #define KR_LOOP(n) \
   for (long long i = blockIdx.x * 256ll + threadIdx.x; i < (n); i += (long long)gridDim.x * 256)
 
-// p = r + beta (p - omega v), beta = (rho / rho_old)(alpha / omega)
+// p = r + beta (p - omega v), beta = (rho / rho_old)(alpha / omega) from the state
 template <typename R>
 __global__ void __launch_bounds__(256) bicg_p_kernel(const C2<R>* r, C2<R>* p, const C2<R>* v,
                                                      const RhsState* st, const int* active,
@@ -70,8 +70,7 @@ __global__ void __launch_bounds__(256) bicg_p_kernel(const C2<R>* r, C2<R>* p, c
   const int k = blockIdx.y;
   if (!active[k]) return;
   const RhsState s = st[k];
-  const double2 beta = cmul(cdiv(s.rho, s.rho_old), cdiv(s.alpha, s.omega));
-  const R br = R(beta.x), bi = R(beta.y), wr = R(s.omega.x), wi = R(s.omega.y);
+  const R br = R(s.beta.x), bi = R(s.beta.y), wr = R(s.omega.x), wi = R(s.omega.y);
   const long long off = (long long)k * n;
   KR_LOOP(n) {
     const C2<R> rv = r[off + i], pv = p[off + i], vv = v[off + i];
@@ -318,6 +317,7 @@ __device__ void apply_fin(int op, int k, double s0, double s1, double s2, double
       q.rho = double2{s2, 0.0};
       q.rhat2 = s2;
       q.rho_old = q.alpha = q.omega = double2{1.0, 0.0};
+      q.beta = double2{0.0, 0.0};
       q.r2 = q.maxr2 = s2;
       q.iters = 0;
       q.updates = 0;
@@ -363,8 +363,17 @@ __device__ void apply_fin(int op, int k, double s0, double s1, double s2, double
         break;
       }
       if (q.omega.x == 0.0 && q.omega.y == 0.0 && s2 > q.tol2) restart[k] = 1;
+      // beta of the next p-update; undefined after omega = 0 or rho_old = 0
+      // (then p restarts from r, and the restart flag renews rhat)
+      if ((q.rho_old.x != 0.0 || q.rho_old.y != 0.0) && (q.omega.x != 0.0 || q.omega.y != 0.0))
+        q.beta = cmul(cdiv(q.rho, q.rho_old), cdiv(q.alpha, q.omega));
+      else
+        q.beta = double2{0.0, 0.0};
       if (s2 <= q.tol2) {
-        update[k] = 1;  // verify with a recomputed residual
+        // verify with a recomputed residual; no further iterations until then
+        // (this is the end of an iteration, so the state stays consistent)
+        update[k] = 1;
+        active[k] = 0;
       } else if (prm.mixed && s2 < prm.delta2 * q.maxr2) {
         update[k] = 1;
       }
@@ -377,17 +386,26 @@ __device__ void apply_fin(int op, int k, double s0, double s1, double s2, double
       q.r2 = s2;
       q.maxr2 = s2;
       q.updates += 1;
-      if (prm.bicg) q.rho = d01;
+      if (prm.bicg) {  // rho = <rhat, r> of the recomputed residual, and its beta
+        q.rho = d01;
+        if ((q.rho_old.x != 0.0 || q.rho_old.y != 0.0) && (q.omega.x != 0.0 || q.omega.y != 0.0))
+          q.beta = cmul(cdiv(q.rho, q.rho_old), cdiv(q.alpha, q.omega));
+        else
+          q.beta = double2{0.0, 0.0};
+      }
       update[k] = 0;
       if (s2 <= q.tol2) {
         q.conv = 1;
         active[k] = 0;
+      } else if (q.status == 0) {
+        active[k] = 1;  // the iterated residual met tol, the true one did not
       }
       break;
     case FIN_RESTART:  // rhat = r: rho = |r|^2, scalars reset
       q.rho = double2{q.r2, 0.0};
       q.rhat2 = q.r2;
       q.rho_old = q.alpha = q.omega = double2{1.0, 0.0};
+      q.beta = double2{0.0, 0.0};
       restart[k] = 0;
       break;
     case FIN_CG_ALPHA:  // alpha = rz / <p, w>
@@ -407,6 +425,8 @@ __device__ void apply_fin(int op, int k, double s0, double s1, double s2, double
         q.status = UFG_BREAKDOWN;
         break;
       }
+      // CG keeps iterating until the check point verifies (the rest of this
+      // iteration, beta and p, still has to run for a consistent state)
       if (s2 <= q.tol2) {
         update[k] = 1;
       } else if (prm.mixed && s2 < prm.delta2 * q.maxr2) {

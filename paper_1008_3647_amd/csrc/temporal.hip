@@ -122,60 +122,84 @@ __global__ void sca_apply_kernel(const C2<R>* v, C2<R>* x, const R* __restrict__
 // Per spatial mode n with eigenvalue lam of exp(-tau K):
 //   forward : (1 - lam Z) u = v,   (Z w)_t = w_{t-1}, (Z w)_0 = -w_{Ntau-1}
 //   adjoint : (1 - lam Z^T) u = v
-// Closed form of the cyclic first-order recurrence: first the corner value by
-// a Horner sum, then one sweep. u may alias v.
+// Temporal part of M0^{-1} per (rhs, spatial mode): the cyclic first-order
+// recurrence u_t = v_t + lam u_{t-1} with the antiperiodic closure
+// u_{-1} = -u_{Ntau-1}, split into kChunks time chunks so that 8x more threads
+// share the sweep (a thread's chain is Ntau/8 long instead of Ntau):
+// workgroup = 64 modes x kChunks chunks (one chunk per wave, modes along the
+// lanes). Pass 1: every chunk sweeps its slices from a zero carry (g = last
+// value). Then per mode: the chunk carries U_c = g_c + lam^{L_c} U_{c-1} with
+// the antiperiodic closure U_{-1} = -U_{last}, i.e. U_last = G / (1 + lam^N)
+// where G is the scan from a zero start. Pass 2: every chunk sweeps again from
+// its carry. The adjoint runs the same recurrence on reversed time. u may
+// alias v (each thread reads and writes only its own chunk).
+constexpr int kChunks = 8;
+constexpr int kModes = 64;
+
 template <typename R>
-__global__ void m0_temporal_kernel(const C2<R>* v, C2<R>* u, const R* __restrict__ lam_mode,
-                                   int V, int ntau, int nrhs, int adjoint, int subtract,
-                                   const int* gate) {
-  const long long gid = blockIdx.x * (long long)blockDim.x + threadIdx.x;
-  if (gid >= (long long)V * nrhs) return;
-  const int r = int(gid / V);
-  const int n = int(gid - (long long)r * V);
-  if (gate && gate[r] == 0) return;
+__global__ void __launch_bounds__(kModes* kChunks)
+    m0_chunked_kernel(const C2<R>* v, C2<R>* u, const R* __restrict__ lam_mode, int V, int ntau,
+                      int nrhs, int adjoint, int subtract, const int* gate) {
+  __shared__ C2<R> carry[kChunks][kModes];
+  const int ml = threadIdx.x % kModes, c = threadIdx.x / kModes;
+  const long long gid = (long long)blockIdx.x * kModes + ml;
+  const bool inb = gid < (long long)V * nrhs;
+  const int r = inb ? int(gid / V) : 0;
+  const int n = inb ? int(gid - (long long)r * V) : 0;
+  const bool act = inb && !(gate && gate[r] == 0);
+  const int Lc = (ntau + kChunks - 1) / kChunks;
+  const int s0 = min(c * Lc, ntau), s1 = min(s0 + Lc, ntau);  // chunk [s0, s1) in sweep order
   const long long base = (long long)r * ntau * V + n;
-  const R lam = lam_mode[n];
-  R lamN = R(1);
-  for (int k = 0; k < ntau; ++k) lamN *= lam;
-  const R inv = R(1) / (R(1) + lamN);
-  if (!adjoint) {
-    // h = sum_{m=1}^{Ntau-1} lam^m v_{Ntau-m}
-    R hx = R(0), hy = R(0);
-#pragma unroll 4
-    for (int t = 1; t < ntau; ++t) {
-      const C2<R> q = v[base + (long long)t * V];
-      hx = q.x + lam * hx;
-      hy = q.y + lam * hy;
+  const R lam = act ? lam_mode[n] : R(0);
+  auto at = [&](int k) -> long long {  // sweep position -> element index
+    const int t = adjoint ? ntau - 1 - k : k;
+    return base + (long long)t * V;
+  };
+  // pass 1: zero-carry sweep of the chunk
+  C2<R> w = C2<R>{R(0), R(0)};
+  if (act) {
+#pragma unroll 8
+    for (int k = s0; k < s1; ++k) {
+      const C2<R> q = v[at(k)];
+      w = C2<R>{q.x + lam * w.x, q.y + lam * w.y};
     }
-    const C2<R> v0 = v[base];
-    C2<R> prev = C2<R>{(v0.x - lam * hx) * inv, (v0.y - lam * hy) * inv};
-    u[base] = subtract ? C2<R>{prev.x - v0.x, prev.y - v0.y} : prev;
-#pragma unroll 4
-    for (int t = 1; t < ntau; ++t) {
-      const long long i = base + (long long)t * V;
+  }
+  carry[c][ml] = w;
+  __syncthreads();
+  if (c == 0 && act) {
+    R lamL[kChunks];
+    R lamN = R(1);
+    for (int j = 0; j < kChunks; ++j) {
+      const int L = min((j + 1) * Lc, ntau) - min(j * Lc, ntau);
+      R p = R(1);
+      for (int i = 0; i < L; ++i) p *= lam;
+      lamL[j] = p;
+      lamN *= p;
+    }
+    // scan from a zero start: G = carry out of the last chunk
+    C2<R> U = C2<R>{R(0), R(0)};
+    for (int j = 0; j < kChunks; ++j) {
+      const C2<R> g = carry[j][ml];
+      U = C2<R>{g.x + lamL[j] * U.x, g.y + lamL[j] * U.y};
+    }
+    const R inv = R(1) / (R(1) + lamN);
+    // carry into chunk 0 is U_{-1} = -U_last
+    C2<R> cin = C2<R>{-U.x * inv, -U.y * inv};
+    for (int j = 0; j < kChunks; ++j) {
+      const C2<R> g = carry[j][ml];
+      carry[j][ml] = cin;  // carry into chunk j
+      cin = C2<R>{g.x + lamL[j] * cin.x, g.y + lamL[j] * cin.y};
+    }
+  }
+  __syncthreads();
+  if (act) {
+    C2<R> prev = carry[c][ml];
+#pragma unroll 8
+    for (int k = s0; k < s1; ++k) {
+      const long long i = at(k);
       const C2<R> q = v[i];
       prev = C2<R>{q.x + lam * prev.x, q.y + lam * prev.y};
       u[i] = subtract ? C2<R>{prev.x - q.x, prev.y - q.y} : prev;
-    }
-  } else {
-    // h = sum_{t=0}^{Ntau-2} lam^{t+1} v_t
-    R hx = R(0), hy = R(0);
-#pragma unroll 4
-    for (int t = ntau - 2; t >= 0; --t) {
-      const C2<R> q = v[base + (long long)t * V];
-      hx = q.x + lam * hx;
-      hy = q.y + lam * hy;
-    }
-    const long long last = base + (long long)(ntau - 1) * V;
-    const C2<R> vl = v[last];
-    C2<R> next = C2<R>{(vl.x - lam * hx) * inv, (vl.y - lam * hy) * inv};
-    u[last] = subtract ? C2<R>{next.x - vl.x, next.y - vl.y} : next;
-#pragma unroll 4
-    for (int t = ntau - 2; t >= 0; --t) {
-      const long long i = base + (long long)t * V;
-      const C2<R> q = v[i];
-      next = C2<R>{q.x + lam * next.x, q.y + lam * next.y};
-      u[i] = subtract ? C2<R>{next.x - q.x, next.y - q.y} : next;
     }
   }
 }
@@ -215,10 +239,9 @@ int launch_m0_temporal(const Lattice& L, const C2<R>* v, C2<R>* u, int nrhs, boo
                        bool subtract_input, const int* gate) {
   const Fields<R>& F = fields<R>(L);
   const long long n = (long long)L.V * nrhs;
-  const int threads = 128;
-  hipLaunchKernelGGL((m0_temporal_kernel<R>), dim3((unsigned)((n + threads - 1) / threads)),
-                     dim3(threads), 0, L.stream, v, u, F.lam, L.V, L.ntau, nrhs, adjoint ? 1 : 0,
-                     subtract_input ? 1 : 0, gate);
+  hipLaunchKernelGGL((m0_chunked_kernel<R>), dim3((unsigned)((n + kModes - 1) / kModes)),
+                     dim3(kModes * kChunks), 0, L.stream, v, u, F.lam, L.V, L.ntau, nrhs,
+                     adjoint ? 1 : 0, subtract_input ? 1 : 0, gate);
   UFG_HIP(hipGetLastError());
   return UFG_OK;
 }
