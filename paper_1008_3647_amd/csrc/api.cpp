@@ -200,13 +200,25 @@ int create_lattice(int nx, int ntau, double tau, double g, int dtype, void* hip_
     set_error("create_lattice: block form of T failed its check");
     return UFG_EHIP;
   }
+  if (mode_split_coefficients(nx, L->U_host, &L->mode_fwd_host, &L->mode_bwd_host,
+                              &L->mode_perm) > 1e-12) {
+    free_fields(*L);
+    delete L;
+    set_error("create_lattice: block form of the eigenbasis failed its check");
+    return UFG_EHIP;
+  }
+  // mode-space vectors of the streaming basis change use the block order of
+  // the modes; the mode eigenvalues follow it
+  std::vector<double> lam1m = L->lam1_host;
+  if (!L->mode_perm.empty())
+    for (int i = 0; i < nx; ++i) lam1m[i] = L->lam1_host[L->mode_perm[i]];
   std::vector<double> Ut(nx * nx), lam3(L->V);
   for (int i = 0; i < nx; ++i)
     for (int j = 0; j < nx; ++j) Ut[i * nx + j] = L->U_host[j * nx + i];
   for (int z = 0; z < nx; ++z)
     for (int y = 0; y < nx; ++y)
       for (int x = 0; x < nx; ++x)
-        lam3[(z * nx + y) * nx + x] = L->lam1_host[z] * L->lam1_host[y] * L->lam1_host[x];
+        lam3[(z * nx + y) * nx + x] = lam1m[z] * lam1m[y] * lam1m[x];
   int rc = UFG_OK;
   if (!rc) rc = upload<double>(L->stream, L->f64.T, L->T_host);
   if (!rc) rc = upload<float>(L->stream, L->f32.T, L->T_host);

@@ -237,6 +237,11 @@ int launch_hop(const Lattice& L, const HopArgs<R>& a) {
   if (a.shift != 0 && a.mat == fields<R>(L).T && (a.id == nullptr || a.id == a.src) &&
       stream_supported(L))
     return launch_hop_stream<R>(L, a);
+  // basis changes of the eigenbasis: the mode-space vectors are in the block
+  // order of the streaming basis kernel whenever it exists for this nx
+  if (a.shift == 0 && !L.mode_perm.empty() &&
+      (a.mat == fields<R>(L).U || a.mat == fields<R>(L).Ut))
+    return launch_basis_stream<R>(L, a, a.mat == fields<R>(L).Ut);
 #define CALL_HOP(NX) launch_hop_nx<R, NX>(L, a)
   UFG_NX_SWITCH(L.nx, CALL_HOP)
 #undef CALL_HOP

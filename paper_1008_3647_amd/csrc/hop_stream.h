@@ -20,6 +20,17 @@ struct SplitCoef {
 // of the transformed matrix (a self-check).
 double split_coefficients(int nx, const std::vector<double>& T, std::vector<double>* out);
 
+// Host: the block-diagonal forward (U^T) and backward (U) maps of the
+// eigenbasis of T, with the block ordering of the modes (perm); empty for nx
+// not in {8, 12, 16}. Returns the largest off-block entry (a self-check).
+double mode_split_coefficients(int nx, const std::vector<double>& U, std::vector<double>* fwd,
+                               std::vector<double>* bwd, std::vector<int>* perm);
+
+// Basis change y = (U or U^T)^{x3} (pre . x) scaled by post, alpha, plus beta aux,
+// in the block-ordered mode basis (streaming-supported nx only).
+template <typename R>
+int launch_basis_stream(const Lattice& L, const HopArgs<R>& a, bool forward);
+
 int stream_slab(const Lattice& L);
 bool stream_supported(const Lattice& L);
 template <typename R>

@@ -58,11 +58,23 @@ constexpr int lds_slice_elems() {
 // ordering point replaces the block barrier. Each thread's last read and its
 // next first write touch only its own z-line, so no barrier guards the reuse
 // of the buffer by the next slice.
-template <typename R, int NX>
+// MODE 0: T (positions -> positions); 1: U^T (positions -> block-ordered
+// modes); 2: U (modes -> positions). The same three passes serve all three.
+template <int MODE, typename R, int NX>
+__device__ __forceinline__ void line_op(const SplitCoef<R, NX>& c, C2<R> (&v)[NX]) {
+  if constexpr (MODE == 0)
+    split_line<R, NX>(c, v);
+  else if constexpr (MODE == 1)
+    modes_fwd<R, NX>(c, v);
+  else
+    modes_bwd<R, NX>(c, v);
+}
+
+template <typename R, int NX, int MODE = 0>
 __device__ __forceinline__ void slice_T3(const SplitCoef<R, NX>& c, C2<R>* lds, int l,
                                          C2<R> (&v)[NX]) {
   const int y = l / NX, x = l - (l / NX) * NX;
-  split_line<R, NX>(c, v);  // along z
+  line_op<MODE, R, NX>(c, v);  // along z
 #pragma unroll
   for (int z = 0; z < NX; ++z) lds[lds_at<NX>(z * NX + y, x)] = v[z];
   __syncthreads();
@@ -71,7 +83,7 @@ __device__ __forceinline__ void slice_T3(const SplitCoef<R, NX>& c, C2<R>* lds, 
     const int z = l / NX, xx = l - (l / NX) * NX;
 #pragma unroll
     for (int yy = 0; yy < NX; ++yy) w[yy] = lds[lds_at<NX>(z * NX + yy, xx)];
-    split_line<R, NX>(c, w);  // along y
+    line_op<MODE, R, NX>(c, w);  // along y
 #pragma unroll
     for (int yy = 0; yy < NX; ++yy) lds[lds_at<NX>(z * NX + yy, xx)] = w[yy];
   }
@@ -88,7 +100,7 @@ __device__ __forceinline__ void slice_T3(const SplitCoef<R, NX>& c, C2<R>* lds, 
     const int z = l / NX, yy = l - (l / NX) * NX;
 #pragma unroll
     for (int xx = 0; xx < NX; ++xx) w[xx] = lds[lds_at<NX>(z * NX + yy, xx)];
-    split_line<R, NX>(c, w);  // along x
+    line_op<MODE, R, NX>(c, w);  // along x
 #pragma unroll
     for (int xx = 0; xx < NX; ++xx) lds[lds_at<NX>(z * NX + yy, xx)] = w[xx];
   }
@@ -453,6 +465,108 @@ int launch_nx(const Lattice& L, const HopArgs<R>& a) {
   return launch_dir<R, NX, +1>(L, a, c);
 }
 
+// Basis change of whole slices (no time shift): y = post . M^3 (pre . x),
+// M = U^T (forward: positions -> block-ordered modes) or U (backward), then
+// GENERAL: y = alpha y + beta aux. A workgroup walks a slab of slices of one
+// right-hand side (XCD-aware numbering as above); the slices are independent.
+template <typename R, int NX, bool FWD, bool GENERAL>
+__global__ void __launch_bounds__(NX * NX)
+    basis_kernel(HopArgs<R> a, SplitCoef<R, NX> c, int ntau, int slab) {
+  constexpr int P = NX * NX, V = NX * NX * NX;
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  C2<R>* lds = reinterpret_cast<C2<R>*>(smem_raw);
+  const int nb = gridDim.x;
+  const int full = nb & ~7;
+  int lid = blockIdx.x;
+  if (lid < full) lid = (lid & 7) * (full >> 3) + (lid >> 3);
+  const int r = lid % a.nrhs;
+  const int sb = lid / a.nrhs;
+  if (a.gate && a.gate[r] == 0) return;
+  const int l = threadIdx.x;
+  const int t0 = sb * slab, t1 = min(t0 + slab, ntau);
+  const long long rbase = (long long)r * ntau * V;
+  for (int t = t0; t < t1; ++t) {
+    const long long o = rbase + (long long)t * V + l;
+    const long long fo = (long long)t * V + l;
+    C2<R> X[NX];
+#pragma unroll
+    for (int z = 0; z < NX; ++z) X[z] = a.src[o + z * P];
+    if (a.pre) {
+#pragma unroll
+      for (int z = 0; z < NX; ++z) {
+        const R fz = a.pre[fo + z * P];
+        X[z].x *= fz;
+        X[z].y *= fz;
+      }
+    }
+    R F[NX];
+    C2<R> U[GENERAL ? NX : 1];
+#pragma unroll
+    for (int z = 0; z < NX; ++z) F[z] = a.post ? a.post[fo + z * P] : R(1);
+    if (GENERAL && a.aux) {
+#pragma unroll
+      for (int z = 0; z < NX; ++z) U[GENERAL ? z : 0] = a.aux[o + z * P];
+    }
+    slice_T3<R, NX, FWD ? 1 : 2>(c, lds, l, X);
+#pragma unroll
+    for (int z = 0; z < NX; ++z) {
+      C2<R> out;
+      out.x = F[z] * X[z].x;
+      out.y = F[z] * X[z].y;
+      if (GENERAL) {
+        const R ar = R(a.alpha.x), ai = R(a.alpha.y);
+        const C2<R> b = out;
+        out.x = ar * b.x - ai * b.y;
+        out.y = ar * b.y + ai * b.x;
+        if (a.aux) {
+          const C2<R> u = U[GENERAL ? z : 0];
+          const R br = R(a.beta.x), bi = R(a.beta.y);
+          out.x += br * u.x - bi * u.y;
+          out.y += br * u.y + bi * u.x;
+        }
+      }
+      __builtin_nontemporal_store(out.x, &a.dst[o + z * P].x);
+      __builtin_nontemporal_store(out.y, &a.dst[o + z * P].y);
+    }
+  }
+}
+
+template <typename R, int NX, bool FWD, bool GENERAL>
+int launch_basis_one(const Lattice& L, const HopArgs<R>& a, const SplitCoef<R, NX>& c,
+                     dim3 grid, size_t lds, int slab) {
+  static bool attr = false;
+  if (!attr) {
+    UFG_HIP(hipFuncSetAttribute((const void*)basis_kernel<R, NX, FWD, GENERAL>,
+                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+    attr = true;
+  }
+  hipLaunchKernelGGL((basis_kernel<R, NX, FWD, GENERAL>), grid, dim3(NX * NX), lds, L.stream, a,
+                     c, L.ntau, slab);
+  UFG_HIP(hipGetLastError());
+  return UFG_OK;
+}
+
+template <typename R, int NX>
+int launch_basis_nx(const Lattice& L, const HopArgs<R>& a, bool forward) {
+  SplitCoef<R, NX> c;
+  const std::vector<double>& h = forward ? L.mode_fwd_host : L.mode_bwd_host;
+  int k = 0;
+  for (auto& v : c.es) v = R(h[k++]);
+  for (auto& v : c.ea) v = R(h[k++]);
+  for (auto& v : c.os) v = R(h[k++]);
+  for (auto& v : c.oa) v = R(h[k++]);
+  const int slab = stream_slab(L);
+  const int nslab = (L.ntau + slab - 1) / slab;
+  const size_t lds = size_t(lds_slice_elems<NX>()) * sizeof(C2<R>);
+  const dim3 grid(nslab * a.nrhs);
+  const bool general = (a.alpha.x != 1.0 || a.alpha.y != 0.0 || a.aux != nullptr);
+  if (forward)
+    return general ? launch_basis_one<R, NX, true, true>(L, a, c, grid, lds, slab)
+                   : launch_basis_one<R, NX, true, false>(L, a, c, grid, lds, slab);
+  return general ? launch_basis_one<R, NX, false, true>(L, a, c, grid, lds, slab)
+                 : launch_basis_one<R, NX, false, false>(L, a, c, grid, lds, slab);
+}
+
 }  // namespace
 
 int stream_slab(const Lattice& L) {
@@ -486,6 +600,24 @@ int launch_hop_stream(const Lattice& L, const HopArgs<R>& args) {
   }
 }
 
+template <typename R>
+int launch_basis_stream(const Lattice& L, const HopArgs<R>& args, bool forward) {
+  HopArgs<R> a = args;
+  if (a.beta.x == 0.0 && a.beta.y == 0.0) a.aux = nullptr;
+  if (a.shift != 0 || a.red_mode != 0 || a.src_mode != 0 || a.id != nullptr) {
+    set_error("basis change: no shift, identity term or reduction");
+    return UFG_EINVAL;
+  }
+  switch (L.nx) {
+    case 8: return launch_basis_nx<R, 8>(L, a, forward);
+    case 12: return launch_basis_nx<R, 12>(L, a, forward);
+    case 16: return launch_basis_nx<R, 16>(L, a, forward);
+    default: set_error("basis change: unsupported nx"); return UFG_EINVAL;
+  }
+}
+
+template int launch_basis_stream<float>(const Lattice&, const HopArgs<float>&, bool);
+template int launch_basis_stream<double>(const Lattice&, const HopArgs<double>&, bool);
 template int launch_hop_stream<float>(const Lattice&, const HopArgs<float>&);
 template int launch_hop_stream<double>(const Lattice&, const HopArgs<double>&);
 

@@ -39,9 +39,9 @@ static bool invert(int n, std::vector<double> a, std::vector<double>* inv) {
   return true;
 }
 
-double split_coefficients(int nx, const std::vector<double>& T, std::vector<double>* out) {
-  out->clear();
-  if (nx % 4 != 0 || nx < 8) return 0.0;
+// P: positions -> reflection-symmetry components (block order es, ea, os,
+// oa); Pp: the inverse written with additions only (as the kernels do).
+static void butterfly_matrices(int nx, std::vector<double>* Pout, std::vector<double>* Ppout) {
   const int n = nx, H = nx / 2, Q = nx / 4;
   // rows of P: E_j = x_j + x_{-j} (x_0, x_H alone), O_j = x_j - x_{-j}
   auto Erow = [&](int j) {
@@ -129,6 +129,16 @@ double split_coefficients(int nx, const std::vector<double>& T, std::vector<doub
     setrow(j, s);
     setrow(n - j, d);
   }
+  *Pout = P;
+  *Ppout = Pp;
+}
+
+double split_coefficients(int nx, const std::vector<double>& T, std::vector<double>* out) {
+  out->clear();
+  if (nx % 4 != 0 || nx < 8) return 0.0;
+  const int n = nx, Q = nx / 4;
+  std::vector<double> P, Pp;
+  butterfly_matrices(nx, &P, &Pp);
   std::vector<double> Pi, Ppi;
   if (!invert(n, P, &Pi) || !invert(n, Pp, &Ppi)) return 1.0;
   std::vector<double> tmp(n * n, 0.0), B(n * n, 0.0);
@@ -161,6 +171,77 @@ double split_coefficients(int nx, const std::vector<double>& T, std::vector<doub
   for (int b = 0; b < 4; ++b)
     for (int i = 0; i < sizes[b]; ++i)
       for (int j = 0; j < sizes[b]; ++j) out->push_back(B[(starts[b] + i) * n + starts[b] + j]);
+  return off;
+}
+
+// The eigenbasis U of T (columns = modes: cosines and sines) in the same
+// reflection-symmetry basis. Every mode is even or odd under both reflections,
+// so with the modes ordered block by block (perm[i] = the column of U that is
+// block-ordered mode i) the forward map c = U^T a = (U^T P^{-1}) (P a) and the
+// backward map a = U c = Pp (Pp^{-1} U) c are block diagonal: fwd and bwd hold
+// their blocks in the order es, ea, os, oa. Returns the largest off-block
+// entry of either map (a self-check), 1 when the parities do not sort.
+double mode_split_coefficients(int nx, const std::vector<double>& U, std::vector<double>* fwd,
+                               std::vector<double>* bwd, std::vector<int>* perm) {
+  fwd->clear();
+  bwd->clear();
+  perm->clear();
+  if (nx % 4 != 0 || nx < 8) return 0.0;
+  const int n = nx, Q = nx / 4;
+  std::vector<double> P, Pp, Pi, Ppi;
+  butterfly_matrices(nx, &P, &Pp);
+  if (!invert(n, P, &Pi) || !invert(n, Pp, &Ppi)) return 1.0;
+  const int sizes[4] = {Q + 1, Q, Q, Q - 1};
+  const int starts[4] = {0, Q + 1, 2 * Q + 1, 3 * Q + 1};
+  auto block_of = [&](int j) {
+    int b = 0;
+    while (b < 3 && j >= starts[b + 1]) ++b;
+    return b;
+  };
+  // C = U^T P^{-1}: row m = mode m in component coordinates
+  std::vector<double> C(n * n, 0.0);
+  for (int m = 0; m < n; ++m)
+    for (int j = 0; j < n; ++j) {
+      double s = 0;
+      for (int k = 0; k < n; ++k) s += U[k * n + m] * Pi[k * n + j];
+      C[m * n + j] = s;
+    }
+  std::vector<int> blk(n);
+  for (int m = 0; m < n; ++m) {
+    int arg = 0;
+    for (int j = 1; j < n; ++j)
+      if (std::fabs(C[m * n + j]) > std::fabs(C[m * n + arg])) arg = j;
+    blk[m] = block_of(arg);
+  }
+  for (int b = 0; b < 4; ++b)
+    for (int m = 0; m < n; ++m)
+      if (blk[m] == b) perm->push_back(m);
+  for (int b = 0; b < 4; ++b) {
+    int cnt = 0;
+    for (int m = 0; m < n; ++m) cnt += blk[m] == b;
+    if (cnt != sizes[b]) return 1.0;
+  }
+  // D = Pp^{-1} U Pi^T: column i = block-ordered mode i in component coordinates
+  std::vector<double> D(n * n, 0.0);
+  for (int r = 0; r < n; ++r)
+    for (int i = 0; i < n; ++i) {
+      double s = 0;
+      for (int k = 0; k < n; ++k) s += Ppi[r * n + k] * U[k * n + (*perm)[i]];
+      D[r * n + i] = s;
+    }
+  double off = 0.0;
+  for (int i = 0; i < n; ++i)
+    for (int j = 0; j < n; ++j) {
+      if (block_of(i) == block_of(j)) continue;
+      off = std::max(off, std::fabs(C[(*perm)[i] * n + j]));
+      off = std::max(off, std::fabs(D[i * n + j]));
+    }
+  for (int b = 0; b < 4; ++b)
+    for (int i = 0; i < sizes[b]; ++i)
+      for (int k = 0; k < sizes[b]; ++k) {
+        fwd->push_back(C[(*perm)[starts[b] + i] * n + starts[b] + k]);
+        bwd->push_back(D[(starts[b] + i) * n + starts[b] + k]);
+      }
   return off;
 }
 

@@ -85,6 +85,8 @@ struct Lattice {
   Fields<float> f32;
   std::vector<double> T_host, U_host, lam1_host;  // 1D factors (host)
   std::vector<double> split_host;  // block-diagonal form of T (streaming kernel)
+  std::vector<double> mode_fwd_host, mode_bwd_host;  // block form of U^T and U
+  std::vector<int> mode_perm;       // block-ordered mode -> column of U
   int slab = 0;                    // time slices per workgroup of the streaming kernel (0: default)
   int vec_blocks = 0;              // workgroups per rhs of the vector kernels (0: default)
   DevBuf work[24];          // vector workspaces (solver / preconditioner)
