@@ -39,6 +39,8 @@ def parse():
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--precond", default="none", choices=["none", "wce2"])
     ap.add_argument("--slab", type=int, default=0, help="--mv-only: slab size (0 = default)")
+    ap.add_argument("--no-secondary", action="store_true",
+                    help="skip the WCE2-preconditioned solve reported beside the primary one")
     ap.add_argument("--no-tune", action="store_true",
                     help="skip the launch-shape autotuner (run before the timed region)")
     ap.add_argument("--report", choices=["config2", "batched", "batched_solve", "force"],
@@ -398,6 +400,35 @@ def main():
 
     diff_fp64 = float((x - x64).abs().max().item() / x64.abs().max().item())
 
+    # secondary configuration: the same solve with the weak-coupling WCE2
+    # preconditioner (Sec. 3), FP32-refined and all-FP64
+    secondary = None
+    if a.precond == "none" and not a.no_secondary:
+        pcw = Precond("wce", wce_order=2)
+
+        def solve_w(mixed):
+            return L.solve_bicgstab(b, "two_step", precond=pcw, tol=tol, mixed=mixed, maxit=20000)
+
+        solve_w(True)
+        solve_w(False)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(a.steps):
+            xw, stw = solve_w(True)
+        torch.cuda.synchronize()
+        tw = (time.perf_counter() - t0) / a.steps
+        t0 = time.perf_counter()
+        xw64, stw64 = solve_w(False)
+        torch.cuda.synchronize()
+        tw64 = time.perf_counter() - t0
+        secondary = dict(precond="wce2", seconds=round(tw, 4), iters=list(stw["iters"]),
+                         relres_steps=list(stw["relres"]), fp64_seconds=round(tw64, 4),
+                         fp64_iters=list(stw64["iters"]),
+                         fp64_relres_steps=list(stw64["relres"]),
+                         converged=bool(stw["status"] == 0 and max(stw["relres"]) <= tol),
+                         max_rel_diff_vs_unpreconditioned=float(
+                             (xw - x64).abs().max().item() / x64.abs().max().item()))
+
     # apply_M bandwidth (the dominant kernel of the solve), HIP events on the lattice
     # stream. The timed launches cycle through ROT distinct (x, y) pairs (ROT x 216 MB
     # for complex64) so that the working set exceeds the 256 MB Infinity Cache and the
@@ -479,6 +510,7 @@ def main():
         "fp64_relres_steps": list(st64["relres"]),
         "speedup_vs_fp64": round(t_fp64 / t_mixed, 3),
         "max_rel_diff_vs_fp64_solution": diff_fp64,
+        "secondary": secondary,
         "mv": mv,
         "tuning": tuned,
         "roofline": roofline,
