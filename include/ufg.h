@@ -241,6 +241,15 @@ int lattice_norm2(ufg_lattice L, const void* x, int nrhs, double* out_host);
  */
 int lattice_tune(ufg_lattice L, int slab, int vec_blocks);
 
+/*
+ * lattice_tune_slabs -- number of slabs per right-hand side of the streaming
+ *   M / M^T kernel (1..Ntau; 0 derives it from lattice_tune's slab as
+ *   ceil(Ntau / slab)). Slab s covers slices [s Ntau / n, (s + 1) Ntau / n), so
+ *   the count need not divide Ntau; it sets the grid (n x nrhs workgroups) to fit
+ *   the number of resident workgroups. Same result guarantee as lattice_tune.
+ */
+int lattice_tune_slabs(ufg_lattice L, int nslab);
+
 /* lattice_info -- nx, ntau, dtype, A of a handle (host pointers, any may be NULL). */
 int lattice_info(ufg_lattice L, int* nx, int* ntau, int* dtype, double* A);
 

@@ -350,6 +350,15 @@ int lattice_tune(ufg_lattice h, int slab, int vec_blocks) {
   return UFG_OK;
 }
 
+int lattice_tune_slabs(ufg_lattice h, int nslab) {
+  Lattice* L = check_handle(h);
+  UFG_CHECK(L != nullptr, "lattice_tune_slabs: NULL handle");
+  UFG_CHECK(nslab >= 0 && nslab <= L->ntau, "lattice_tune_slabs: nslab must be 0..ntau");
+  UFG_HIP(hipStreamSynchronize(L->stream));
+  L->nslab = nslab;
+  return UFG_OK;
+}
+
 int lattice_info(ufg_lattice h, int* nx, int* ntau, int* dtype, double* A) {
   Lattice* L = check_handle(h);
   UFG_CHECK(L != nullptr, "lattice_info: NULL handle");

@@ -248,10 +248,7 @@ int launch_hop(const Lattice& L, const HopArgs<R>& a) {
 }
 
 int hop_blocks_per_rhs(const Lattice& L) {
-  if (stream_supported(L)) {
-    const int slab = stream_slab(L);
-    return (L.ntau + slab - 1) / slab;
-  }
+  if (stream_supported(L)) return stream_nslab(L);
   int spw = 256 / (L.nx * L.nx);
   if (spw < 1) spw = 1;
   return (L.ntau + spw - 1) / spw;

@@ -32,6 +32,9 @@ template <typename R>
 int launch_basis_stream(const Lattice& L, const HopArgs<R>& a, bool forward);
 
 int stream_slab(const Lattice& L);
+// Slabs per right-hand side: slab s of nslab covers slices [s ntau / nslab,
+// (s + 1) ntau / nslab), so every slab holds floor or ceil of ntau / nslab.
+int stream_nslab(const Lattice& L);
 bool stream_supported(const Lattice& L);
 template <typename R>
 int launch_hop_stream(const Lattice& L, const HopArgs<R>& a);

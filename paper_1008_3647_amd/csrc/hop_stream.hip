@@ -241,7 +241,7 @@ __device__ __forceinline__ double wsum(double v) {
 // and W (transform of the previous one).
 template <typename R, int NX, int DIR, bool GENERAL, int SRC, int RED>
 __global__ void __launch_bounds__(NX * NX)
-    hop_stream_kernel(HopArgs<R> a, SplitCoef<R, NX> c, int ntau, int slab, int nslab) {
+    hop_stream_kernel(HopArgs<R> a, SplitCoef<R, NX> c, int ntau, int nslab) {
   constexpr int P = NX * NX, V = NX * NX * NX;
   constexpr int ES = sizeof(C2<R>), FS = sizeof(R);
   extern __shared__ __align__(16) unsigned char smem_raw[];
@@ -257,8 +257,8 @@ __global__ void __launch_bounds__(NX * NX)
   if (a.gate && a.gate[r] == 0) return;
 
   const int l = threadIdx.x;
-  const int t0 = sb * slab;
-  const int t1 = min(t0 + slab, ntau);  // exclusive
+  const int t0 = (int)((long long)sb * ntau / nslab);
+  const int t1 = (int)((long long)(sb + 1) * ntau / nslab);  // exclusive
   const long long rbase = (long long)r * ntau * V;
   const unsigned vbytes = (unsigned)ntau * V * ES;
   const unsigned fbytes = (unsigned)ntau * V * FS;
@@ -411,7 +411,7 @@ __global__ void __launch_bounds__(NX * NX)
 
 template <typename R, int NX, int DIR, bool GENERAL, int SRC, int RED>
 int launch_one(const Lattice& L, const HopArgs<R>& a, const SplitCoef<R, NX>& c, dim3 grid,
-               size_t lds, int slab, int nslab) {
+               size_t lds, int nslab) {
   static bool attr = false;
   if (!attr) {
     UFG_HIP(hipFuncSetAttribute((const void*)hop_stream_kernel<R, NX, DIR, GENERAL, SRC, RED>,
@@ -419,32 +419,31 @@ int launch_one(const Lattice& L, const HopArgs<R>& a, const SplitCoef<R, NX>& c,
     attr = true;
   }
   hipLaunchKernelGGL((hop_stream_kernel<R, NX, DIR, GENERAL, SRC, RED>), grid, dim3(NX * NX),
-                     lds, L.stream, a, c, L.ntau, slab, nslab);
+                     lds, L.stream, a, c, L.ntau, nslab);
   UFG_HIP(hipGetLastError());
   return UFG_OK;
 }
 
 template <typename R, int NX, int DIR>
 int launch_dir(const Lattice& L, const HopArgs<R>& a, const SplitCoef<R, NX>& c) {
-  const int slab = stream_slab(L);
-  const int nslab = (L.ntau + slab - 1) / slab;
+  const int nslab = stream_nslab(L);
   const size_t lds = size_t(lds_slice_elems<NX>()) * sizeof(C2<R>);
   const bool general = (a.alpha.x != 1.0 || a.alpha.y != 0.0 || a.aux != nullptr);
   const dim3 grid(nslab * a.nrhs);
   // instantiated combinations: plain apply (any reduction), the residual form
   // b - A x, and the two fused BiCGStab sources with their reductions
   if (a.src_mode == 1 && a.red_mode == 1 && !general)
-    return launch_one<R, NX, DIR, false, 1, 1>(L, a, c, grid, lds, slab, nslab);
+    return launch_one<R, NX, DIR, false, 1, 1>(L, a, c, grid, lds, nslab);
   if (a.src_mode == 2 && a.red_mode == 3 && !general)
-    return launch_one<R, NX, DIR, false, 2, 3>(L, a, c, grid, lds, slab, nslab);
+    return launch_one<R, NX, DIR, false, 2, 3>(L, a, c, grid, lds, nslab);
   if (a.src_mode == 0 && general && a.red_mode == 0)
-    return launch_one<R, NX, DIR, true, 0, 0>(L, a, c, grid, lds, slab, nslab);
+    return launch_one<R, NX, DIR, true, 0, 0>(L, a, c, grid, lds, nslab);
   if (a.src_mode == 0 && !general) {
     switch (a.red_mode) {
-      case 0: return launch_one<R, NX, DIR, false, 0, 0>(L, a, c, grid, lds, slab, nslab);
-      case 1: return launch_one<R, NX, DIR, false, 0, 1>(L, a, c, grid, lds, slab, nslab);
-      case 2: return launch_one<R, NX, DIR, false, 0, 2>(L, a, c, grid, lds, slab, nslab);
-      case 3: return launch_one<R, NX, DIR, false, 0, 3>(L, a, c, grid, lds, slab, nslab);
+      case 0: return launch_one<R, NX, DIR, false, 0, 0>(L, a, c, grid, lds, nslab);
+      case 1: return launch_one<R, NX, DIR, false, 0, 1>(L, a, c, grid, lds, nslab);
+      case 2: return launch_one<R, NX, DIR, false, 0, 2>(L, a, c, grid, lds, nslab);
+      case 3: return launch_one<R, NX, DIR, false, 0, 3>(L, a, c, grid, lds, nslab);
       default: break;
     }
   }
@@ -471,7 +470,7 @@ int launch_nx(const Lattice& L, const HopArgs<R>& a) {
 // right-hand side (XCD-aware numbering as above); the slices are independent.
 template <typename R, int NX, bool FWD, bool GENERAL>
 __global__ void __launch_bounds__(NX * NX)
-    basis_kernel(HopArgs<R> a, SplitCoef<R, NX> c, int ntau, int slab) {
+    basis_kernel(HopArgs<R> a, SplitCoef<R, NX> c, int ntau, int nslab) {
   constexpr int P = NX * NX, V = NX * NX * NX;
   extern __shared__ __align__(16) unsigned char smem_raw[];
   C2<R>* lds = reinterpret_cast<C2<R>*>(smem_raw);
@@ -483,7 +482,8 @@ __global__ void __launch_bounds__(NX * NX)
   const int sb = lid / a.nrhs;
   if (a.gate && a.gate[r] == 0) return;
   const int l = threadIdx.x;
-  const int t0 = sb * slab, t1 = min(t0 + slab, ntau);
+  const int t0 = (int)((long long)sb * ntau / nslab);
+  const int t1 = (int)((long long)(sb + 1) * ntau / nslab);
   const long long rbase = (long long)r * ntau * V;
   for (int t = t0; t < t1; ++t) {
     const long long o = rbase + (long long)t * V + l;
@@ -533,7 +533,7 @@ __global__ void __launch_bounds__(NX * NX)
 
 template <typename R, int NX, bool FWD, bool GENERAL>
 int launch_basis_one(const Lattice& L, const HopArgs<R>& a, const SplitCoef<R, NX>& c,
-                     dim3 grid, size_t lds, int slab) {
+                     dim3 grid, size_t lds, int nslab) {
   static bool attr = false;
   if (!attr) {
     UFG_HIP(hipFuncSetAttribute((const void*)basis_kernel<R, NX, FWD, GENERAL>,
@@ -541,7 +541,7 @@ int launch_basis_one(const Lattice& L, const HopArgs<R>& a, const SplitCoef<R, N
     attr = true;
   }
   hipLaunchKernelGGL((basis_kernel<R, NX, FWD, GENERAL>), grid, dim3(NX * NX), lds, L.stream, a,
-                     c, L.ntau, slab);
+                     c, L.ntau, nslab);
   UFG_HIP(hipGetLastError());
   return UFG_OK;
 }
@@ -555,16 +555,15 @@ int launch_basis_nx(const Lattice& L, const HopArgs<R>& a, bool forward) {
   for (auto& v : c.ea) v = R(h[k++]);
   for (auto& v : c.os) v = R(h[k++]);
   for (auto& v : c.oa) v = R(h[k++]);
-  const int slab = stream_slab(L);
-  const int nslab = (L.ntau + slab - 1) / slab;
+  const int nslab = stream_nslab(L);
   const size_t lds = size_t(lds_slice_elems<NX>()) * sizeof(C2<R>);
   const dim3 grid(nslab * a.nrhs);
   const bool general = (a.alpha.x != 1.0 || a.alpha.y != 0.0 || a.aux != nullptr);
   if (forward)
-    return general ? launch_basis_one<R, NX, true, true>(L, a, c, grid, lds, slab)
-                   : launch_basis_one<R, NX, true, false>(L, a, c, grid, lds, slab);
-  return general ? launch_basis_one<R, NX, false, true>(L, a, c, grid, lds, slab)
-                 : launch_basis_one<R, NX, false, false>(L, a, c, grid, lds, slab);
+    return general ? launch_basis_one<R, NX, true, true>(L, a, c, grid, lds, nslab)
+                   : launch_basis_one<R, NX, true, false>(L, a, c, grid, lds, nslab);
+  return general ? launch_basis_one<R, NX, false, true>(L, a, c, grid, lds, nslab)
+                 : launch_basis_one<R, NX, false, false>(L, a, c, grid, lds, nslab);
 }
 
 }  // namespace
@@ -572,6 +571,12 @@ int launch_basis_nx(const Lattice& L, const HopArgs<R>& a, bool forward) {
 int stream_slab(const Lattice& L) {
   if (L.slab > 0) return std::min(L.slab, L.ntau);
   return std::min(2, L.ntau);  // best measured for 16^3 slices with HBM-resident data
+}
+
+int stream_nslab(const Lattice& L) {
+  if (L.nslab > 0) return std::min(L.nslab, L.ntau);
+  const int slab = stream_slab(L);
+  return (L.ntau + slab - 1) / slab;
 }
 
 bool stream_supported(const Lattice& L) {

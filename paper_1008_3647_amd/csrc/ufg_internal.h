@@ -88,6 +88,7 @@ struct Lattice {
   std::vector<double> mode_fwd_host, mode_bwd_host;  // block form of U^T and U
   std::vector<int> mode_perm;       // block-ordered mode -> column of U
   int slab = 0;                    // time slices per workgroup of the streaming kernel (0: default)
+  int nslab = 0;                   // slabs per rhs of the streaming kernel (0: from slab)
   int vec_blocks = 0;              // workgroups per rhs of the vector kernels (0: default)
   DevBuf work[24];          // vector workspaces (solver / preconditioner)
   DevBuf red;               // reduction partials

@@ -144,9 +144,11 @@ class Lattice:
         L.check(code, "solve_bicgstab")
         return x, st.as_dict()
 
-    def tune(self, slab=0, vec_blocks=0):
-        """Launch parameters (0 = library default); see lattice_tune in ufg.h."""
+    def tune(self, slab=0, vec_blocks=0, nslab=0):
+        """Launch parameters (0 = library default); see lattice_tune and
+        lattice_tune_slabs in ufg.h (nslab, when given, overrides slab)."""
         L.check(self._lib.lattice_tune(self._h, int(slab), int(vec_blocks)), "lattice_tune")
+        L.check(self._lib.lattice_tune_slabs(self._h, int(nslab)), "lattice_tune_slabs")
 
     def norm2(self, x):
         """||x_r||^2 per right-hand side (host list), FP64 accumulation."""
