@@ -281,7 +281,7 @@ __global__ void __launch_bounds__(NX * NX)
   const int step = (DIR < 0) ? 1 : -1;
   const int th = (DIR < 0) ? ((t0 == 0) ? ntau - 1 : t0 - 1) : ((t1 == ntau) ? 0 : t1);
 
-  double acc0 = 0, acc1 = 0, acc2 = 0, acc3 = 0;
+  double acc0 = 0, acc1 = 0, acc2 = 0, acc3 = 0, acc4 = 0, acc5 = 0, acc6 = 0, acc7 = 0;
   C2<R> W[NX], X[NX];
   load_source<R, NX, SRC>(b, q, th * V * ES, vo, W);
   if (DIR < 0) scale_field<R, NX>(b.pre, th * V * FS, fo, W);
@@ -304,7 +304,7 @@ __global__ void __launch_bounds__(NX * NX)
     // chunk (field, aux, reduction weights) are loaded ahead of its stores
     // (loads cannot be moved across buffer stores). complex128 with a
     // reduction uses half-slice chunks to stay within the register file.
-    constexpr int ZC = (sizeof(R) == 8 && (GENERAL || RED != 0)) ? NX / 2 : NX;
+    constexpr int ZC = ((sizeof(R) == 8 && (GENERAL || RED != 0)) || RED == 4) ? NX / 2 : NX;
 #pragma unroll
     for (int z0 = 0; z0 < NX; z0 += ZC) {
       R F[DIR > 0 ? ZC : 1];
@@ -318,8 +318,8 @@ __global__ void __launch_bounds__(NX * NX)
 #pragma unroll
         for (int j = 0; j < ZC; ++j) U[j] = bload<R>(b.aux, vo, so + (z0 + j) * P * ES);
       }
-      C2<R> Wr[(RED == 1 || RED == 2) ? ZC : 1];
-      if (RED == 1 || RED == 2) {
+      C2<R> Wr[(RED == 1 || RED == 2 || RED == 4) ? ZC : 1];
+      if (RED == 1 || RED == 2 || RED == 4) {
 #pragma unroll
         for (int j = 0; j < ZC; ++j) Wr[j] = bload<R>(b.rw, vo, so + (z0 + j) * P * ES);
       }
@@ -361,11 +361,18 @@ __global__ void __launch_bounds__(NX * NX)
           acc1 += double(out.x) * u.y - double(out.y) * u.x;
           acc2 += double(out.x) * out.x + double(out.y) * out.y;
           acc3 += double(u.x) * u.x + double(u.y) * u.y;
-        } else if (RED == 3) {  // <out, source>, |out|^2, |source|^2
+        } else if (RED == 3 || RED == 4) {  // <out, source>, |out|^2, |source|^2
           acc0 += double(out.x) * id.x + double(out.y) * id.y;
           acc1 += double(out.x) * id.y - double(out.y) * id.x;
           acc2 += double(out.x) * out.x + double(out.y) * out.y;
           acc3 += double(id.x) * id.x + double(id.y) * id.y;
+          if (RED == 4) {  // <w, out>, <w, source>
+            const C2<R> u = Wr[RED == 4 ? j : 0];
+            acc4 += double(u.x) * out.x + double(u.y) * out.y;
+            acc5 += double(u.x) * out.y - double(u.y) * out.x;
+            acc6 += double(u.x) * id.x + double(u.y) * id.y;
+            acc7 += double(u.x) * id.y - double(u.y) * id.x;
+          }
         }
       }
     }
@@ -378,33 +385,31 @@ __global__ void __launch_bounds__(NX * NX)
     }
   }
   if (RED != 0) {
-    acc0 = wsum(acc0);
-    acc1 = wsum(acc1);
-    acc2 = wsum(acc2);
-    acc3 = wsum(acc3);
+    constexpr int NR = (RED == 4) ? 8 : 4;
+    double acc[NR];
+    acc[0] = wsum(acc0);
+    acc[1] = wsum(acc1);
+    acc[2] = wsum(acc2);
+    acc[3] = wsum(acc3);
+    if (RED == 4) {
+      acc[NR - 4] = wsum(acc4);
+      acc[NR - 3] = wsum(acc5);
+      acc[NR - 2] = wsum(acc6);
+      acc[NR - 1] = wsum(acc7);
+    }
     __syncthreads();
     double* sm = reinterpret_cast<double*>(smem_raw);
     const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
     if (lane == 0) {
-      sm[wid * 4 + 0] = acc0;
-      sm[wid * 4 + 1] = acc1;
-      sm[wid * 4 + 2] = acc2;
-      sm[wid * 4 + 3] = acc3;
+#pragma unroll
+      for (int j = 0; j < NR; ++j) sm[wid * NR + j] = acc[j];
     }
     __syncthreads();
-    if (threadIdx.x == 0) {
-      double s0 = 0, s1 = 0, s2 = 0, s3 = 0;
-      for (int w = 0; w < (P + 63) / 64; ++w) {
-        s0 += sm[w * 4 + 0];
-        s1 += sm[w * 4 + 1];
-        s2 += sm[w * 4 + 2];
-        s3 += sm[w * 4 + 3];
-      }
-      double* out = a.red_out + ((long long)r * nslab + sb) * 4;
-      out[0] = s0;
-      out[1] = s1;
-      out[2] = s2;
-      out[3] = s3;
+    if (threadIdx.x < NR) {
+      const int j = threadIdx.x;
+      double v = 0;
+      for (int w = 0; w < (P + 63) / 64; ++w) v += sm[w * NR + j];
+      a.red_out[((long long)r * nslab + sb) * NR + j] = v;
     }
   }
 }
@@ -436,6 +441,8 @@ int launch_dir(const Lattice& L, const HopArgs<R>& a, const SplitCoef<R, NX>& c)
     return launch_one<R, NX, DIR, false, 1, 1>(L, a, c, grid, lds, nslab);
   if (a.src_mode == 2 && a.red_mode == 3 && !general)
     return launch_one<R, NX, DIR, false, 2, 3>(L, a, c, grid, lds, nslab);
+  if (a.src_mode == 2 && a.red_mode == 4 && !general && a.red_w != nullptr)
+    return launch_one<R, NX, DIR, false, 2, 4>(L, a, c, grid, lds, nslab);
   if (a.src_mode == 0 && general && a.red_mode == 0)
     return launch_one<R, NX, DIR, true, 0, 0>(L, a, c, grid, lds, nslab);
   if (a.src_mode == 0 && !general) {

@@ -33,7 +33,8 @@ struct KrylovState {
   int* active = nullptr;
   int* update = nullptr;
   int* restart = nullptr;
-  double* part = nullptr;  // [nrhs][nblk][4]
+  double* part = nullptr;   // [nrhs][nblk][4] (8 per block for the streaming reduction mode 4)
+  double* part2 = nullptr;  // [nrhs][vector blocks][4]: partials kept across one operator launch
   KrylovParams prm{};
 };
 
@@ -49,7 +50,9 @@ enum FinOp {
   FIN_CG_R,
   FIN_CG_BETA,
   FIN_CG_INIT_RZ,
-  FIN_NORM
+  FIN_NORM,
+  FIN_ALPHA_XR,   // |r|^2 of the deferred x, r update (part2), then alpha (part)
+  FIN_OMEGA_RHO   // omega, then rho of the next iteration from <rhat, s>, <rhat, t>
 };
 
 int vec_blocks(const Lattice& L, int nrhs);
@@ -64,6 +67,12 @@ int k_bicg_xr(const Lattice& L, C2<R>* x, const C2<R>* phat, const C2<R>* shat, 
 template <typename R>
 int k_bicg_xr_fused(const Lattice& L, C2<R>* x, const C2<R>* p, C2<R>* r, const C2<R>* v,
                     const C2<R>* t, const C2<R>* rhat, const KrylovState& K);
+// x, r update of one iteration merged with the p update of the next:
+// s = r - alpha v, x += alpha p + omega s, r = s - omega t,
+// p = r + beta (p - omega v); |r|^2 partials into K.part2.
+template <typename R>
+int k_bicg_xrp(const Lattice& L, C2<R>* x, C2<R>* p, C2<R>* r, const C2<R>* v, const C2<R>* t,
+               const KrylovState& K);
 template <typename R>
 int k_reduce(const Lattice& L, const C2<R>* a, const C2<R>* b, int mode, const int* gate,
              const KrylovState& K);
@@ -85,7 +94,11 @@ int k_cg_p(const Lattice& L, const C2<R>* z, C2<R>* p, const KrylovState& K);
 template <typename R>
 int k_restart(const Lattice& L, const C2<R>* r, C2<R>* rhat, C2<R>* p, C2<R>* v,
               const KrylovState& K);
-int k_finalize(const Lattice& L, int op, int nblk, const int* gate, const KrylovState& K);
+// Sums `nblk` partials of `stride` (4 or 8) doubles per rhs from K.part into
+// s[0 .. stride), and, with nblk2 > 0, nblk2 partials of 4 from K.part2 into
+// s[4 .. 8); then applies `op` to the state.
+int k_finalize(const Lattice& L, int op, int nblk, const int* gate, const KrylovState& K,
+               int stride = 4, int nblk2 = 0);
 // Partials of rhs (segment) k are part[first[k] .. first[k] + count[k]) (4 doubles each).
 int k_finalize_seg(hipStream_t stream, int op, const double* part, const int* first,
                    const int* count, const int* gate, const KrylovState& K);

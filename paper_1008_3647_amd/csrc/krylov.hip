@@ -156,6 +156,40 @@ __global__ void __launch_bounds__(256) bicg_xr_fused_kernel(C2<R>* x, const C2<R
   bsum4(d0, d1, d2, 0.0, part + ((long long)k * gridDim.x + blockIdx.x) * 4);
 }
 
+// The x, r update of one iteration merged with the p update of the next
+// (beta from the rho that FIN_OMEGA_RHO derived): s = r - alpha v,
+// x += alpha p + omega s, r = s - omega t, p = r + beta (p - omega v);
+// partial |r|^2 in slot 2.
+template <typename R>
+__global__ void __launch_bounds__(256) bicg_xrp_kernel(C2<R>* x, C2<R>* p, C2<R>* r,
+                                                       const C2<R>* v, const C2<R>* t,
+                                                       const RhsState* st, const int* active,
+                                                       long long n, double* part) {
+  const int k = blockIdx.y;
+  if (!active[k]) return;
+  const RhsState q = st[k];
+  const R ar = R(q.alpha.x), ai = R(q.alpha.y), wr = R(q.omega.x), wi = R(q.omega.y);
+  const R br = R(q.beta.x), bi = R(q.beta.y);
+  const long long off = (long long)k * n;
+  double d2 = 0;
+  KR_LOOP(n) {
+    const long long j = off + i;
+    const C2<R> pv = p[j], vv = v[j], tv = t[j], rv = r[j];
+    C2<R> xv = x[j];
+    const C2<R> sv = c2<R>(rv.x - (ar * vv.x - ai * vv.y), rv.y - (ar * vv.y + ai * vv.x));
+    xv.x += (ar * pv.x - ai * pv.y) + (wr * sv.x - wi * sv.y);
+    xv.y += (ar * pv.y + ai * pv.x) + (wr * sv.y + wi * sv.x);
+    x[j] = xv;
+    const C2<R> rn = c2<R>(sv.x - (wr * tv.x - wi * tv.y), sv.y - (wr * tv.y + wi * tv.x));
+    r[j] = rn;
+    const R dx = pv.x - (wr * vv.x - wi * vv.y);
+    const R dy = pv.y - (wr * vv.y + wi * vv.x);
+    p[j] = c2<R>(rn.x + br * dx - bi * dy, rn.y + br * dy + bi * dx);
+    d2 += double(rn.x) * rn.x + double(rn.y) * rn.y;
+  }
+  bsum4(0.0, 0.0, d2, 0.0, part + ((long long)k * gridDim.x + blockIdx.x) * 4);
+}
+
 // Generic reductions: mode 0 |a|^2 -> [2]; mode 1 <a, b> -> [0,1];
 // mode 2 <a, b> -> [0,1] and |a|^2 -> [2]; mode 3 <b, a> -> [0,1] and |a|^2 -> [2].
 template <typename R>
@@ -303,10 +337,11 @@ __global__ void __launch_bounds__(256) restart_kernel(const C2<R>* r, C2<R>* rha
   }
 }
 
-// Scalar update of one rhs from its summed partials (s0, s1, s2).
-__device__ void apply_fin(int op, int k, double s0, double s1, double s2, double s3, RhsState* st,
-                          int* active, int* update, int* restart, const KrylovParams& prm) {
-  RhsState q = st[k];
+// Scalar update of one rhs from its summed partials s[0..8).
+// The state and the flags of the rhs are held in registers by the caller.
+__device__ void apply_fin(int op, const double* s, RhsState& q, int& act, int& upd, int& rst,
+                          const KrylovParams& prm) {
+  const double s0 = s[0], s1 = s[1], s2 = s[2], s3 = s[3];
   const double2 d01 = double2{s0, s1};
   switch (op) {
     case FIN_INIT_B:  // |b|^2
@@ -322,14 +357,14 @@ __device__ void apply_fin(int op, int k, double s0, double s1, double s2, double
       q.iters = 0;
       q.updates = 0;
       q.conv = (s2 <= q.tol2) ? 1 : 0;
-      active[k] = q.conv ? 0 : 1;
-      update[k] = 0;
-      restart[k] = 0;
+      act = q.conv ? 0 : 1;
+      upd = 0;
+      rst = 0;
       q.status = 0;
       break;
     case FIN_ALPHA:  // alpha = rho / <rhat, v>
       if (d01.x == 0.0 && d01.y == 0.0) {
-        restart[k] = 1;
+        rst = 1;
         q.alpha = double2{0.0, 0.0};
       } else {
         q.alpha = cdiv(q.rho, d01);
@@ -358,11 +393,11 @@ __device__ void apply_fin(int op, int k, double s0, double s1, double s2, double
       q.r2 = s2;
       q.iters += 1;
       if (!(s2 == s2) || s2 > 1e300) {  // NaN / overflow: stop this rhs
-        active[k] = 0;
+        act = 0;
         q.status = UFG_BREAKDOWN;
         break;
       }
-      if (q.omega.x == 0.0 && q.omega.y == 0.0 && s2 > q.tol2) restart[k] = 1;
+      if (q.omega.x == 0.0 && q.omega.y == 0.0 && s2 > q.tol2) rst = 1;
       // beta of the next p-update; undefined after omega = 0 or rho_old = 0
       // (then p restarts from r, and the restart flag renews rhat)
       if ((q.rho_old.x != 0.0 || q.rho_old.y != 0.0) && (q.omega.x != 0.0 || q.omega.y != 0.0))
@@ -372,14 +407,14 @@ __device__ void apply_fin(int op, int k, double s0, double s1, double s2, double
       if (s2 <= q.tol2) {
         // verify with a recomputed residual; no further iterations until then
         // (this is the end of an iteration, so the state stays consistent)
-        update[k] = 1;
-        active[k] = 0;
+        upd = 1;
+        act = 0;
       } else if (prm.mixed && s2 < prm.delta2 * q.maxr2) {
-        update[k] = 1;
+        upd = 1;
       }
       if (s2 > q.maxr2) q.maxr2 = s2;
       // near breakdown of the bi-orthogonality: restart with rhat = r
-      if (!update[k] && (d01.x * d01.x + d01.y * d01.y) < 1e-28 * q.rhat2 * s2) restart[k] = 1;
+      if (!upd && (d01.x * d01.x + d01.y * d01.y) < 1e-28 * q.rhat2 * s2) rst = 1;
       break;
     }
     case FIN_UPDATE:  // reliable update done: r is b - A x
@@ -393,12 +428,12 @@ __device__ void apply_fin(int op, int k, double s0, double s1, double s2, double
         else
           q.beta = double2{0.0, 0.0};
       }
-      update[k] = 0;
+      upd = 0;
       if (s2 <= q.tol2) {
         q.conv = 1;
-        active[k] = 0;
+        act = 0;
       } else if (q.status == 0) {
-        active[k] = 1;  // the iterated residual met tol, the true one did not
+        act = 1;  // the iterated residual met tol, the true one did not
       }
       break;
     case FIN_RESTART:  // rhat = r: rho = |r|^2, scalars reset
@@ -406,11 +441,11 @@ __device__ void apply_fin(int op, int k, double s0, double s1, double s2, double
       q.rhat2 = q.r2;
       q.rho_old = q.alpha = q.omega = double2{1.0, 0.0};
       q.beta = double2{0.0, 0.0};
-      restart[k] = 0;
+      rst = 0;
       break;
     case FIN_CG_ALPHA:  // alpha = rz / <p, w>
       if (d01.x == 0.0 && d01.y == 0.0) {
-        active[k] = 0;
+        act = 0;
         q.status = UFG_BREAKDOWN;
         q.alpha = double2{0.0, 0.0};
       } else {
@@ -421,16 +456,16 @@ __device__ void apply_fin(int op, int k, double s0, double s1, double s2, double
       q.r2 = s2;
       q.iters += 1;
       if (!(s2 == s2) || s2 > 1e300) {
-        active[k] = 0;
+        act = 0;
         q.status = UFG_BREAKDOWN;
         break;
       }
       // CG keeps iterating until the check point verifies (the rest of this
       // iteration, beta and p, still has to run for a consistent state)
       if (s2 <= q.tol2) {
-        update[k] = 1;
+        upd = 1;
       } else if (prm.mixed && s2 < prm.delta2 * q.maxr2) {
-        update[k] = 1;
+        upd = 1;
       }
       if (s2 > q.maxr2) q.maxr2 = s2;
       break;
@@ -446,28 +481,125 @@ __device__ void apply_fin(int op, int k, double s0, double s1, double s2, double
     case FIN_NORM:  // true residual norm into r2 (no flags)
       q.r2 = s2;
       break;
+    case FIN_ALPHA_XR: {
+      // s[6] = |r|^2 after the deferred x, r update (the checks of FIN_RHO,
+      // with rho from FIN_OMEGA_RHO), then alpha = rho / <rhat, v> from s0, s1
+      const double r2 = s[6];
+      q.r2 = r2;
+      q.iters += 1;
+      if (!(r2 == r2) || r2 > 1e300) {
+        act = 0;
+        q.status = UFG_BREAKDOWN;
+        break;
+      }
+      if (q.omega.x == 0.0 && q.omega.y == 0.0 && r2 > q.tol2) rst = 1;
+      if (r2 <= q.tol2) {
+        // stop and verify; p already holds the next direction, so a rhs the
+        // check sends back to work restarts from its recomputed residual
+        upd = 1;
+        rst = 1;
+        act = 0;
+      } else if (prm.mixed && r2 < prm.delta2 * q.maxr2) {
+        upd = 1;
+      }
+      if (r2 > q.maxr2) q.maxr2 = r2;
+      if (!upd && (q.rho.x * q.rho.x + q.rho.y * q.rho.y) < 1e-28 * q.rhat2 * r2)
+        rst = 1;
+      if (!act) break;
+      if (d01.x == 0.0 && d01.y == 0.0) {
+        rst = 1;
+        q.alpha = double2{0.0, 0.0};
+      } else {
+        q.alpha = cdiv(q.rho, d01);
+      }
+      break;
+    }
+    case FIN_OMEGA_RHO: {
+      // omega as FIN_OMEGA; r_new = s - omega t gives
+      // rho_new = <rhat, r_new> = <rhat, s> - omega <rhat, t> (s[6,7], s[4,5])
+      if (s2 > 0.0) {
+        double2 w = double2{s0 / s2, s1 / s2};
+        const double c = std::sqrt((s0 * s0 + s1 * s1) / (s2 * s3));
+        if (prm.limit_omega && s3 > 0.0 && c < 0.7 && c > 0.0) {
+          w.x *= 0.7 / c;
+          w.y *= 0.7 / c;
+        }
+        q.omega = w;
+      } else {
+        q.omega = double2{0.0, 0.0};
+      }
+      const double2 wt = cmul(q.omega, double2{s[4], s[5]});
+      q.rho_old = q.rho;
+      q.rho = double2{s[6] - wt.x, s[7] - wt.y};
+      if ((q.rho_old.x != 0.0 || q.rho_old.y != 0.0) && (q.omega.x != 0.0 || q.omega.y != 0.0))
+        q.beta = cmul(cdiv(q.rho, q.rho_old), cdiv(q.alpha, q.omega));
+      else
+        q.beta = double2{0.0, 0.0};
+      break;
+    }
   }
-  st[k] = q;
 }
-// One block per rhs: sum `nblk` partials (fixed order) and apply `op` to the state.
+// One block per rhs: sum `nblk` partials of `stride` doubles (fixed order)
+// into s[0..stride), and nblk2 partials of 4 from part2 into s[4..8), then
+// apply `op`. NV: number of sums (4, or 8 with stride 8 or part2).
+template <int NV>
 __global__ void __launch_bounds__(256) finalize_kernel(int op, const double* part, int nblk,
-                                                       RhsState* st, int* active, int* update,
-                                                       int* restart, const int* gate,
-                                                       KrylovParams prm) {
+                                                       int stride, const double* part2,
+                                                       int nblk2, RhsState* st, int* active,
+                                                       int* update, int* restart,
+                                                       const int* gate, KrylovParams prm) {
   const int k = blockIdx.x;
   if (gate && !gate[k]) return;
-  double s0 = 0, s1 = 0, s2 = 0, s3 = 0;
-  for (int b = threadIdx.x; b < nblk; b += 256) {
-    const double* q = part + ((long long)k * nblk + b) * 4;
-    s0 += q[0];
-    s1 += q[1];
-    s2 += q[2];
-    s3 += q[3];
+  // the state is fetched while the partials are summed
+  RhsState q;
+  int act = 0, upd = 0, rst = 0;
+  if (threadIdx.x == 0) {
+    q = st[k];
+    act = active[k];
+    upd = update[k];
+    rst = restart[k];
   }
-  __shared__ double out[4];
-  bsum4(s0, s1, s2, s3, out);
+  double a[NV];
+#pragma unroll
+  for (int j = 0; j < NV; ++j) a[j] = 0.0;
+  if (NV == 8 && stride == 8) {
+    for (int b = threadIdx.x; b < nblk; b += 256) {
+      const double* q = part + ((long long)k * nblk + b) * 8;
+#pragma unroll
+      for (int j = 0; j < NV; ++j) a[j] += q[j];
+    }
+  } else {
+    for (int b = threadIdx.x; b < nblk; b += 256) {
+      const double* q = part + ((long long)k * nblk + b) * 4;
+#pragma unroll
+      for (int j = 0; j < 4; ++j) a[j] += q[j];
+    }
+    if (NV == 8) {
+      for (int b = threadIdx.x; b < nblk2; b += 256) {
+        const double* q = part2 + ((long long)k * nblk2 + b) * 4;
+#pragma unroll
+        for (int j = 0; j < 4; ++j) a[NV - 4 + j] += q[j];
+      }
+    }
+  }
+  __shared__ double sm[4][NV];
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+#pragma unroll
+  for (int j = 0; j < NV; ++j) {
+    a[j] = wsum(a[j]);
+    if (lane == 0) sm[wid][j] = a[j];
+  }
+  __syncthreads();
   if (threadIdx.x != 0) return;
-  apply_fin(op, k, out[0], out[1], out[2], out[3], st, active, update, restart, prm);
+  double s[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+  for (int w = 0; w < 4; ++w)
+#pragma unroll
+    for (int j = 0; j < NV; ++j) s[j] += sm[w][j];
+  apply_fin(op, s, q, act, upd, rst, prm);
+  st[k] = q;
+  active[k] = act;
+  update[k] = upd;
+  restart[k] = rst;
 }
 
 // Segmented variant: rhs (segment) k owns partials [first[k], first[k] + count[k]).
@@ -478,6 +610,14 @@ __global__ void __launch_bounds__(256) finalize_seg_kernel(int op, const double*
                                                            const int* gate, KrylovParams prm) {
   const int k = blockIdx.x;
   if (gate && !gate[k]) return;
+  RhsState q;
+  int act = 0, upd = 0, rst = 0;
+  if (threadIdx.x == 0) {
+    q = st[k];
+    act = active[k];
+    upd = update[k];
+    rst = restart[k];
+  }
   double s0 = 0, s1 = 0, s2 = 0, s3 = 0;
   const int f = first[k], c = count[k];
   for (int b = threadIdx.x; b < c; b += 256) {
@@ -490,7 +630,12 @@ __global__ void __launch_bounds__(256) finalize_seg_kernel(int op, const double*
   __shared__ double out[4];
   bsum4(s0, s1, s2, s3, out);
   if (threadIdx.x != 0) return;
-  apply_fin(op, k, out[0], out[1], out[2], out[3], st, active, update, restart, prm);
+  const double s[8] = {out[0], out[1], out[2], out[3], 0, 0, 0, 0};
+  apply_fin(op, s, q, act, upd, rst, prm);
+  st[k] = q;
+  active[k] = act;
+  update[k] = upd;
+  restart[k] = rst;
 }
 
 }  // namespace
@@ -538,6 +683,17 @@ int k_bicg_xr_fused(const Lattice& L, C2<R>* x, const C2<R>* p, C2<R>* r, const 
                     const C2<R>* t, const C2<R>* rhat, const KrylovState& K) {
   hipLaunchKernelGGL((bicg_xr_fused_kernel<R>), vgrid(L.N, K.nrhs), dim3(256), 0, L.stream, x, p,
                      r, v, t, rhat, K.st, K.active, L.N, K.part);
+  return UFG_OK;
+}
+template <typename R>
+int k_bicg_xrp(const Lattice& L, C2<R>* x, C2<R>* p, C2<R>* r, const C2<R>* v, const C2<R>* t,
+               const KrylovState& K) {
+  if (K.part2 == nullptr) {
+    set_error("k_bicg_xrp: no second partials buffer");
+    return UFG_EINVAL;
+  }
+  hipLaunchKernelGGL((bicg_xrp_kernel<R>), vgrid(L.N, K.nrhs), dim3(256), 0, L.stream, x, p, r,
+                     v, t, K.st, K.active, L.N, K.part2);
   return UFG_OK;
 }
 template <typename R>
@@ -596,9 +752,19 @@ int k_finalize_seg(hipStream_t stream, int op, const double* part, const int* fi
                      count, K.st, K.active, K.update, K.restart, gate, K.prm);
   return UFG_OK;
 }
-int k_finalize(const Lattice& L, int op, int nblk, const int* gate, const KrylovState& K) {
-  hipLaunchKernelGGL(finalize_kernel, dim3(K.nrhs), dim3(256), 0, L.stream, op, K.part, nblk, K.st,
-                     K.active, K.update, K.restart, gate, K.prm);
+int k_finalize(const Lattice& L, int op, int nblk, const int* gate, const KrylovState& K,
+               int stride, int nblk2) {
+  if ((stride != 4 && stride != 8) || (nblk2 > 0 && (stride != 4 || K.part2 == nullptr))) {
+    set_error("k_finalize: bad partials layout");
+    return UFG_EINVAL;
+  }
+  if (stride == 8 || nblk2 > 0)
+    hipLaunchKernelGGL(finalize_kernel<8>, dim3(K.nrhs), dim3(256), 0, L.stream, op, K.part, nblk,
+                       stride, K.part2, nblk2, K.st, K.active, K.update, K.restart, gate, K.prm);
+  else
+    hipLaunchKernelGGL(finalize_kernel<4>, dim3(K.nrhs), dim3(256), 0, L.stream, op, K.part, nblk,
+                       stride, K.part2, nblk2, K.st, K.active, K.update, K.restart, gate, K.prm);
+  UFG_HIP(hipGetLastError());
   return UFG_OK;
 }
 
@@ -611,6 +777,8 @@ int k_finalize(const Lattice& L, int op, int nblk, const int* gate, const Krylov
                             const C2<R>*, C2<R>*, const C2<R>*, const KrylovState&);             \
   template int k_bicg_xr_fused<R>(const Lattice&, C2<R>*, const C2<R>*, C2<R>*, const C2<R>*,   \
                                   const C2<R>*, const C2<R>*, const KrylovState&);               \
+  template int k_bicg_xrp<R>(const Lattice&, C2<R>*, C2<R>*, C2<R>*, const C2<R>*, const C2<R>*, \
+                             const KrylovState&);                                                \
   template int k_reduce<R>(const Lattice&, const C2<R>*, const C2<R>*, int, const int*,          \
                            const KrylovState&);                                                  \
   template int k_axpby<R>(const Lattice&, double2, const C2<R>*, double2, C2<R>*, int,           \

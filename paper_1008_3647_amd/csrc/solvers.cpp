@@ -169,11 +169,19 @@ int bicgstab_step(Lattice& L, const PcPlan& pc, int op, const C2<RO>* b, C2<RO>*
   }
   UFG_TRY(k_finalize(L, FIN_INIT_R, nvb, nullptr, K));
 
-  // Unpreconditioned BiCGStab with the streaming operator runs fused: the
-  // p update rides on the first operator launch, s = r - alpha v is formed on
-  // the fly by the second one and recomputed by the x/r update, so s is never
-  // stored. p and v alternate between two buffers (a workgroup reads the halo
-  // slice of the previous iterate while its neighbour writes the new one).
+  // Unpreconditioned BiCGStab with the streaming operator runs fused. s = r -
+  // alpha v is formed on the fly by the second operator launch (t = A s) and
+  // again by the x, r update, so s is never stored. Between check points the
+  // x, r update of an iteration is merged with the p update of the next one
+  // (one vector pass instead of two): the second operator launch also reduces
+  // <rhat, s> and <rhat, t>, which give rho of the next iteration as
+  // <rhat, r - alpha v - omega t> before r is formed, hence beta; the first
+  // launch of the next iteration is then a plain v = A p. Iterations that end
+  // at a check point run the separate x, r update (rho from r itself) so that
+  // x and r are current there, and the iteration after a check point forms p
+  // inside the first operator launch; p and v then alternate between two
+  // buffers (a workgroup reads the halo slice of the previous iterate while
+  // its neighbour writes the new one).
   const bool fused = !need_pc && stream_supported(L);
   C2<RI>* P2[2] = {V.p, nullptr};
   C2<RI>* V2[2] = {V.v, nullptr};
@@ -211,20 +219,15 @@ int bicgstab_step(Lattice& L, const PcPlan& pc, int op, const C2<RO>* b, C2<RO>*
   int it = 0;
   bool done = false;
   UFG_TRY(read_flags(L, K, hflags.data(), &done));
+  int cur = 0;          // P2[cur], V2[cur] hold the current p and v
+  bool merged = false;  // p was formed by the merged x, r, p update
   for (it = 0; it < o.maxit && !done; ++it) {
+    const bool check_it = (it + 1) % check == 0 || it + 1 == o.maxit;
     if (fused) {
-      const int cur = it & 1;
-      HopArgs<RI> a1;  // v_new = A p_new, p_new = r + beta (p - omega v); <rhat, v_new>
-      a1.src = a1.id = P2[cur ^ 1];
-      a1.dst = V2[cur ^ 1];
+      HopArgs<RI> a1;  // v = A p; <rhat, v>
       a1.mat = F.T;
       a1.nrhs = nrhs;
       a1.gate = K.active;
-      a1.src_mode = 1;
-      a1.fr = V.r;
-      a1.fp = P2[cur];
-      a1.fv = V2[cur];
-      a1.fpnew = P2[cur ^ 1];
       a1.st = K.st;
       a1.red_mode = 1;
       a1.red_w = V.rhat;
@@ -236,21 +239,44 @@ int bicgstab_step(Lattice& L, const PcPlan& pc, int op, const C2<RO>* b, C2<RO>*
         a1.shift = kShiftMdag;
         a1.post = F.b;
       }
-      UFG_TRY(launch_hop<RI>(L, a1));
-      UFG_TRY(k_finalize(L, FIN_ALPHA, nhb, K.active, K));
-      HopArgs<RI> a2 = a1;  // t = A s, s = r - alpha v_new; <t, s>, |t|^2
-      a2.src = a2.id = V2[cur ^ 1];
+      if (merged) {
+        a1.src = a1.id = P2[cur];
+        a1.dst = V2[cur];
+        UFG_TRY(launch_hop<RI>(L, a1));
+        UFG_TRY(k_finalize(L, FIN_ALPHA_XR, nhb, K.active, K, 4, nvb));
+      } else {  // p_new = r + beta (p - omega v) formed by the launch
+        a1.src = a1.id = P2[cur ^ 1];
+        a1.dst = V2[cur ^ 1];
+        a1.src_mode = 1;
+        a1.fr = V.r;
+        a1.fp = P2[cur];
+        a1.fv = V2[cur];
+        a1.fpnew = P2[cur ^ 1];
+        UFG_TRY(launch_hop<RI>(L, a1));
+        UFG_TRY(k_finalize(L, FIN_ALPHA, nhb, K.active, K));
+        cur ^= 1;
+      }
+      HopArgs<RI> a2 = a1;  // t = A s, s = r - alpha v; <t, s>, |t|^2, |s|^2, <rhat, t>, <rhat, s>
+      a2.src = a2.id = V2[cur];
       a2.dst = V.t;
       a2.src_mode = 2;
-      a2.fv = V2[cur ^ 1];
+      a2.fr = V.r;
+      a2.fv = V2[cur];
       a2.fp = nullptr;
       a2.fpnew = nullptr;
-      a2.red_mode = 3;
-      a2.red_w = nullptr;
+      a2.red_mode = check_it ? 3 : 4;
+      a2.red_w = check_it ? nullptr : V.rhat;
       UFG_TRY(launch_hop<RI>(L, a2));
-      UFG_TRY(k_finalize(L, FIN_OMEGA, nhb, K.active, K));
-      UFG_TRY(k_bicg_xr_fused<RI>(L, V.x, P2[cur ^ 1], V.r, V2[cur ^ 1], V.t, V.rhat, K));
-      UFG_TRY(k_finalize(L, FIN_RHO, nvb, K.active, K));
+      if (check_it) {
+        UFG_TRY(k_finalize(L, FIN_OMEGA, nhb, K.active, K));
+        UFG_TRY(k_bicg_xr_fused<RI>(L, V.x, P2[cur], V.r, V2[cur], V.t, V.rhat, K));
+        UFG_TRY(k_finalize(L, FIN_RHO, nvb, K.active, K));
+        merged = false;
+      } else {
+        UFG_TRY(k_finalize(L, FIN_OMEGA_RHO, nhb, K.active, K, 8));
+        UFG_TRY(k_bicg_xrp<RI>(L, V.x, P2[cur], V.r, V2[cur], V.t, K));
+        merged = true;
+      }
     } else {
       UFG_TRY(k_bicg_p<RI>(L, V.r, V.p, V.v, K));
       if (need_pc) UFG_TRY(pc_apply<RI>(L, pc, op, V.p, V.phat, nrhs, K.active, cnt));

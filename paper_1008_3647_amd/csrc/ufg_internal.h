@@ -133,9 +133,11 @@ struct HopArgs {
   const int* gate = nullptr;
   // optional fused reduction over the output (per rhs, per block partials):
   //   red_mode 1: <w, dst>  (complex)        red_mode 2: <dst, id>, <dst, dst>
+  //   red_mode 4 (streaming kernel, src_mode 2): those of mode 3, then <w, dst>
+  //   and <w, source> (8 doubles per partial)
   int red_mode = 0;
   const C2<R>* red_w = nullptr;
-  double* red_out = nullptr;  // [nrhs][nblk_per_rhs][4]
+  double* red_out = nullptr;  // [nrhs][nblk_per_rhs][4, or 8 for red_mode 4]
   // Fused BiCGStab source (streaming kernel only). src_mode 0: the source is
   // `src`. 1: p = r + beta (p_old - omega v_old) with beta, omega of the rhs
   // state, stored to fpnew for the workgroup's own slices. 2: s = r - alpha v.
