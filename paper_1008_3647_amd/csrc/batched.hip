@@ -250,14 +250,18 @@ __device__ __forceinline__ void bsource(const C2<R>* src, const BSrc<R>& b, cons
 }
 
 // y_t = x_t + s T^3(...) over the items [i0, i1) of one class.
-// RES (SRC 0, R = double): y = b - M x on the outer FP64 vectors of the segment.
-// red_mode 1: <w, y>; 3: <y, source>, |y|^2, |source|^2 (per item partials).
+// RES (SRC 0, R = double): y = b - M x on the outer FP64 vectors of the segment;
+// else SRC 0 applies the operator to bs.p. SRC 3 is the source of SRC 2 with
+// red_mode 4.
+// red_mode 1: <w, y>; 3: <y, source>, |y|^2, |source|^2; 4: those of 3, then
+// <w, y>, <w, source> (per item partials: 4 doubles, 8 for mode 4).
 template <typename R, int NX, int DIR, bool RES, bool SPLIT, int SRC>
 __global__ void __launch_bounds__(bop_threads(NX))
     bop_kernel(BCoef<R, NX, SPLIT> c, const BSeg* __restrict__ segs,
                const BHop* __restrict__ items, int i0, int i1, BSrc<R> bs, C2<R>* dst_cat,
                int red_mode, const C2<R>* redw_cat, double* part, const int* gate, int slab) {
   constexpr int P = NX * NX, V = NX * NX * NX, SL = NX * NX * (NX + 1), SG = bop_groups(NX);
+  constexpr int SM = (SRC == 3) ? 2 : SRC;  // source mode
   extern __shared__ __align__(16) unsigned char smem_raw[];
   __shared__ double scratch[4 * (bop_threads(NX) / 64)];
   const int tid = threadIdx.x;
@@ -279,8 +283,9 @@ __global__ void __launch_bounds__(bop_threads(NX))
     } else {
       so = g.off;
       dst = dst_cat + so;
+      if (SRC == 0) src = bs.p;
     }
-    const BScal<R> q = bsrc_scalars<R, SRC>(bs, h.seg);
+    const BScal<R> q = bsrc_scalars<R, SM>(bs, h.seg);
     const C2<R>* redw = redw_cat ? redw_cat + so : nullptr;
     const R* f = fld<R>(g);
     const int ntau = g.ntau;
@@ -294,7 +299,7 @@ __global__ void __launch_bounds__(bop_threads(NX))
     const int th = (DIR < 0) ? ((ts0 == 0) ? ntau - 1 : ts0 - 1) : ((ts1 == ntau) ? 0 : ts1);
     C2<R> W[NX], X[NX];
     if (live) {
-      bsource<R, NX, SRC>(src, bs, q, so + (long long)th * V + l, W);
+      bsource<R, NX, SM>(src, bs, q, so + (long long)th * V + l, W);
       if (DIR < 0) {
 #pragma unroll
         for (int z = 0; z < NX; ++z) {
@@ -305,7 +310,7 @@ __global__ void __launch_bounds__(bop_threads(NX))
       }
     }
     bslice_T3<R, NX, SPLIT>(c, my, l, live, W);
-    double a0 = 0, a1 = 0, a2 = 0, a3 = 0;
+    double a0 = 0, a1 = 0, a2 = 0, a3 = 0, a4 = 0, a5 = 0, a6 = 0, a7 = 0;
     for (int k = 0; k < slab; ++k) {
       const bool act = k < count;
       const int t = tfirst + k * step;
@@ -316,7 +321,7 @@ __global__ void __launch_bounds__(bop_threads(NX))
         else
           sgn = (t == ntau - 1) ? R(1) : R(-1);
         const long long o = (long long)t * V + l;
-        bsource<R, NX, SRC>(src, bs, q, so + o, X);
+        bsource<R, NX, SM>(src, bs, q, so + o, X);
         if (SRC == 1) {
 #pragma unroll
           for (int z = 0; z < NX; ++z) bs.pout[so + o + z * P] = X[z];
@@ -329,7 +334,7 @@ __global__ void __launch_bounds__(bop_threads(NX))
 #pragma unroll
           for (int z = 0; z < NX; ++z) B[RES ? z : 0] = aux[o + z * P];
         }
-        if (red_mode == 1) {
+        if (red_mode == 1 || SRC == 3) {
 #pragma unroll
           for (int z = 0; z < NX; ++z) Q[z] = redw[o + z * P];
         }
@@ -344,11 +349,17 @@ __global__ void __launch_bounds__(bop_threads(NX))
           if (red_mode == 1) {  // <w, y>
             a0 += double(Q[z].x) * out.x + double(Q[z].y) * out.y;
             a1 += double(Q[z].x) * out.y - double(Q[z].y) * out.x;
-          } else if (red_mode == 3) {  // <y, source>, |y|^2, |source|^2
+          } else if (red_mode == 3 || red_mode == 4) {  // <y, source>, |y|^2, |source|^2
             a0 += double(out.x) * X[z].x + double(out.y) * X[z].y;
             a1 += double(out.x) * X[z].y - double(out.y) * X[z].x;
             a2 += double(out.x) * out.x + double(out.y) * out.y;
             a3 += double(X[z].x) * X[z].x + double(X[z].y) * X[z].y;
+            if (SRC == 3) {  // <w, y>, <w, source>
+              a4 += double(Q[z].x) * out.x + double(Q[z].y) * out.y;
+              a5 += double(Q[z].x) * out.y - double(Q[z].y) * out.x;
+              a6 += double(Q[z].x) * X[z].x + double(Q[z].y) * X[z].y;
+              a7 += double(Q[z].x) * X[z].y - double(Q[z].y) * X[z].x;
+            }
           }
         }
       }
@@ -368,7 +379,12 @@ __global__ void __launch_bounds__(bop_threads(NX))
         bslice_T3<R, NX, SPLIT>(c, my, l, tr, W);
       }
     }
-    if (red_mode) bsum4b(a0, a1, a2, a3, part + (long long)it * 4, scratch);
+    if (SRC == 3) {
+      bsum4b(a0, a1, a2, a3, part + (long long)it * 8, scratch);
+      bsum4b(a4, a5, a6, a7, part + (long long)it * 8 + 4, scratch);
+    } else if (red_mode) {
+      bsum4b(a0, a1, a2, a3, part + (long long)it * 4, scratch);
+    }
   }
 }
 
@@ -379,7 +395,9 @@ __global__ void __launch_bounds__(bop_threads(NX))
 // 9 x/r update with s = r - alpha v recomputed (+partials),
 // 3 init (x_in = 0, r = b, rhat = r, p = v = 0; |b|^2 partials, x64 = 0),
 // 4 promote (x64 += x_in, x_in = 0), 5 demote (r = r64; <rhat, r>, |r64|^2),
-// 6 restart (rhat = r, p = v = 0), 7 |b64|^2 partials, 8 |r64|^2 partials.
+// 6 restart (rhat = r, p = v = 0), 7 |b64|^2 partials, 8 |r64|^2 partials,
+// 10 the x/r update of op 9 merged with the next p update, pn = r + beta (p -
+// omega v) (beta from the rho that FIN_OMEGA_RHO derived; |r|^2 partials).
 struct BVecArgs {
   void* x;
   void* r;
@@ -387,6 +405,7 @@ struct BVecArgs {
   void* p;
   void* v;
   void* t;
+  void* pn;  // op 10: the new p
 };
 
 template <typename R>
@@ -421,6 +440,24 @@ __global__ void __launch_bounds__(256)
         Rr[o + i] = rn;
         a0 += double(h.x) * rn.x + double(h.y) * rn.y;
         a1 += double(h.x) * rn.y - double(h.y) * rn.x;
+        a2 += double(rn.x) * rn.x + double(rn.y) * rn.y;
+      }
+    } else if (op == 10) {
+      const R ar = R(q.alpha.x), ai = R(q.alpha.y), wr = R(q.omega.x), wi = R(q.omega.y);
+      const R br = R(q.beta.x), bi = R(q.beta.y);
+      C2<R>* Pn = reinterpret_cast<C2<R>*>(A.pn);
+      BV_LOOP(item) {
+        const C2<R> pv = Pp[o + i], rv = Rr[o + i], vv = Vv[o + i], tv = Tt[o + i];
+        const C2<R> sv = mk<R>(rv.x - (ar * vv.x - ai * vv.y), rv.y - (ar * vv.y + ai * vv.x));
+        C2<R> xv = X[o + i];
+        xv.x += (ar * pv.x - ai * pv.y) + (wr * sv.x - wi * sv.y);
+        xv.y += (ar * pv.y + ai * pv.x) + (wr * sv.y + wi * sv.x);
+        X[o + i] = xv;
+        const C2<R> rn = mk<R>(sv.x - (wr * tv.x - wi * tv.y), sv.y - (wr * tv.y + wi * tv.x));
+        Rr[o + i] = rn;
+        const R dx = pv.x - (wr * vv.x - wi * vv.y);
+        const R dy = pv.y - (wr * vv.y + wi * vv.x);
+        Pn[o + i] = mk<R>(rn.x + br * dx - bi * dy, rn.y + br * dy + bi * dx);
         a2 += double(rn.x) * rn.x + double(rn.y) * rn.y;
       }
     } else if (op == 3) {
@@ -643,7 +680,7 @@ int run_batched(std::vector<Lattice*>& Ls, const void* const* bu, void* const* x
   UFG_TRY(dhops.alloc(sizeof(BHop) * hops.size()));
   UFG_TRY(dvecs.alloc(sizeof(BVec) * vecs.size()));
   UFG_TRY(dtab.alloc(sizeof(int) * 4 * S));
-  UFG_TRY(dhpart.alloc(sizeof(double) * 4 * hops.size()));
+  UFG_TRY(dhpart.alloc(sizeof(double) * 8 * hops.size()));
   UFG_TRY(dvpart.alloc(sizeof(double) * 4 * vecs.size()));
   UFG_TRY(dstate.alloc(sizeof(RhsState) * S + sizeof(int) * 3 * S));
   hipStream_t cs = nullptr;
@@ -691,7 +728,7 @@ int run_batched(std::vector<Lattice*>& Ls, const void* const* bu, void* const* x
   double* hpart = reinterpret_cast<double*>(dhpart.p);
   double* vpart = reinterpret_cast<double*>(dvpart.p);
   // inner vectors: x, r, rhat, p (two, alternating), v (two, alternating), t
-  BVecArgs VA{dvec[0].p, dvec[1].p, dvec[2].p, dvec[3].p, dvec[4].p, dvec[6].p};
+  BVecArgs VA{dvec[0].p, dvec[1].p, dvec[2].p, dvec[3].p, dvec[4].p, dvec[6].p, nullptr};
   C2<RI>* vr = reinterpret_cast<C2<RI>*>(dvec[1].p);
   C2<RI>* vrh = reinterpret_cast<C2<RI>*>(dvec[2].p);
   C2<RI>* vt = reinterpret_cast<C2<RI>*>(dvec[6].p);
@@ -711,6 +748,14 @@ int run_batched(std::vector<Lattice*>& Ls, const void* const* bu, void* const* x
     UFG_TRY((launch_bop<RI, -1, false, 2>(k, ncu, cs, true, nullptr, nullptr, nosrc, nullptr, 0,
                                           nullptr, nullptr, nullptr, slab)));
     UFG_TRY((launch_bop<RI, 1, false, 2>(k, ncu, cs, true, nullptr, nullptr, nosrc, nullptr, 0,
+                                         nullptr, nullptr, nullptr, slab)));
+    UFG_TRY((launch_bop<RI, -1, false, 0>(k, ncu, cs, true, nullptr, nullptr, nosrc, nullptr, 0,
+                                          nullptr, nullptr, nullptr, slab)));
+    UFG_TRY((launch_bop<RI, -1, false, 3>(k, ncu, cs, true, nullptr, nullptr, nosrc, nullptr, 0,
+                                          nullptr, nullptr, nullptr, slab)));
+    UFG_TRY((launch_bop<RI, 1, false, 3>(k, ncu, cs, true, nullptr, nullptr, nosrc, nullptr, 0,
+                                         nullptr, nullptr, nullptr, slab)));
+    UFG_TRY((launch_bop<RI, 1, false, 0>(k, ncu, cs, true, nullptr, nullptr, nosrc, nullptr, 0,
                                          nullptr, nullptr, nullptr, slab)));
     UFG_TRY((launch_bop<double, -1, true, 0>(k, ncu, cs, true, nullptr, nullptr, nosrc64, nullptr,
                                              0, nullptr, nullptr, nullptr, slab)));
@@ -743,24 +788,39 @@ int run_batched(std::vector<Lattice*>& Ls, const void* const* bu, void* const* x
       segs[s].r64 = reinterpret_cast<double2*>(dr64.p) + segs[s].off;
     }
     UFG_HIP(hipMemcpyAsync(dsegs.p, segs.data(), sizeof(BSeg) * S, hipMemcpyHostToDevice, cs));
-    // p_new = r + beta (p - omega v) fused into v_new = A p_new (+ <rhat, v_new>), or
-    // s = r - alpha v fused into t = A s (+ <t, s>, |t|^2, |s|^2); p and v alternate
-    // between two buffers so that halo reads never see this launch's writes
-    auto hop = [&](int src_mode, const C2<RI>* pin, C2<RI>* pout, const C2<RI>* vin,
+    // src_mode 1: p_new = r + beta (p - omega v) fused into v_new = A p_new
+    // (+ <rhat, v_new>); 0: v = A p (+ <rhat, v>); 2: s = r - alpha v fused into
+    // t = A s (+ <t, s>, |t|^2, |s|^2, and with red 4 <rhat, t>, <rhat, s>).
+    // p and v alternate between two buffers so that halo reads never see this
+    // launch's writes.
+    auto hop = [&](int src_mode, int red, const C2<RI>* pin, C2<RI>* pout, const C2<RI>* vin,
                    C2<RI>* dst) -> int {
       const BSrc<RI> b{vr, pin, vin, pout, K.st};
+      const C2<RI>* w = (red == 1 || red == 4) ? vrh : nullptr;
       for (const BClass& k : cls) {
         if (src_mode == 1 && dir < 0)
-          UFG_TRY((launch_bop<RI, -1, false, 1>(k, ncu, cs, false, dseg, dhop, b, dst, 1, vrh,
+          UFG_TRY((launch_bop<RI, -1, false, 1>(k, ncu, cs, false, dseg, dhop, b, dst, red, w,
                                                 hpart, K.active, slab)));
         else if (src_mode == 1)
-          UFG_TRY((launch_bop<RI, 1, false, 1>(k, ncu, cs, false, dseg, dhop, b, dst, 1, vrh,
+          UFG_TRY((launch_bop<RI, 1, false, 1>(k, ncu, cs, false, dseg, dhop, b, dst, red, w,
+                                               hpart, K.active, slab)));
+        else if (src_mode == 0 && dir < 0)
+          UFG_TRY((launch_bop<RI, -1, false, 0>(k, ncu, cs, false, dseg, dhop, b, dst, red, w,
+                                                hpart, K.active, slab)));
+        else if (src_mode == 0)
+          UFG_TRY((launch_bop<RI, 1, false, 0>(k, ncu, cs, false, dseg, dhop, b, dst, red, w,
+                                               hpart, K.active, slab)));
+        else if (red == 4 && dir < 0)
+          UFG_TRY((launch_bop<RI, -1, false, 3>(k, ncu, cs, false, dseg, dhop, b, dst, red, w,
+                                                hpart, K.active, slab)));
+        else if (red == 4)
+          UFG_TRY((launch_bop<RI, 1, false, 3>(k, ncu, cs, false, dseg, dhop, b, dst, red, w,
                                                hpart, K.active, slab)));
         else if (dir < 0)
-          UFG_TRY((launch_bop<RI, -1, false, 2>(k, ncu, cs, false, dseg, dhop, b, dst, 3,
-                                                nullptr, hpart, K.active, slab)));
+          UFG_TRY((launch_bop<RI, -1, false, 2>(k, ncu, cs, false, dseg, dhop, b, dst, red, w,
+                                                hpart, K.active, slab)));
         else
-          UFG_TRY((launch_bop<RI, 1, false, 2>(k, ncu, cs, false, dseg, dhop, b, dst, 3, nullptr,
+          UFG_TRY((launch_bop<RI, 1, false, 2>(k, ncu, cs, false, dseg, dhop, b, dst, red, w,
                                                hpart, K.active, slab)));
       }
       return UFG_OK;
@@ -785,23 +845,42 @@ int run_batched(std::vector<Lattice*>& Ls, const void* const* bu, void* const* x
     UFG_TRY(k_finalize_seg(cs, FIN_INIT_B, vpart, vf, vc, nullptr, K));
     UFG_TRY(k_finalize_seg(cs, FIN_INIT_R, vpart, vf, vc, nullptr, K));
     UFG_HIP(hipGetLastError());
-    // one check interval of iterations (an even count, so that p and v are back
-    // in their first buffers at every check point), captured once
+    // One check interval of iterations (an even count; every iteration moves p
+    // and v to the other buffer, so they are back in their first buffers at
+    // every check point), captured once. As in the single-lattice solver, the
+    // x, r update of an iteration is merged with the p update of the next one
+    // (rho of the next iteration from <rhat, s> - omega <rhat, t>, reduced by
+    // the second operator launch), except in the last iteration of the
+    // interval, which runs the separate update so that x and r are current at
+    // the check point; the first iteration forms p in its operator launch.
     auto body = [&]() -> int {
       for (int k = 0; k < check; ++k) {
+        const bool last = (k + 1 == check);
         C2<RI>* pin = pbuf[k & 1];
         C2<RI>* pout = pbuf[(k + 1) & 1];
         C2<RI>* vin = vbuf[k & 1];
         C2<RI>* vout = vbuf[(k + 1) & 1];
-        UFG_TRY(hop(1, pin, pout, vin, vout));
-        UFG_TRY(k_finalize_seg(cs, FIN_ALPHA, hpart, hf, hc, K.active, K));
-        UFG_TRY(hop(2, nullptr, nullptr, vout, vt));
-        UFG_TRY(k_finalize_seg(cs, FIN_OMEGA, hpart, hf, hc, K.active, K));
+        if (k == 0) {
+          UFG_TRY(hop(1, 1, pin, pout, vin, vout));
+          UFG_TRY(k_finalize_seg(cs, FIN_ALPHA, hpart, hf, hc, K.active, K));
+        } else {  // pout was formed by the merged update of the previous iteration
+          UFG_TRY(hop(0, 1, pout, nullptr, nullptr, vout));
+          UFG_TRY(k_finalize_seg(cs, FIN_ALPHA_XR, hpart, hf, hc, K.active, K, 4, vpart, vf,
+                                 vc));
+        }
+        UFG_TRY(hop(2, last ? 3 : 4, nullptr, nullptr, vout, vt));
         BVecArgs A = VA;
         A.p = pout;
         A.v = vout;
-        vop(9, K.active, A);
-        UFG_TRY(k_finalize_seg(cs, FIN_RHO, vpart, vf, vc, K.active, K));
+        if (last) {
+          UFG_TRY(k_finalize_seg(cs, FIN_OMEGA, hpart, hf, hc, K.active, K));
+          vop(9, K.active, A);
+          UFG_TRY(k_finalize_seg(cs, FIN_RHO, vpart, vf, vc, K.active, K));
+        } else {
+          UFG_TRY(k_finalize_seg(cs, FIN_OMEGA_RHO, hpart, hf, hc, K.active, K, 8));
+          A.pn = pin;  // the p of the next iteration
+          vop(10, K.active, A);
+        }
       }
       return UFG_OK;
     };

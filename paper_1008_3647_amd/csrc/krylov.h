@@ -99,8 +99,12 @@ int k_restart(const Lattice& L, const C2<R>* r, C2<R>* rhat, C2<R>* p, C2<R>* v,
 // s[4 .. 8); then applies `op` to the state.
 int k_finalize(const Lattice& L, int op, int nblk, const int* gate, const KrylovState& K,
                int stride = 4, int nblk2 = 0);
-// Partials of rhs (segment) k are part[first[k] .. first[k] + count[k]) (4 doubles each).
+// Partials of rhs (segment) k are part[first[k] .. first[k] + count[k]) (`stride`
+// doubles each, into s[0 .. stride)); with part2, also part2[first2[k] ..
+// first2[k] + count2[k]) (4 doubles each, into s[4 .. 8)).
 int k_finalize_seg(hipStream_t stream, int op, const double* part, const int* first,
-                   const int* count, const int* gate, const KrylovState& K);
+                   const int* count, const int* gate, const KrylovState& K, int stride = 4,
+                   const double* part2 = nullptr, const int* first2 = nullptr,
+                   const int* count2 = nullptr);
 
 }  // namespace ufg

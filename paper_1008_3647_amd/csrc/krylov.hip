@@ -602,9 +602,14 @@ __global__ void __launch_bounds__(256) finalize_kernel(int op, const double* par
   restart[k] = rst;
 }
 
-// Segmented variant: rhs (segment) k owns partials [first[k], first[k] + count[k]).
+// Segmented variant: rhs (segment) k owns partials [first[k], first[k] + count[k])
+// of `stride` doubles (into s[0..stride)), and, with part2, partials
+// [first2[k], first2[k] + count2[k]) of 4 doubles (into s[4..8)).
+template <int NV>
 __global__ void __launch_bounds__(256) finalize_seg_kernel(int op, const double* part,
                                                            const int* first, const int* count,
+                                                           int stride, const double* part2,
+                                                           const int* first2, const int* count2,
                                                            RhsState* st, int* active,
                                                            int* update, int* restart,
                                                            const int* gate, KrylovParams prm) {
@@ -618,19 +623,44 @@ __global__ void __launch_bounds__(256) finalize_seg_kernel(int op, const double*
     upd = update[k];
     rst = restart[k];
   }
-  double s0 = 0, s1 = 0, s2 = 0, s3 = 0;
+  double a[NV];
+#pragma unroll
+  for (int j = 0; j < NV; ++j) a[j] = 0.0;
   const int f = first[k], c = count[k];
-  for (int b = threadIdx.x; b < c; b += 256) {
-    const double* q = part + ((long long)f + b) * 4;
-    s0 += q[0];
-    s1 += q[1];
-    s2 += q[2];
-    s3 += q[3];
+  if (NV == 8 && stride == 8) {
+    for (int b = threadIdx.x; b < c; b += 256) {
+      const double* qq = part + ((long long)f + b) * 8;
+#pragma unroll
+      for (int j = 0; j < NV; ++j) a[j] += qq[j];
+    }
+  } else {
+    for (int b = threadIdx.x; b < c; b += 256) {
+      const double* qq = part + ((long long)f + b) * 4;
+#pragma unroll
+      for (int j = 0; j < 4; ++j) a[j] += qq[j];
+    }
+    if (NV == 8) {
+      const int f2 = first2[k], c2 = count2[k];
+      for (int b = threadIdx.x; b < c2; b += 256) {
+        const double* qq = part2 + ((long long)f2 + b) * 4;
+#pragma unroll
+        for (int j = 0; j < 4; ++j) a[NV - 4 + j] += qq[j];
+      }
+    }
   }
-  __shared__ double out[4];
-  bsum4(s0, s1, s2, s3, out);
+  __shared__ double sm[4][NV];
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+#pragma unroll
+  for (int j = 0; j < NV; ++j) {
+    a[j] = wsum(a[j]);
+    if (lane == 0) sm[wid][j] = a[j];
+  }
+  __syncthreads();
   if (threadIdx.x != 0) return;
-  const double s[8] = {out[0], out[1], out[2], out[3], 0, 0, 0, 0};
+  double s[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+  for (int w = 0; w < 4; ++w)
+#pragma unroll
+    for (int j = 0; j < NV; ++j) s[j] += sm[w][j];
   apply_fin(op, s, q, act, upd, rst, prm);
   st[k] = q;
   active[k] = act;
@@ -747,9 +777,20 @@ int k_restart(const Lattice& L, const C2<R>* r, C2<R>* rhat, C2<R>* p, C2<R>* v,
   return UFG_OK;
 }
 int k_finalize_seg(hipStream_t stream, int op, const double* part, const int* first,
-                   const int* count, const int* gate, const KrylovState& K) {
-  hipLaunchKernelGGL(finalize_seg_kernel, dim3(K.nrhs), dim3(256), 0, stream, op, part, first,
-                     count, K.st, K.active, K.update, K.restart, gate, K.prm);
+                   const int* count, const int* gate, const KrylovState& K, int stride,
+                   const double* part2, const int* first2, const int* count2) {
+  if ((stride != 4 && stride != 8) || (part2 && (stride != 4 || !first2 || !count2))) {
+    set_error("k_finalize_seg: bad partials layout");
+    return UFG_EINVAL;
+  }
+  if (stride == 8 || part2)
+    hipLaunchKernelGGL(finalize_seg_kernel<8>, dim3(K.nrhs), dim3(256), 0, stream, op, part,
+                       first, count, stride, part2, first2, count2, K.st, K.active, K.update,
+                       K.restart, gate, K.prm);
+  else
+    hipLaunchKernelGGL(finalize_seg_kernel<4>, dim3(K.nrhs), dim3(256), 0, stream, op, part,
+                       first, count, stride, part2, first2, count2, K.st, K.active, K.update,
+                       K.restart, gate, K.prm);
   return UFG_OK;
 }
 int k_finalize(const Lattice& L, int op, int nblk, const int* gate, const KrylovState& K,

@@ -91,6 +91,42 @@ def test_single_system_bicgstab(op_name, dtype, mixed):
     assert _relres_oracle(x, bb, sigma, op_name) <= 1.2 * tol
 
 
+@pytest.mark.parametrize("mixed", [False, True])
+@pytest.mark.parametrize("op_name", ["M", "Mdag"])
+def test_bicgstab_check_interval(op_name, mixed):
+    """On streaming lattices the unpreconditioned BiCGStab merges the x, r
+    update of an iteration with the p update of the next one, and runs the
+    separate update only in iterations that end at a check point. check_every
+    = 1 gives the separate form only; 7 and 25 mostly the merged one (odd and
+    long intervals change which p / v buffers are current at a check point).
+    All must converge to the same solution with the true residual (oracle)
+    within tol and comparable iteration counts."""
+    require_gpu()
+    from paper_1008_3647_amd import Lattice
+    nx, ntau, nrhs = 8, 40, 2
+    sigma = sigma_field(nx, ntau, 441)
+    b = gaussian_rhs(nx, ntau, [442, 443])
+    L = Lattice(nx, ntau, TAU, G, torch.complex128)
+    L.set_aux_field(to_dev(sigma))
+    tol = 1e-10
+    sols, iters = [], []
+    for check in (1, 7, 25):
+        say(f"bicgstab {op_name} mixed={mixed} check_every={check}")
+        x, st = L.solve_bicgstab(to_dev(b), op_name, tol=tol, mixed=mixed, check_every=check)
+        say(st)
+        assert st["status"] == 0
+        xh = to_host(x)
+        assert _relres_oracle(xh, b, sigma, op_name) <= 1.2 * tol
+        sols.append(xh)
+        iters.append(max(st["iters"]))
+    # every solution has a true residual <= tol: they differ by at most about
+    # cond(M) tol (cond(M) of this lattice is far below 1e3)
+    for xh in sols[1:]:
+        assert np.max(np.abs(xh - sols[0])) / np.max(np.abs(sols[0])) < 1e-6
+    # a check interval of c stops at most c - 1 iterations late
+    assert max(iters) <= 1.25 * min(iters) + 25
+
+
 @pytest.mark.parametrize("mixed", [True, False])
 def test_lattice_16x400_against_oracle_reference(mixed):
     """Full-size two-step solve, 8 rhs, in the configuration bench.py times.
