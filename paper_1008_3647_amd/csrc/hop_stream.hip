@@ -70,7 +70,7 @@ __device__ __forceinline__ void line_op(const SplitCoef<R, NX>& c, C2<R> (&v)[NX
     modes_bwd<R, NX>(c, v);
 }
 
-template <typename R, int NX, int MODE = 0>
+template <typename R, int NX, int MODE = 0, bool KEEP = false>
 __device__ __forceinline__ void slice_T3(const SplitCoef<R, NX>& c, C2<R>* lds, int l,
                                          C2<R> (&v)[NX]) {
   const int y = l / NX, x = l - (l / NX) * NX;
@@ -105,6 +105,7 @@ __device__ __forceinline__ void slice_T3(const SplitCoef<R, NX>& c, C2<R>* lds, 
     for (int xx = 0; xx < NX; ++xx) lds[lds_at<NX>(z * NX + yy, xx)] = w[xx];
   }
   __syncthreads();
+  if (KEEP) return;  // the result stays in LDS: z-line of thread (y, x) at lds_at(z NX + y, x)
 #pragma unroll
   for (int z = 0; z < NX; ++z) v[z] = lds[lds_at<NX>(z * NX + y, x)];
 }
@@ -237,8 +238,9 @@ __device__ __forceinline__ double wsum(double v) {
 // DIR = -1: M-type, output t reads source t-1; the slab is walked upwards.
 // DIR = +1: M^T-type, output t reads source t+1; the slab is walked downwards.
 // Either way the slice loaded for the identity term of output t is the source
-// of the next output, so each thread holds two z-lines: X (current source)
-// and W (transform of the previous one).
+// of the next output: each thread holds one z-line X (current source) in
+// registers, and the transform of the previous source stays in the LDS slice,
+// from which the output phase reads the thread's own z-line.
 template <typename R, int NX, int DIR, bool GENERAL, int SRC, int RED>
 __global__ void __launch_bounds__(NX * NX)
     hop_stream_kernel(HopArgs<R> a, SplitCoef<R, NX> c, int ntau, int nslab) {
@@ -282,10 +284,14 @@ __global__ void __launch_bounds__(NX * NX)
   const int th = (DIR < 0) ? ((t0 == 0) ? ntau - 1 : t0 - 1) : ((t1 == ntau) ? 0 : t1);
 
   double acc0 = 0, acc1 = 0, acc2 = 0, acc3 = 0, acc4 = 0, acc5 = 0, acc6 = 0, acc7 = 0;
-  C2<R> W[NX], X[NX];
-  load_source<R, NX, SRC>(b, q, th * V * ES, vo, W);
-  if (DIR < 0) scale_field<R, NX>(b.pre, th * V * FS, fo, W);
-  slice_T3<R, NX>(c, lds, l, W);
+  // X: the z-line of the current source slice. The T^3 of the previous one
+  // stays in the LDS slice (each thread reads back only its own z-line, which
+  // is also the first thing it writes in the next transform).
+  C2<R> X[NX];
+  const int ly = l / NX, lx = l - (l / NX) * NX;
+  load_source<R, NX, SRC>(b, q, th * V * ES, vo, X);
+  if (DIR < 0) scale_field<R, NX>(b.pre, th * V * FS, fo, X);
+  slice_T3<R, NX, 0, true>(c, lds, l, X);
   for (int k = 0; k < count; ++k) {
     const int t = tfirst + k * step;
     const int so = t * V * ES;  // slice byte offset (uniform)
@@ -328,10 +334,11 @@ __global__ void __launch_bounds__(NX * NX)
         const int z = z0 + j;
         const int s = so + z * P * ES;
         const C2<R> id = X[z];
+        const C2<R> wz = lds[lds_at<NX>(z * NX + ly, lx)];
         C2<R> base;
         const R f = (DIR > 0) ? F[DIR > 0 ? j : 0] : sgn;
-        base.x = f * W[z].x;
-        base.y = f * W[z].y;
+        base.x = f * wz.x;
+        base.y = f * wz.y;
         if (a.id) {
           base.x += id.x;
           base.y += id.y;
@@ -376,12 +383,17 @@ __global__ void __launch_bounds__(NX * NX)
         }
       }
     }
+    if (RED != 0) {
+      // the reductions of this slice are complete here: without this point the
+      // compiler sinks them below the next transform and keeps the slice's
+      // operands live across it
+      asm volatile("" ::"v"(acc0), "v"(acc1), "v"(acc2), "v"(acc3));
+      if (RED == 4) asm volatile("" ::"v"(acc4), "v"(acc5), "v"(acc6), "v"(acc7));
+    }
     if (k + 1 < count) {
       // transform source slice t for the next output slice
       if (DIR < 0) scale_field<R, NX>(b.pre, t * V * FS, fo, X);
-#pragma unroll
-      for (int z = 0; z < NX; ++z) W[z] = X[z];
-      slice_T3<R, NX>(c, lds, l, W);
+      slice_T3<R, NX, 0, true>(c, lds, l, X);
     }
   }
   if (RED != 0) {
