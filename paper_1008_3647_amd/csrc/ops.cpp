@@ -248,6 +248,11 @@ static int basis_change(const Lattice& L, const R* mat, const C2<R>* x, C2<R>* y
 }
 
 // y = W_d x (adjoint: W_d^T x). Uses three temporaries.
+// The truncated series sum_m w_m K^m M0^{-1} x (K = -A M0^{-1} M1) is evaluated
+// in Horner form, z_d = w_d u_0, z_m = w_m u_0 + K z_{m+1}: the last basis
+// change of each K application adds w_m u_0 itself (alpha / beta form), so no
+// separate accumulation pass runs. The adjoint is the transpose of the same
+// polynomial: M0^{-T} (sum_m w_m K'^m x), K' = A S U^3 [(1 - lam Z^T)^{-1} - 1] U^3T.
 template <typename R>
 static int wce_apply(Lattice& L, const PcPlan& pc, bool adjoint, const C2<R>* x, C2<R>* y,
                      int nrhs, const int* gate, Counters* cnt) {
@@ -264,48 +269,52 @@ static int wce_apply(Lattice& L, const PcPlan& pc, bool adjoint, const C2<R>* x,
     // u_0 = M0^{-1} x
     UFG_TRY(basis_change<R>(L, F.Ut, x, tmp, nrhs, gate, nullptr, nullptr, one, nullptr, zero));
     UFG_TRY(launch_m0_temporal<R>(L, tmp, tmp, nrhs, false, false, gate));
-    if (d == 0) {
-      UFG_TRY(basis_change<R>(L, F.U, tmp, y, nrhs, gate, nullptr, nullptr,
-                              double2{pc.w[0], 0.0}, nullptr, zero));
-    } else {
-      UFG_TRY(basis_change<R>(L, F.U, tmp, cur, nrhs, gate, nullptr, nullptr, one, nullptr, zero));
-      UFG_TRY(k_axpby<R>(L, double2{pc.w[0], 0.0}, cur, zero, y, nrhs, gate));
-    }
     cnt->m0inv += 1;
-    for (int m = 1; m <= d; ++m) {
-      // u_m = A U^3 [(1 - lam Z)^{-1} - 1] U^3T (sin sigma u_{m-1})
-      UFG_TRY(basis_change<R>(L, F.Ut, cur, tmp, nrhs, gate, F.sn, nullptr, one, nullptr, zero));
+    if (d == 0) {
+      return basis_change<R>(L, F.U, tmp, y, nrhs, gate, nullptr, nullptr,
+                             double2{pc.w[0], 0.0}, nullptr, zero);
+    }
+    C2<R>* u0 = slot_vec<R>(L, SLOT_PC0 + 2, nrhs, &rc);
+    UFG_TRY(rc);
+    UFG_TRY(basis_change<R>(L, F.U, tmp, u0, nrhs, gate, nullptr, nullptr, one, nullptr, zero));
+    // K v = A U^3 [(1 - lam Z)^{-1} - 1] U^3T (sin sigma v); z_m = w_m u_0 + K z_{m+1}
+    const C2<R>* src = u0;
+    double scale = pc.w[d];
+    for (int m = d - 1; m >= 0; --m) {
+      C2<R>* dst = (m == 0) ? y : cur;
+      UFG_TRY(basis_change<R>(L, F.Ut, src, tmp, nrhs, gate, F.sn, nullptr, one, nullptr, zero));
       UFG_TRY(launch_m0_temporal<R>(L, tmp, tmp, nrhs, false, true, gate));
-      if (m < d) {
-        UFG_TRY(basis_change<R>(L, F.U, tmp, cur, nrhs, gate, nullptr, nullptr,
-                                double2{A, 0.0}, nullptr, zero));
-        UFG_TRY(k_axpby<R>(L, double2{pc.w[m], 0.0}, cur, one, y, nrhs, gate));
-      } else {
-        UFG_TRY(basis_change<R>(L, F.U, tmp, y, nrhs, gate, nullptr, nullptr,
-                                double2{A * pc.w[m], 0.0}, y, one));
-      }
+      UFG_TRY(basis_change<R>(L, F.U, tmp, dst, nrhs, gate, nullptr, nullptr,
+                              double2{A * scale, 0.0}, u0, double2{pc.w[m], 0.0}));
+      src = dst;
+      scale = 1.0;
       cnt->m0inv += 1;
       cnt->mv += 1;
     }
   } else {
-    // acc = sum_m w_m v_m with v_0 = x, v_m = A S U^3 [(1 - lam Z^T)^{-1} - 1] U^3T v_{m-1};
-    // y = U^3 (1 - lam Z^T)^{-1} U^3T acc. `cur` holds v_m, `y` holds acc.
-    C2<R>* acc = slot_vec<R>(L, SLOT_PC0 + 2, nrhs, &rc);
-    UFG_TRY(rc);
-    const C2<R>* vprev = x;
-    UFG_TRY(k_axpby<R>(L, double2{pc.w[0], 0.0}, x, zero, acc, nrhs, gate));
-    for (int m = 1; m <= d; ++m) {
-      UFG_TRY(basis_change<R>(L, F.Ut, vprev, tmp, nrhs, gate, nullptr, nullptr, one, nullptr,
-                              zero));
-      UFG_TRY(launch_m0_temporal<R>(L, tmp, tmp, nrhs, true, true, gate));
-      UFG_TRY(basis_change<R>(L, F.U, tmp, cur, nrhs, gate, nullptr, F.sn, double2{A, 0.0},
-                              nullptr, zero));
-      UFG_TRY(k_axpby<R>(L, double2{pc.w[m], 0.0}, cur, one, acc, nrhs, gate));
-      vprev = cur;
-      cnt->m0inv += 1;
-      cnt->mv += 1;
+    // acc = sum_m w_m K'^m x in Horner form (z_m = w_m x + K' z_{m+1}), then
+    // y = M0^{-T} acc
+    const C2<R>* acc = x;
+    double scale = pc.w[0];
+    if (d > 0) {
+      const C2<R>* src = x;
+      double s = pc.w[d];
+      for (int m = d - 1; m >= 0; --m) {
+        UFG_TRY(basis_change<R>(L, F.Ut, src, tmp, nrhs, gate, nullptr, nullptr, one, nullptr,
+                                zero));
+        UFG_TRY(launch_m0_temporal<R>(L, tmp, tmp, nrhs, true, true, gate));
+        UFG_TRY(basis_change<R>(L, F.U, tmp, cur, nrhs, gate, nullptr, F.sn, double2{A * s, 0.0},
+                                x, double2{pc.w[m], 0.0}));
+        src = cur;
+        s = 1.0;
+        cnt->m0inv += 1;
+        cnt->mv += 1;
+      }
+      acc = cur;
+      scale = 1.0;
     }
-    UFG_TRY(basis_change<R>(L, F.Ut, acc, tmp, nrhs, gate, nullptr, nullptr, one, nullptr, zero));
+    UFG_TRY(basis_change<R>(L, F.Ut, acc, tmp, nrhs, gate, nullptr, nullptr,
+                            double2{scale, 0.0}, nullptr, zero));
     UFG_TRY(launch_m0_temporal<R>(L, tmp, tmp, nrhs, true, false, gate));
     UFG_TRY(basis_change<R>(L, F.U, tmp, y, nrhs, gate, nullptr, nullptr, one, nullptr, zero));
     cnt->m0inv += 1;
