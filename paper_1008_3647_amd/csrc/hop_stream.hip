@@ -4,8 +4,9 @@
 // side and walks it in the direction that reuses loads: upwards for M (output
 // t reads source t-1), downwards for M^T (output t reads source t+1). The
 // slice loaded for the identity term of output t is the source of the next
-// output, so every input slice of the slab is loaded from HBM once; only one
-// halo slice per slab is loaded twice, and it is often a cache hit.
+// output, so every input slice of the slab is loaded once; only one halo
+// slice per slab is loaded twice (at two slices per slab the L2 misses come to
+// about 1.2 times the algorithmic bytes).
 //
 // Workgroups are numbered so that each XCD receives a contiguous run of
 // (slab, rhs) pairs with the rhs index fastest: the eight right-hand sides of
@@ -27,7 +28,9 @@
 //
 // Fused BiCGStab sources: the kernel can build its source on the fly from the
 // Krylov vectors (p = r + beta (p_old - omega v_old), or s = r - alpha v) so
-// that BiCGStab's vector updates ride on the operator's memory stream.
+// that BiCGStab's vector updates ride on the operator's memory stream, and
+// reduce FP64 dot products of its output, its source and a weight vector into
+// one partial per workgroup.
 #include "hop_stream.h"
 #include "krylov.h"
 #include "split_line.h"
