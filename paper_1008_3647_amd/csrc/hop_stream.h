@@ -31,6 +31,14 @@ double mode_split_coefficients(int nx, const std::vector<double>& U, std::vector
 template <typename R>
 int launch_basis_stream(const Lattice& L, const HopArgs<R>& a, bool forward);
 
+// Two basis changes per slice in one pass (streaming-supported nx):
+// z = alpha post . U^3 x + beta aux (stored to zout unless null), y = U^3T (mid . z).
+// post, mid: real fields or null (1); y may alias x; zout must alias neither.
+template <typename R>
+int launch_basis_pair(const Lattice& L, const C2<R>* x, C2<R>* y, C2<R>* zout, const R* post,
+                      double2 alpha, const C2<R>* aux, double2 beta, const R* mid, int nrhs,
+                      const int* gate);
+
 int stream_slab(const Lattice& L);
 // Slabs per right-hand side: slab s of nslab covers slices [s ntau / nslab,
 // (s + 1) ntau / nslab), so every slab holds floor or ceil of ntau / nslab.

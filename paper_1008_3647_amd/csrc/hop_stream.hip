@@ -553,6 +553,113 @@ __global__ void __launch_bounds__(NX * NX)
   }
 }
 
+// Two basis changes of each slice in one pass (the weak-coupling series, whose
+// consecutive orders meet as U^3 then U^3T with only per-site factors between):
+//   z = alpha post . U^3 x + beta aux  (stored to zout when given),
+//   y = U^3T (mid . z).
+// The second transform's first LDS write touches only the thread's own z-line,
+// which the first transform's last read has already consumed.
+template <typename R>
+struct PairArgs {
+  const C2<R>* src = nullptr;
+  C2<R>* dst = nullptr;
+  C2<R>* zout = nullptr;
+  const R* post = nullptr;
+  const R* mid = nullptr;
+  const C2<R>* aux = nullptr;
+  double2 alpha = {1.0, 0.0};
+  double2 beta = {0.0, 0.0};
+  const int* gate = nullptr;
+  int nrhs = 1;
+};
+
+template <typename R, int NX>
+__global__ void __launch_bounds__(NX * NX)
+    basis_pair_kernel(PairArgs<R> a, SplitCoef<R, NX> cb, SplitCoef<R, NX> cf, int ntau,
+                      int nslab) {
+  constexpr int P = NX * NX, V = NX * NX * NX;
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  C2<R>* lds = reinterpret_cast<C2<R>*>(smem_raw);
+  const int nb = gridDim.x;
+  const int full = nb & ~7;
+  int lid = blockIdx.x;
+  if (lid < full) lid = (lid & 7) * (full >> 3) + (lid >> 3);
+  const int r = lid % a.nrhs;
+  const int sb = lid / a.nrhs;
+  if (a.gate && a.gate[r] == 0) return;
+  const int l = threadIdx.x;
+  const int t0 = (int)((long long)sb * ntau / nslab);
+  const int t1 = (int)((long long)(sb + 1) * ntau / nslab);
+  const long long rbase = (long long)r * ntau * V;
+  const R ar = R(a.alpha.x), ai = R(a.alpha.y), br = R(a.beta.x), bi = R(a.beta.y);
+  for (int t = t0; t < t1; ++t) {
+    const long long o = rbase + (long long)t * V + l;
+    const long long fo = (long long)t * V + l;
+    C2<R> X[NX];
+#pragma unroll
+    for (int z = 0; z < NX; ++z) X[z] = a.src[o + z * P];
+    R F[NX], G[NX];
+#pragma unroll
+    for (int z = 0; z < NX; ++z) {
+      F[z] = a.post ? a.post[fo + z * P] : R(1);
+      G[z] = a.mid ? a.mid[fo + z * P] : R(1);
+    }
+    C2<R> Au[NX];
+    if (a.aux) {
+#pragma unroll
+      for (int z = 0; z < NX; ++z) Au[z] = a.aux[o + z * P];
+    }
+    slice_T3<R, NX, 2>(cb, lds, l, X);  // U^3
+#pragma unroll
+    for (int z = 0; z < NX; ++z) {
+      const C2<R> b = C2<R>{F[z] * X[z].x, F[z] * X[z].y};
+      C2<R> w = C2<R>{ar * b.x - ai * b.y, ar * b.y + ai * b.x};
+      if (a.aux) {
+        w.x += br * Au[z].x - bi * Au[z].y;
+        w.y += br * Au[z].y + bi * Au[z].x;
+      }
+      if (a.zout) {
+        __builtin_nontemporal_store(w.x, &a.zout[o + z * P].x);
+        __builtin_nontemporal_store(w.y, &a.zout[o + z * P].y);
+      }
+      X[z] = C2<R>{G[z] * w.x, G[z] * w.y};
+    }
+    slice_T3<R, NX, 1>(cf, lds, l, X);  // U^3T
+#pragma unroll
+    for (int z = 0; z < NX; ++z) {
+      __builtin_nontemporal_store(X[z].x, &a.dst[o + z * P].x);
+      __builtin_nontemporal_store(X[z].y, &a.dst[o + z * P].y);
+    }
+  }
+}
+
+template <typename R, int NX>
+int launch_basis_pair_nx(const Lattice& L, const PairArgs<R>& a) {
+  SplitCoef<R, NX> cb, cf;
+  int k = 0;
+  for (auto& v : cb.es) v = R(L.mode_bwd_host[k++]);
+  for (auto& v : cb.ea) v = R(L.mode_bwd_host[k++]);
+  for (auto& v : cb.os) v = R(L.mode_bwd_host[k++]);
+  for (auto& v : cb.oa) v = R(L.mode_bwd_host[k++]);
+  k = 0;
+  for (auto& v : cf.es) v = R(L.mode_fwd_host[k++]);
+  for (auto& v : cf.ea) v = R(L.mode_fwd_host[k++]);
+  for (auto& v : cf.os) v = R(L.mode_fwd_host[k++]);
+  for (auto& v : cf.oa) v = R(L.mode_fwd_host[k++]);
+  const int nslab = stream_nslab(L);
+  const size_t lds = size_t(lds_slice_elems<NX>()) * sizeof(C2<R>);
+  static bool attr = false;
+  if (!attr) {
+    UFG_HIP(hipFuncSetAttribute((const void*)basis_pair_kernel<R, NX>,
+                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+    attr = true;
+  }
+  hipLaunchKernelGGL((basis_pair_kernel<R, NX>), dim3(nslab * a.nrhs), dim3(NX * NX), lds,
+                     L.stream, a, cb, cf, L.ntau, nslab);
+  UFG_HIP(hipGetLastError());
+  return UFG_OK;
+}
+
 template <typename R, int NX, bool FWD, bool GENERAL>
 int launch_basis_one(const Lattice& L, const HopArgs<R>& a, const SplitCoef<R, NX>& c,
                      dim3 grid, size_t lds, int nslab) {
@@ -643,6 +750,43 @@ int launch_basis_stream(const Lattice& L, const HopArgs<R>& args, bool forward) 
   }
 }
 
+template <typename R>
+int launch_basis_pair(const Lattice& L, const C2<R>* x, C2<R>* y, C2<R>* zout, const R* post,
+                      double2 alpha, const C2<R>* aux, double2 beta, const R* mid, int nrhs,
+                      const int* gate) {
+  if (L.mode_perm.empty() || !stream_supported(L)) {
+    set_error("basis pair: needs the block form of U (nx in {8, 12, 16})");
+    return UFG_EINVAL;
+  }
+  if (x == nullptr || y == nullptr || (zout != nullptr && (zout == x || zout == y))) {
+    set_error("basis pair: bad vectors");
+    return UFG_EINVAL;
+  }
+  PairArgs<R> a;
+  a.src = x;
+  a.dst = y;
+  a.zout = zout;
+  a.post = post;
+  a.mid = mid;
+  a.alpha = alpha;
+  a.beta = beta;
+  a.aux = (beta.x == 0.0 && beta.y == 0.0) ? nullptr : aux;
+  a.gate = gate;
+  a.nrhs = nrhs;
+  switch (L.nx) {
+    case 8: return launch_basis_pair_nx<R, 8>(L, a);
+    case 12: return launch_basis_pair_nx<R, 12>(L, a);
+    case 16: return launch_basis_pair_nx<R, 16>(L, a);
+    default: set_error("basis pair: unsupported nx"); return UFG_EINVAL;
+  }
+}
+
+template int launch_basis_pair<float>(const Lattice&, const float2*, float2*, float2*,
+                                      const float*, double2, const float2*, double2,
+                                      const float*, int, const int*);
+template int launch_basis_pair<double>(const Lattice&, const double2*, double2*, double2*,
+                                       const double*, double2, const double2*, double2,
+                                       const double*, int, const int*);
 template int launch_basis_stream<float>(const Lattice&, const HopArgs<float>&, bool);
 template int launch_basis_stream<double>(const Lattice&, const HopArgs<double>&, bool);
 template int launch_hop_stream<float>(const Lattice&, const HopArgs<float>&);

@@ -13,6 +13,7 @@
 //     so every order of the expansion costs two spatial basis changes and one
 //     temporal sweep, with the M1 factor folded into them.
 #include "ops.h"
+#include "hop_stream.h"
 
 #include <cmath>
 #include <complex>
@@ -265,6 +266,53 @@ static int wce_apply(Lattice& L, const PcPlan& pc, bool adjoint, const C2<R>* x,
   const double2 one{1.0, 0.0}, zero{0.0, 0.0};
   const double A = L.A;
   const int d = pc.order;
+  // With the block form of U (streaming-supported nx), consecutive orders meet
+  // as U^3 then U^3T with only per-site factors between them: one launch does
+  // both (launch_basis_pair), and z_m is stored only where it is needed again.
+  const bool pair = d > 0 && stream_supported(L) && !L.mode_perm.empty();
+  if (pair && !adjoint) {
+    C2<R>* u0 = slot_vec<R>(L, SLOT_PC0 + 2, nrhs, &rc);
+    UFG_TRY(rc);
+    // mode space of u_0 = M0^{-1} x; then u_0 itself and U^3T (sin sigma u_0)
+    UFG_TRY(basis_change<R>(L, F.Ut, x, tmp, nrhs, gate, nullptr, nullptr, one, nullptr, zero));
+    UFG_TRY(launch_m0_temporal<R>(L, tmp, tmp, nrhs, false, false, gate));
+    cnt->m0inv += 1;
+    UFG_TRY(launch_basis_pair<R>(L, tmp, tmp, u0, nullptr, one, nullptr, zero, F.sn, nrhs, gate));
+    double scale = pc.w[d];
+    for (int m = d - 1; m >= 0; --m) {
+      // tmp holds U^3T (sin sigma z_{m+1}) up to `scale`; z_m = w_m u_0 + K z_{m+1}
+      UFG_TRY(launch_m0_temporal<R>(L, tmp, tmp, nrhs, false, true, gate));
+      const double2 al{A * scale, 0.0}, be{pc.w[m], 0.0};
+      if (m > 0) {
+        UFG_TRY(launch_basis_pair<R>(L, tmp, tmp, nullptr, nullptr, al, u0, be, F.sn, nrhs,
+                                     gate));
+      } else {
+        UFG_TRY(basis_change<R>(L, F.U, tmp, y, nrhs, gate, nullptr, nullptr, al, u0, be));
+      }
+      scale = 1.0;
+      cnt->m0inv += 1;
+      cnt->mv += 1;
+    }
+    return UFG_OK;
+  }
+  if (pair && adjoint) {
+    // z_m = w_m x + K' z_{m+1}, K' v = A S U^3 [(1 - lam Z^T)^{-1} - 1] U^3T v, acc = z_0;
+    // y = U^3 (1 - lam Z^T)^{-1} U^3T acc
+    UFG_TRY(basis_change<R>(L, F.Ut, x, tmp, nrhs, gate, nullptr, nullptr, one, nullptr, zero));
+    double scale = pc.w[d];
+    for (int m = d - 1; m >= 0; --m) {
+      UFG_TRY(launch_m0_temporal<R>(L, tmp, tmp, nrhs, true, true, gate));
+      UFG_TRY(launch_basis_pair<R>(L, tmp, tmp, nullptr, F.sn, double2{A * scale, 0.0}, x,
+                                   double2{pc.w[m], 0.0}, nullptr, nrhs, gate));
+      scale = 1.0;
+      cnt->m0inv += 1;
+      cnt->mv += 1;
+    }
+    UFG_TRY(launch_m0_temporal<R>(L, tmp, tmp, nrhs, true, false, gate));
+    UFG_TRY(basis_change<R>(L, F.U, tmp, y, nrhs, gate, nullptr, nullptr, one, nullptr, zero));
+    cnt->m0inv += 1;
+    return UFG_OK;
+  }
   if (!adjoint) {
     // u_0 = M0^{-1} x
     UFG_TRY(basis_change<R>(L, F.Ut, x, tmp, nrhs, gate, nullptr, nullptr, one, nullptr, zero));
