@@ -20,7 +20,7 @@ from gpu_util import require_gpu, to_dev, to_host, rel_err, say, TAU, G
 pytestmark = pytest.mark.gpu
 
 TOL = {torch.complex128: 1e-12, torch.complex64: 2e-5}
-SHAPES = [(4, 12, 2), (6, 9, 1), (8, 20, 3), (16, 5, 1)]
+SHAPES = [(4, 12, 2), (6, 9, 1), (8, 20, 3), (12, 7, 2), (16, 5, 1)]
 
 
 def _setup(nx, ntau, nrhs, dtype, seed):
