@@ -93,6 +93,11 @@ typedef struct {
  *   delta      reliable-update trigger: update when the inner residual has
  *              fallen below delta times its maximum since the last update.
  *   check_every  iterations between host convergence checks (>= 1).
+ *   eager      0: where the iteration is not fused into the streaming kernel
+ *              (preconditioned solves, CG, Nx outside {8, 12, 16}), every
+ *              check interval after the first replays a HIP graph captured
+ *              from the same launches (same results; fewer host launches for
+ *              small lattices). 1: launch every kernel separately.
  */
 typedef struct {
   double tol;
@@ -101,6 +106,7 @@ typedef struct {
   double delta;
   int check_every;
   int use_x0;
+  int eager;
 } ufg_solve_opts;
 
 /* Solve statistics (worst case over the right-hand sides). */

@@ -29,7 +29,8 @@ class ufg_precond(C.Structure):
 
 class ufg_solve_opts(C.Structure):
     _fields_ = [("tol", C.c_double), ("maxit", C.c_int), ("mixed", C.c_int),
-                ("delta", C.c_double), ("check_every", C.c_int), ("use_x0", C.c_int)]
+                ("delta", C.c_double), ("check_every", C.c_int), ("use_x0", C.c_int),
+                ("eager", C.c_int)]
 
 
 class ufg_solve_stats(C.Structure):
@@ -128,5 +129,6 @@ class Precond:
                            self.wce_order, int(self.euler), self.euler_p)
 
 
-def solve_opts(tol=1e-10, maxit=10000, mixed=False, delta=0.1, check_every=10, use_x0=False):
-    return ufg_solve_opts(tol, maxit, int(mixed), delta, check_every, int(use_x0))
+def solve_opts(tol=1e-10, maxit=10000, mixed=False, delta=0.1, check_every=10, use_x0=False,
+               eager=False):
+    return ufg_solve_opts(tol, maxit, int(mixed), delta, check_every, int(use_x0), int(eager))

@@ -26,6 +26,57 @@ namespace ufg {
 
 namespace {
 
+// One check interval of a solver's iterations, captured once on a private
+// stream and replayed on the lattice's stream. Small lattices run hundreds of
+// short launches per interval; a replay submits them at once. The body must
+// hold kernel launches only (no allocation, memset or copy): it runs after the
+// first interval has been launched eagerly, so every workspace and function
+// attribute exists already. Counters advanced by the host code of the body are
+// counted per replay.
+struct IntervalGraph {
+  hipGraph_t g = nullptr;
+  hipGraphExec_t e = nullptr;
+  hipStream_t cs = nullptr;
+  Counters delta;
+  ~IntervalGraph() {
+    if (e) (void)hipGraphExecDestroy(e);
+    if (g) (void)hipGraphDestroy(g);
+    if (cs) (void)hipStreamDestroy(cs);
+  }
+  template <typename F>
+  int capture(Lattice& L, Counters* cnt, F&& body) {
+    if (!cs) UFG_HIP(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking));
+    const Counters before = *cnt;
+    hipStream_t saved = L.stream;
+    L.stream = cs;
+    const hipError_t eb = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
+    int brc = (eb == hipSuccess) ? body() : UFG_EHIP;
+    hipGraph_t graph = nullptr;
+    const hipError_t ee = (eb == hipSuccess) ? hipStreamEndCapture(cs, &graph) : eb;
+    L.stream = saved;
+    g = graph;
+    if (eb != hipSuccess || ee != hipSuccess) {
+      (void)hipGetLastError();
+      set_error("solver: graph capture failed");
+      return UFG_EHIP;
+    }
+    UFG_TRY(brc);
+    UFG_HIP(hipGraphInstantiate(&e, g, nullptr, nullptr, 0));
+    delta.mv = cnt->mv - before.mv;
+    delta.m0inv = cnt->m0inv - before.m0inv;
+    delta.sca = cnt->sca - before.sca;
+    *cnt = before;
+    return UFG_OK;
+  }
+  int replay(const Lattice& L, Counters* cnt) {
+    UFG_HIP(hipGraphLaunch(e, L.stream));
+    cnt->mv += delta.mv;
+    cnt->m0inv += delta.m0inv;
+    cnt->sca += delta.sca;
+    return UFG_OK;
+  }
+};
+
 struct StepResult {
   int iters = 0;
   int status = 0;
@@ -221,8 +272,34 @@ int bicgstab_step(Lattice& L, const PcPlan& pc, int op, const C2<RO>* b, C2<RO>*
   UFG_TRY(read_flags(L, K, hflags.data(), &done));
   int cur = 0;          // P2[cur], V2[cur] hold the current p and v
   bool merged = false;  // p was formed by the merged x, r, p update
+  // one iteration of the unfused form (preconditioned, or a lattice without
+  // the streaming kernel); whole check intervals of it replay from a graph
+  auto classic_iteration = [&]() -> int {
+    UFG_TRY(k_bicg_p<RI>(L, V.r, V.p, V.v, K));
+    if (need_pc) UFG_TRY(pc_apply<RI>(L, pc, op, V.p, V.phat, nrhs, K.active, cnt));
+    UFG_TRY(op_apply<RI>(L, op, V.phat, V.v, nrhs, K.active, 1, V.rhat, K.part));
+    UFG_TRY(k_finalize(L, FIN_ALPHA, nhb, K.active, K));
+    UFG_TRY(k_bicg_s<RI>(L, V.r, V.v, V.s, K));
+    if (need_pc) UFG_TRY(pc_apply<RI>(L, pc, op, V.s, V.shat, nrhs, K.active, cnt));
+    UFG_TRY(op_apply<RI>(L, op, V.shat, V.t, nrhs, K.active, 2, V.s, K.part));
+    UFG_TRY(k_finalize(L, FIN_OMEGA, nhb, K.active, K));
+    UFG_TRY(k_bicg_xr<RI>(L, V.x, V.phat, V.shat, V.s, V.t, V.r, V.rhat, K));
+    UFG_TRY(k_finalize(L, FIN_RHO, nvb, K.active, K));
+    cnt->mv += 2;
+    return UFG_OK;
+  };
+  IntervalGraph G;
   for (it = 0; it < o.maxit && !done; ++it) {
     const bool check_it = (it + 1) % check == 0 || it + 1 == o.maxit;
+    // a whole check interval after the first one: replay the captured interval
+    const bool replay = !fused && !o.eager && it >= check && it % check == 0 &&
+                        it + check <= o.maxit;
+    if (replay && !G.e) {
+      UFG_TRY(G.capture(L, cnt, [&]() -> int {
+        for (int k = 0; k < check; ++k) UFG_TRY(classic_iteration());
+        return UFG_OK;
+      }));
+    }
     if (fused) {
       HopArgs<RI> a1;  // v = A p; <rhat, v>
       a1.mat = F.T;
@@ -277,19 +354,13 @@ int bicgstab_step(Lattice& L, const PcPlan& pc, int op, const C2<RO>* b, C2<RO>*
         UFG_TRY(k_bicg_xrp<RI>(L, V.x, P2[cur], V.r, V2[cur], V.t, K));
         merged = true;
       }
+      cnt->mv += 2;
+    } else if (replay) {
+      UFG_TRY(G.replay(L, cnt));
+      it += check - 1;  // the interval ends at the check point below
     } else {
-      UFG_TRY(k_bicg_p<RI>(L, V.r, V.p, V.v, K));
-      if (need_pc) UFG_TRY(pc_apply<RI>(L, pc, op, V.p, V.phat, nrhs, K.active, cnt));
-      UFG_TRY(op_apply<RI>(L, op, V.phat, V.v, nrhs, K.active, 1, V.rhat, K.part));
-      UFG_TRY(k_finalize(L, FIN_ALPHA, nhb, K.active, K));
-      UFG_TRY(k_bicg_s<RI>(L, V.r, V.v, V.s, K));
-      if (need_pc) UFG_TRY(pc_apply<RI>(L, pc, op, V.s, V.shat, nrhs, K.active, cnt));
-      UFG_TRY(op_apply<RI>(L, op, V.shat, V.t, nrhs, K.active, 2, V.s, K.part));
-      UFG_TRY(k_finalize(L, FIN_OMEGA, nhb, K.active, K));
-      UFG_TRY(k_bicg_xr<RI>(L, V.x, V.phat, V.shat, V.s, V.t, V.r, V.rhat, K));
-      UFG_TRY(k_finalize(L, FIN_RHO, nvb, K.active, K));
+      UFG_TRY(classic_iteration());
     }
-    cnt->mv += 2;
     if ((it + 1) % check == 0 || it + 1 == o.maxit) {
       UFG_TRY(read_flags(L, K, hflags.data(), &done));
       bool any_update = false, any_restart = false;
@@ -400,7 +471,7 @@ int cg_solve(Lattice& L, const PcPlan& pc, const C2<RO>* b, C2<RO>* x, int nrhs,
   const int check = o.check_every > 0 ? o.check_every : 10;
   bool done = false;
   UFG_TRY(read_flags(L, K, hflags.data(), &done));
-  for (int it = 0; it < o.maxit && !done; ++it) {
+  auto iteration = [&]() -> int {
     UFG_TRY(q_apply<RI>(L, V.p, V.tmp, V.w, nrhs, K.active, 1, V.p, K.part));
     UFG_TRY(k_finalize(L, FIN_CG_ALPHA, nhb, K.active, K));
     UFG_TRY(k_cg_xr<RI>(L, V.x, V.p, V.r, V.w, K));
@@ -411,7 +482,23 @@ int cg_solve(Lattice& L, const PcPlan& pc, const C2<RO>* b, C2<RO>* x, int nrhs,
       UFG_TRY(k_reduce<RI>(L, V.r, V.z, 1, K.active, K));
     }
     UFG_TRY(k_finalize(L, FIN_CG_BETA, nvb, K.active, K));
-    UFG_TRY(k_cg_p<RI>(L, V.z, V.p, K));
+    return k_cg_p<RI>(L, V.z, V.p, K);
+  };
+  IntervalGraph G;
+  for (int it = 0; it < o.maxit && !done; ++it) {
+    // whole check intervals after the first one replay a captured interval
+    if (!o.eager && it >= check && it % check == 0 && it + check <= o.maxit) {
+      if (!G.e) {
+        UFG_TRY(G.capture(L, cnt, [&]() -> int {
+          for (int k = 0; k < check; ++k) UFG_TRY(iteration());
+          return UFG_OK;
+        }));
+      }
+      UFG_TRY(G.replay(L, cnt));
+      it += check - 1;
+    } else {
+      UFG_TRY(iteration());
+    }
     if ((it + 1) % check == 0 || it + 1 == o.maxit) {
       UFG_TRY(read_flags(L, K, hflags.data(), &done));
       bool any_update = false;

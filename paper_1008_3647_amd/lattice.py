@@ -117,11 +117,11 @@ class Lattice:
         return torch.complex128 if mixed else self.dtype
 
     def solve_cg_normal(self, b, precond: Precond | None = None, tol=1e-10, maxit=10000,
-                        mixed=False, delta=0.1, check_every=10, x0=None):
+                        mixed=False, delta=0.1, check_every=10, x0=None, graph=True):
         dt = self._solve_dtype(mixed)
         n = self._vec(b, "b", dt)
         x = torch.empty_like(b) if x0 is None else x0
-        o = L.solve_opts(tol, maxit, mixed, delta, check_every, x0 is not None)
+        o = L.solve_opts(tol, maxit, mixed, delta, check_every, x0 is not None, not graph)
         st = L.ufg_solve_stats()
         p = precond.to_c() if precond else None
         code = self._lib.solve_cg_normal(self._h, C.byref(p) if p else None,
@@ -131,11 +131,12 @@ class Lattice:
         return x, st.as_dict()
 
     def solve_bicgstab(self, b, op="two_step", precond: Precond | None = None, tol=1e-10,
-                       maxit=10000, mixed=False, delta=0.1, check_every=10, x0=None):
+                       maxit=10000, mixed=False, delta=0.1, check_every=10, x0=None,
+                       graph=True):
         dt = self._solve_dtype(mixed)
         n = self._vec(b, "b", dt)
         x = torch.empty_like(b) if x0 is None else x0
-        o = L.solve_opts(tol, maxit, mixed, delta, check_every, x0 is not None)
+        o = L.solve_opts(tol, maxit, mixed, delta, check_every, x0 is not None, not graph)
         st = L.ufg_solve_stats()
         p = precond.to_c() if precond else None
         code = self._lib.solve_bicgstab(self._h, C.byref(p) if p else None, _OPS[op],
