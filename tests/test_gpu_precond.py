@@ -71,15 +71,16 @@ def test_wce(nx, ntau, nrhs, dtype, order, euler):
 
 
 @pytest.mark.parametrize("dtype", [torch.complex128, torch.complex64])
-@pytest.mark.parametrize("nx,ntau", [(8, 16), (8, 100), (4, 333), (4, 600)])
-def test_m0_inverse_on_device(nx, ntau, dtype):
+@pytest.mark.parametrize("nx,ntau,nrhs", [(8, 16, 2), (8, 100, 2), (4, 333, 2), (4, 600, 2),
+                                          (16, 40, 2), (16, 24, 4)])
+def test_m0_inverse_on_device(nx, ntau, nrhs, dtype):
     """WCE of order 0 is M0^{-1}; M0 (g = 0) undoes it. The temporal solve
-    splits each mode's time line into 8 chunks: the extents give chunks of 2,
-    13, 42 (the last one 39) and 75 slices."""
+    splits each mode's time line into 8 chunks (here of 2, 13, 42 with a last
+    one of 39, 75, 5 and 3 slices), 64 modes per workgroup."""
     require_gpu()
     from paper_1008_3647_amd import Lattice, Precond
-    say(f"m0 inverse nx={nx} ntau={ntau} {dtype}")
-    x = gaussian_rhs(nx, ntau, [650, 651])
+    say(f"m0 inverse nx={nx} ntau={ntau} nrhs={nrhs} {dtype}")
+    x = gaussian_rhs(nx, ntau, range(650, 650 + nrhs))
     L0 = Lattice(nx, ntau, TAU, 0.0, dtype)
     xd = to_dev(x, dtype)
     tol = 1e-13 if dtype == torch.complex128 else 5e-5  # FP32 recurrences over Ntau slices
