@@ -699,7 +699,10 @@ int launch_basis_nx(const Lattice& L, const HopArgs<R>& a, bool forward) {
 
 int stream_slab(const Lattice& L) {
   if (L.slab > 0) return std::min(L.slab, L.ntau);
-  return std::min(2, L.ntau);  // best measured for 16^3 slices with HBM-resident data
+  // two slices per workgroup measured best at 16^3 x 400; lattices below 2^20
+  // sites take one, which doubles the workgroups of their short launches
+  if ((long long)L.V * L.ntau < (1ll << 20)) return 1;
+  return std::min(2, L.ntau);
 }
 
 int stream_nslab(const Lattice& L) {
