@@ -99,6 +99,12 @@ def test_invalid_arguments_are_rejected():
         L.apply_M(torch.zeros((1, 4, 4, 4, 4), dtype=torch.complex64, device="cuda"))
     with pytest.raises(ValueError):
         L.apply_M(torch.zeros((1, 5, 4, 4, 4), dtype=torch.complex128, device="cuda"))
+    with pytest.raises(UfgError):
+        L.tune(slab=5)  # more slices per slab than Ntau
+    with pytest.raises(UfgError):
+        L.tune(nslab=5)  # more slabs than Ntau
+    with pytest.raises(UfgError):
+        L.tune(vec_blocks=5000)
 
 
 @pytest.mark.parametrize("dtype", [torch.complex128, torch.complex64])
