@@ -9,6 +9,7 @@ import pytest
 import torch
 
 import oracle
+from oracle import operator as oracle_op
 from synthetic import sigma_field, gaussian_rhs, WORKLOADS
 from gpu_util import require_gpu, to_dev, to_host, rel_err, say, TAU, G
 
@@ -170,3 +171,47 @@ def test_device_copy_helper():
     device_copy(x, y)
     torch.cuda.synchronize()
     assert torch.equal(x, y)
+
+
+def _slice_M(x, sigma, t, ntau):
+    """Output slice t of y = M x from the oracle's pieces (Eq. MatrixM): the
+    identity term plus the coupling of source slice t - 1."""
+    tp = (t - 1) % ntau
+    s = 1.0 if tp == ntau - 1 else -1.0
+    b = oracle_op.field_b(sigma[tp], oracle_op.coupling_A(TAU, G))
+    return x[t] + s * oracle_op.apply_expK(b * x[tp], TAU)
+
+
+def _slice_Mdag(x, sigma, t, ntau):
+    tn = (t + 1) % ntau
+    s = 1.0 if t == ntau - 1 else -1.0
+    b = oracle_op.field_b(sigma[t], oracle_op.coupling_A(TAU, G))
+    return x[t] + s * b * oracle_op.apply_expK(x[tn], TAU)
+
+
+@pytest.mark.parametrize("ntau", [32767, 32768])
+def test_largest_rhs_blocks(ntau):
+    """The streaming kernel addresses one right-hand side with 32-bit byte
+    offsets, so it takes complex128 blocks below 2^31 bytes (16^3 x 32767) and
+    larger ones (16^3 x 32768) go to the general slice kernel. Both must give
+    the operator: sampled output slices (first, wrap-around, middle, last)
+    against the oracle's slice formula."""
+    require_gpu()
+    from paper_1008_3647_amd import Lattice
+    nx = 16
+    say(f"largest blocks nx={nx} ntau={ntau}")
+    sigma = sigma_field(nx, 32768, 470)[:ntau]
+    x = gaussian_rhs(nx, 32768, [471])[0][:ntau]
+    L = Lattice(nx, ntau, TAU, G, torch.complex128)
+    L.set_aux_field(to_dev(sigma))
+    xd = to_dev(x[None])
+    y = L.apply_M(xd)
+    yd = L.apply_Mdag(xd)
+    for t in (0, 1, ntau // 2, ntau - 2, ntau - 1):
+        ref = _slice_M(x, sigma, t, ntau)
+        assert rel_err(to_host(y[0, t]), ref) < TOL[torch.complex128], t
+        refd = _slice_Mdag(x, sigma, t, ntau)
+        assert rel_err(to_host(yd[0, t]), refd) < TOL[torch.complex128], t
+    del y, yd, xd
+    L.close()
+    torch.cuda.empty_cache()
