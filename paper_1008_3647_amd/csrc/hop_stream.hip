@@ -490,7 +490,10 @@ int launch_nx(const Lattice& L, const HopArgs<R>& a) {
 // M = U^T (forward: positions -> block-ordered modes) or U (backward), then
 // GENERAL: y = alpha y + beta aux. A workgroup walks a slab of slices of one
 // right-hand side (XCD-aware numbering as above); the slices are independent.
-template <typename R, int NX, bool FWD, bool GENERAL>
+// SRC 1 / 2: x is built while loading as the BiCGStab p = r + beta (p - omega v)
+// or s = r - alpha v of the rhs state and stored to fpnew (the first basis
+// change of a weak-coupling application takes over the vector update).
+template <typename R, int NX, bool FWD, bool GENERAL, int SRC>
 __global__ void __launch_bounds__(NX * NX)
     basis_kernel(HopArgs<R> a, SplitCoef<R, NX> c, int ntau, int nslab) {
   constexpr int P = NX * NX, V = NX * NX * NX;
@@ -507,12 +510,30 @@ __global__ void __launch_bounds__(NX * NX)
   const int t0 = (int)((long long)sb * ntau / nslab);
   const int t1 = (int)((long long)(sb + 1) * ntau / nslab);
   const long long rbase = (long long)r * ntau * V;
+  const SrcScal<R> q = src_scalars<R, SRC>(a, r);
   for (int t = t0; t < t1; ++t) {
     const long long o = rbase + (long long)t * V + l;
     const long long fo = (long long)t * V + l;
     C2<R> X[NX];
+    if constexpr (SRC == 0) {
 #pragma unroll
-    for (int z = 0; z < NX; ++z) X[z] = a.src[o + z * P];
+      for (int z = 0; z < NX; ++z) X[z] = a.src[o + z * P];
+    } else {
+#pragma unroll
+      for (int z = 0; z < NX; ++z) {
+        const long long i = o + z * P;
+        const C2<R> rv = a.fr[i], vv = a.fv[i];
+        if constexpr (SRC == 1) {
+          const C2<R> pv = a.fp[i];
+          const R dx = pv.x - (q.wr * vv.x - q.wi * vv.y);
+          const R dy = pv.y - (q.wr * vv.y + q.wi * vv.x);
+          X[z] = C2<R>{rv.x + q.br * dx - q.bi * dy, rv.y + q.br * dy + q.bi * dx};
+        } else {
+          X[z] = C2<R>{rv.x - (q.ar * vv.x - q.ai * vv.y), rv.y - (q.ar * vv.y + q.ai * vv.x)};
+        }
+        a.fpnew[i] = X[z];
+      }
+    }
     if (a.pre) {
 #pragma unroll
       for (int z = 0; z < NX; ++z) {
@@ -660,17 +681,17 @@ int launch_basis_pair_nx(const Lattice& L, const PairArgs<R>& a) {
   return UFG_OK;
 }
 
-template <typename R, int NX, bool FWD, bool GENERAL>
+template <typename R, int NX, bool FWD, bool GENERAL, int SRC = 0>
 int launch_basis_one(const Lattice& L, const HopArgs<R>& a, const SplitCoef<R, NX>& c,
                      dim3 grid, size_t lds, int nslab) {
   static bool attr = false;
   if (!attr) {
-    UFG_HIP(hipFuncSetAttribute((const void*)basis_kernel<R, NX, FWD, GENERAL>,
+    UFG_HIP(hipFuncSetAttribute((const void*)basis_kernel<R, NX, FWD, GENERAL, SRC>,
                                 hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
     attr = true;
   }
-  hipLaunchKernelGGL((basis_kernel<R, NX, FWD, GENERAL>), grid, dim3(NX * NX), lds, L.stream, a,
-                     c, L.ntau, nslab);
+  hipLaunchKernelGGL((basis_kernel<R, NX, FWD, GENERAL, SRC>), grid, dim3(NX * NX), lds,
+                     L.stream, a, c, L.ntau, nslab);
   UFG_HIP(hipGetLastError());
   return UFG_OK;
 }
@@ -688,6 +709,14 @@ int launch_basis_nx(const Lattice& L, const HopArgs<R>& a, bool forward) {
   const size_t lds = size_t(lds_slice_elems<NX>()) * sizeof(C2<R>);
   const dim3 grid(nslab * a.nrhs);
   const bool general = (a.alpha.x != 1.0 || a.alpha.y != 0.0 || a.aux != nullptr);
+  if (forward && a.src_mode == 1 && !general)
+    return launch_basis_one<R, NX, true, false, 1>(L, a, c, grid, lds, nslab);
+  if (forward && a.src_mode == 2 && !general)
+    return launch_basis_one<R, NX, true, false, 2>(L, a, c, grid, lds, nslab);
+  if (a.src_mode != 0) {
+    set_error("basis change: a fused source needs the plain forward change");
+    return UFG_EINVAL;
+  }
   if (forward)
     return general ? launch_basis_one<R, NX, true, true>(L, a, c, grid, lds, nslab)
                    : launch_basis_one<R, NX, true, false>(L, a, c, grid, lds, nslab);
@@ -741,8 +770,13 @@ template <typename R>
 int launch_basis_stream(const Lattice& L, const HopArgs<R>& args, bool forward) {
   HopArgs<R> a = args;
   if (a.beta.x == 0.0 && a.beta.y == 0.0) a.aux = nullptr;
-  if (a.shift != 0 || a.red_mode != 0 || a.src_mode != 0 || a.id != nullptr) {
+  if (a.shift != 0 || a.red_mode != 0 || a.id != nullptr) {
     set_error("basis change: no shift, identity term or reduction");
+    return UFG_EINVAL;
+  }
+  if (a.src_mode != 0 && (a.src_mode > 2 || !a.fr || !a.fv || !a.fpnew || !a.st ||
+                          (a.src_mode == 1 && !a.fp))) {
+    set_error("basis change: incomplete fused source");
     return UFG_EINVAL;
   }
   switch (L.nx) {

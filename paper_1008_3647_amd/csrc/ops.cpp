@@ -256,7 +256,8 @@ static int basis_change(const Lattice& L, const R* mat, const C2<R>* x, C2<R>* y
 // polynomial: M0^{-T} (sum_m w_m K'^m x), K' = A S U^3 [(1 - lam Z^T)^{-1} - 1] U^3T.
 template <typename R>
 static int wce_apply(Lattice& L, const PcPlan& pc, bool adjoint, const C2<R>* x, C2<R>* y,
-                     int nrhs, const int* gate, Counters* cnt) {
+                     int nrhs, const int* gate, Counters* cnt,
+                     const PcSource<R>* src = nullptr) {
   const Fields<R>& F = fields<R>(L);
   int rc = 0;
   C2<R>* tmp = slot_vec<R>(L, SLOT_PC0 + 0, nrhs, &rc);
@@ -270,11 +271,34 @@ static int wce_apply(Lattice& L, const PcPlan& pc, bool adjoint, const C2<R>* x,
   // as U^3 then U^3T with only per-site factors between them: one launch does
   // both (launch_basis_pair), and z_m is stored only where it is needed again.
   const bool pair = d > 0 && stream_supported(L) && !L.mode_perm.empty();
+  if (src && (!pair || src->out != x)) {
+    set_error("weak-coupling apply: fused source without the paired basis changes");
+    return UFG_EINVAL;
+  }
+  // the first change U^3T x; with a fused source x is formed (and stored) here
+  auto first_change = [&]() -> int {
+    HopArgs<R> a;
+    a.src = x;
+    a.dst = tmp;
+    a.mat = F.Ut;
+    a.shift = kShiftNone;
+    a.nrhs = nrhs;
+    a.gate = gate;
+    if (src) {
+      a.src_mode = src->mode;
+      a.fr = src->r;
+      a.fp = src->p;
+      a.fv = src->v;
+      a.fpnew = src->out;
+      a.st = src->st;
+    }
+    return launch_hop<R>(L, a);
+  };
   if (pair && !adjoint) {
     C2<R>* u0 = slot_vec<R>(L, SLOT_PC0 + 2, nrhs, &rc);
     UFG_TRY(rc);
     // mode space of u_0 = M0^{-1} x; then u_0 itself and U^3T (sin sigma u_0)
-    UFG_TRY(basis_change<R>(L, F.Ut, x, tmp, nrhs, gate, nullptr, nullptr, one, nullptr, zero));
+    UFG_TRY(first_change());
     UFG_TRY(launch_m0_temporal<R>(L, tmp, tmp, nrhs, false, false, gate));
     cnt->m0inv += 1;
     UFG_TRY(launch_basis_pair<R>(L, tmp, tmp, u0, nullptr, one, nullptr, zero, F.sn, nrhs, gate));
@@ -298,7 +322,7 @@ static int wce_apply(Lattice& L, const PcPlan& pc, bool adjoint, const C2<R>* x,
   if (pair && adjoint) {
     // z_m = w_m x + K' z_{m+1}, K' v = A S U^3 [(1 - lam Z^T)^{-1} - 1] U^3T v, acc = z_0;
     // y = U^3 (1 - lam Z^T)^{-1} U^3T acc
-    UFG_TRY(basis_change<R>(L, F.Ut, x, tmp, nrhs, gate, nullptr, nullptr, one, nullptr, zero));
+    UFG_TRY(first_change());
     double scale = pc.w[d];
     for (int m = d - 1; m >= 0; --m) {
       UFG_TRY(launch_m0_temporal<R>(L, tmp, tmp, nrhs, true, true, gate));
@@ -425,9 +449,20 @@ static int q_pc_apply(Lattice& L, const PcPlan& pc, const C2<R>* x, C2<R>* y, in
   }
 }
 
+bool pc_fuses_source(const Lattice& L, const PcPlan& pc, int op) {
+  return pc.kind == UFG_PC_WCE && op != UFG_OP_Q && pc.order > 0 && stream_supported(L) &&
+         !L.mode_perm.empty();
+}
+
 template <typename R>
 int pc_apply(Lattice& L, const PcPlan& pc, int op, const C2<R>* x, C2<R>* y, int nrhs,
-             const int* gate, Counters* cnt) {
+             const int* gate, Counters* cnt, const PcSource<R>* src) {
+  if (src && !pc_fuses_source(L, pc, op)) {
+    set_error("preconditioner: no fused source for this plan");
+    return UFG_EINVAL;
+  }
+  if (src)
+    return wce_apply<R>(L, pc, op == UFG_OP_MDAG, x, y, nrhs, gate, cnt, src);
   if (pc.kind == UFG_PC_NONE) return k_axpby<R>(L, double2{1.0, 0.0}, x, double2{0.0, 0.0}, y,
                                                  nrhs, gate);
   if (op == UFG_OP_Q) return q_pc_apply<R>(L, pc, x, y, nrhs, gate, cnt);
@@ -498,7 +533,7 @@ static int estimate_lam_max(Lattice& L, double* out) {
   template int q_residual<R>(const Lattice&, const C2<R>*, const C2<R>*, C2<R>*, C2<R>*, int,    \
                              const int*);                                                        \
   template int pc_apply<R>(Lattice&, const PcPlan&, int, const C2<R>*, C2<R>*, int, const int*, \
-                           Counters*);
+                           Counters*, const PcSource<R>*);
 INST_OPS(float)
 INST_OPS(double)
 

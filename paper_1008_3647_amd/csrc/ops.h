@@ -44,10 +44,27 @@ int q_residual(const Lattice& L, const C2<R>* x, const C2<R>* b, C2<R>* tmp, C2<
 
 int resolve_precond(Lattice& L, const ufg_precond* p, PcPlan* out);
 
+// BiCGStab source formed inside a weak-coupling application: its first basis
+// change builds x from the rhs state while loading (mode 1: p = r + beta (p -
+// omega v), mode 2: s = r - alpha v), stores it to `out` (== the x passed to
+// pc_apply) and goes on from there. Only where pc_fuses_source holds.
+template <typename R>
+struct PcSource {
+  int mode = 0;
+  const C2<R>* r = nullptr;
+  const C2<R>* p = nullptr;
+  const C2<R>* v = nullptr;
+  C2<R>* out = nullptr;
+  const void* st = nullptr;  // RhsState array
+};
+
+bool pc_fuses_source(const Lattice& L, const PcPlan& pc, int op);
+
 // y = K^{-1} x for the plan and operator (table in ufg.h). y must not alias x.
+// With `src`, x is first formed as described for PcSource.
 template <typename R>
 int pc_apply(Lattice& L, const PcPlan& pc, int op, const C2<R>* x, C2<R>* y, int nrhs,
-             const int* gate, Counters* cnt);
+             const int* gate, Counters* cnt, const PcSource<R>* src = nullptr);
 
 // Workspace slots (each holds nrhs vectors of the requested type).
 enum Slot {

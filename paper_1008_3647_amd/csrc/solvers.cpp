@@ -274,13 +274,36 @@ int bicgstab_step(Lattice& L, const PcPlan& pc, int op, const C2<RO>* b, C2<RO>*
   bool merged = false;  // p was formed by the merged x, r, p update
   // one iteration of the unfused form (preconditioned, or a lattice without
   // the streaming kernel); whole check intervals of it replay from a graph
+  // a weak-coupling preconditioner forms p and s in its first basis change
+  const bool fuse_src = need_pc && pc_fuses_source(L, pc, op);
   auto classic_iteration = [&]() -> int {
-    UFG_TRY(k_bicg_p<RI>(L, V.r, V.p, V.v, K));
-    if (need_pc) UFG_TRY(pc_apply<RI>(L, pc, op, V.p, V.phat, nrhs, K.active, cnt));
+    if (fuse_src) {
+      PcSource<RI> ps;
+      ps.mode = 1;
+      ps.r = V.r;
+      ps.p = V.p;
+      ps.v = V.v;
+      ps.out = V.p;
+      ps.st = K.st;
+      UFG_TRY(pc_apply<RI>(L, pc, op, V.p, V.phat, nrhs, K.active, cnt, &ps));
+    } else {
+      UFG_TRY(k_bicg_p<RI>(L, V.r, V.p, V.v, K));
+      if (need_pc) UFG_TRY(pc_apply<RI>(L, pc, op, V.p, V.phat, nrhs, K.active, cnt));
+    }
     UFG_TRY(op_apply<RI>(L, op, V.phat, V.v, nrhs, K.active, 1, V.rhat, K.part));
     UFG_TRY(k_finalize(L, FIN_ALPHA, nhb, K.active, K));
-    UFG_TRY(k_bicg_s<RI>(L, V.r, V.v, V.s, K));
-    if (need_pc) UFG_TRY(pc_apply<RI>(L, pc, op, V.s, V.shat, nrhs, K.active, cnt));
+    if (fuse_src) {
+      PcSource<RI> ps;
+      ps.mode = 2;
+      ps.r = V.r;
+      ps.v = V.v;
+      ps.out = V.s;
+      ps.st = K.st;
+      UFG_TRY(pc_apply<RI>(L, pc, op, V.s, V.shat, nrhs, K.active, cnt, &ps));
+    } else {
+      UFG_TRY(k_bicg_s<RI>(L, V.r, V.v, V.s, K));
+      if (need_pc) UFG_TRY(pc_apply<RI>(L, pc, op, V.s, V.shat, nrhs, K.active, cnt));
+    }
     UFG_TRY(op_apply<RI>(L, op, V.shat, V.t, nrhs, K.active, 2, V.s, K.part));
     UFG_TRY(k_finalize(L, FIN_OMEGA, nhb, K.active, K));
     UFG_TRY(k_bicg_xr<RI>(L, V.x, V.phat, V.shat, V.s, V.t, V.r, V.rhat, K));
