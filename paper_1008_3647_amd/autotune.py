@@ -25,10 +25,11 @@ DEFAULT_CACHE = os.path.join(os.environ.get("XDG_CACHE_HOME", os.path.expanduser
                              "ufg_mi355x", "tune.json")
 
 
-def _key(L: Lattice, nrhs, mixed):
+def _key(L: Lattice, nrhs, mixed, precond=None):
     dev = torch.cuda.get_device_properties(L.device)
     arch = getattr(dev, "gcnArchName", dev.name)
-    return f"{arch}|{L.nx}|{L.ntau}|{nrhs}|{L.dtype}|{int(mixed)}"
+    key = f"{arch}|{L.nx}|{L.ntau}|{nrhs}|{L.dtype}|{int(mixed)}"
+    return key if precond is None else f"{key}|{precond!r}"
 
 
 def _load(path):
@@ -58,11 +59,12 @@ def candidate_slabs(L: Lattice):
 
 def tune(L: Lattice, b: torch.Tensor, mixed=False, op="M", iters=16, reps=2,
          vec_blocks=(0, 32, 64, 128, 256, 512), cache: str | None = DEFAULT_CACHE,
-         force=False, verbose=False):
-    """Pick (slab, vec_blocks) for solves of `b` on `L`; returns a dict with the
+         force=False, verbose=False, precond=None):
+    """Pick (slab, vec_blocks) for solves of `b` on `L` (with `precond`, whose
+    basis-change launches follow the same slab choice); returns a dict with the
     choice and the timings of every candidate."""
     nrhs = b.shape[0]
-    key = _key(L, nrhs, mixed)
+    key = _key(L, nrhs, mixed, precond)
     data = _load(cache) if cache else {}
     if not force and key in data:
         best = data[key]
@@ -72,12 +74,13 @@ def tune(L: Lattice, b: torch.Tensor, mixed=False, op="M", iters=16, reps=2,
     for slab in candidate_slabs(L):
         for vb in vec_blocks:
             L.tune(slab, vb)
-            L.solve_bicgstab(b, op, tol=1e-30, maxit=2, mixed=mixed)  # warm-up
+            L.solve_bicgstab(b, op, precond=precond, tol=1e-30, maxit=2, mixed=mixed)  # warm-up
             best_t = float("inf")
             for _ in range(reps):
                 torch.cuda.synchronize()
                 t0 = time.perf_counter()
-                L.solve_bicgstab(b, op, tol=1e-30, maxit=iters, mixed=mixed, check_every=iters)
+                L.solve_bicgstab(b, op, precond=precond, tol=1e-30, maxit=iters, mixed=mixed,
+                                 check_every=iters)
                 torch.cuda.synchronize()
                 best_t = min(best_t, time.perf_counter() - t0)
             results.append(dict(slab=slab, vec_blocks=vb, seconds=best_t))

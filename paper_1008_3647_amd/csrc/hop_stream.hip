@@ -148,13 +148,13 @@ __device__ __forceinline__ __amdgpu_buffer_rsrc_t make_rsrc(const void* p, unsig
   return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(p), 0, (int)bytes, kRsrcWord3);
 }
 
-template <typename R>
+template <typename R, int AUX = 0>
 __device__ __forceinline__ C2<R> bload(__amdgpu_buffer_rsrc_t rs, int vo, int so) {
   if constexpr (sizeof(R) == 4) {
-    const u32x2 v = __builtin_amdgcn_raw_buffer_load_b64(rs, vo, so, 0);
+    const u32x2 v = __builtin_amdgcn_raw_buffer_load_b64(rs, vo, so, AUX);
     return __builtin_bit_cast(C2<R>, v);
   } else {
-    const u32x4 v = __builtin_amdgcn_raw_buffer_load_b128(rs, vo, so, 0);
+    const u32x4 v = __builtin_amdgcn_raw_buffer_load_b128(rs, vo, so, AUX);
     return __builtin_bit_cast(C2<R>, v);
   }
 }
@@ -195,7 +195,8 @@ struct Rsrc {
 };
 
 // z-line of the source slice at byte offset so (uniform); vo = lane byte offset.
-template <typename R, int NX, int SRC>
+// AUX: cache policy of the loads (kAuxNT for slices that no other workgroup reads).
+template <typename R, int NX, int SRC, int AUX>
 __device__ __forceinline__ void load_source(const Rsrc& b, const SrcScal<R>& q, int so, int vo,
                                             C2<R> (&X)[NX]) {
   constexpr int ZB = NX * NX * (int)sizeof(C2<R>);
@@ -203,16 +204,16 @@ __device__ __forceinline__ void load_source(const Rsrc& b, const SrcScal<R>& q, 
   for (int z = 0; z < NX; ++z) {
     const int s = so + z * ZB;
     if (SRC == 0) {
-      X[z] = bload<R>(b.src, vo, s);
+      X[z] = bload<R, AUX>(b.src, vo, s);
     } else if (SRC == 1) {
-      const C2<R> rv = bload<R>(b.fr, vo, s), pv = bload<R>(b.fp, vo, s),
-                  vv = bload<R>(b.fv, vo, s);
+      const C2<R> rv = bload<R, AUX>(b.fr, vo, s), pv = bload<R, AUX>(b.fp, vo, s),
+                  vv = bload<R, AUX>(b.fv, vo, s);
       const R dx = pv.x - (q.wr * vv.x - q.wi * vv.y);
       const R dy = pv.y - (q.wr * vv.y + q.wi * vv.x);
       X[z].x = rv.x + q.br * dx - q.bi * dy;
       X[z].y = rv.y + q.br * dy + q.bi * dx;
     } else {
-      const C2<R> rv = bload<R>(b.fr, vo, s), vv = bload<R>(b.fv, vo, s);
+      const C2<R> rv = bload<R, AUX>(b.fr, vo, s), vv = bload<R, AUX>(b.fv, vo, s);
       X[z].x = rv.x - (q.ar * vv.x - q.ai * vv.y);
       X[z].y = rv.y - (q.ar * vv.y + q.ai * vv.x);
     }
@@ -249,6 +250,10 @@ __global__ void __launch_bounds__(NX * NX)
     hop_stream_kernel(HopArgs<R> a, SplitCoef<R, NX> c, int ntau, int nslab) {
   constexpr int P = NX * NX, V = NX * NX * NX;
   constexpr int ES = sizeof(C2<R>), FS = sizeof(R);
+  // Single-use operand slices are loaded non-temporal (measured: faster for
+  // every complex64 variant and the fused complex128 ones, slower for the
+  // plain complex128 operator, which keeps the default policy).
+  constexpr int kNTA = (sizeof(R) == 4 || SRC != 0 || RED != 0) ? kAuxNT : 0;
   extern __shared__ __align__(16) unsigned char smem_raw[];
   C2<R>* lds = reinterpret_cast<C2<R>*>(smem_raw);
 
@@ -292,13 +297,18 @@ __global__ void __launch_bounds__(NX * NX)
   // is also the first thing it writes in the next transform).
   C2<R> X[NX];
   const int ly = l / NX, lx = l - (l / NX) * NX;
-  load_source<R, NX, SRC>(b, q, th * V * ES, vo, X);
+  load_source<R, NX, SRC, 0>(b, q, th * V * ES, vo, X);
   if (DIR < 0) scale_field<R, NX>(b.pre, th * V * FS, fo, X);
   slice_T3<R, NX, 0, true>(c, lds, l, X);
   for (int k = 0; k < count; ++k) {
     const int t = tfirst + k * step;
     const int so = t * V * ES;  // slice byte offset (uniform)
-    load_source<R, NX, SRC>(b, q, so, vo, X);
+    // the last slice of the slab is the halo of the neighbouring slab: it
+    // stays cacheable, the others are streamed
+    if (k + 1 < count)
+      load_source<R, NX, SRC, kNTA>(b, q, so, vo, X);
+    else
+      load_source<R, NX, SRC, 0>(b, q, so, vo, X);
     if (SRC == 1) {
 #pragma unroll
       for (int z = 0; z < NX; ++z) bstore<R, false>(X[z], a.fpnew + rbase, b.fpnew, vo, so + z * P * ES);
@@ -325,12 +335,12 @@ __global__ void __launch_bounds__(NX * NX)
       C2<R> U[GENERAL ? ZC : 1];
       if (GENERAL && a.aux) {
 #pragma unroll
-        for (int j = 0; j < ZC; ++j) U[j] = bload<R>(b.aux, vo, so + (z0 + j) * P * ES);
+        for (int j = 0; j < ZC; ++j) U[j] = bload<R, kNTA>(b.aux, vo, so + (z0 + j) * P * ES);
       }
       C2<R> Wr[(RED == 1 || RED == 2 || RED == 4) ? ZC : 1];
       if (RED == 1 || RED == 2 || RED == 4) {
 #pragma unroll
-        for (int j = 0; j < ZC; ++j) Wr[j] = bload<R>(b.rw, vo, so + (z0 + j) * P * ES);
+        for (int j = 0; j < ZC; ++j) Wr[j] = bload<R, kNTA>(b.rw, vo, so + (z0 + j) * P * ES);
       }
 #pragma unroll
       for (int j = 0; j < ZC; ++j) {

@@ -191,3 +191,54 @@ def test_graph_replay_matches_eager_launches(case):
     kind = "Q" if case.startswith("cg") else None
     if kind:
         assert _relres_oracle(x1, b, sigma, "Q") <= 1.5e-10
+
+
+@pytest.mark.parametrize("op_name", ["M", "Mdag", "two_step"])
+@pytest.mark.parametrize("mixed", [False, True])
+def test_wce_bicgstab_fused_sources(op_name, mixed):
+    """With the weak-coupling preconditioner on a streaming lattice, the first
+    basis change of each application forms BiCGStab's p and s itself. The
+    result must satisfy the oracle's residual for M, M^T and the two-step
+    solve, in FP64 and FP32-refined; Nx = 12 with Ntau = 30 (uneven slabs)."""
+    require_gpu()
+    from paper_1008_3647_amd import Lattice, Precond
+    nx, ntau = 12, 30
+    sigma = sigma_field(nx, ntau, 471)
+    b = gaussian_rhs(nx, ntau, [472, 473])
+    say(f"wce2 bicgstab {op_name} mixed={mixed}")
+    L = Lattice(nx, ntau, TAU, G, torch.complex128)
+    L.set_aux_field(to_dev(sigma))
+    tol = 1e-10
+    x, st = L.solve_bicgstab(to_dev(b), op_name, Precond("wce", wce_order=2), tol=tol,
+                             mixed=mixed, check_every=7)
+    say(st)
+    assert st["status"] == 0
+    xh = to_host(x)
+    kind = "Q" if op_name == "two_step" else op_name
+    # two-step: per-step residuals <= tol give ||b - Q x|| <~ cond(M) tol
+    bound = 1.2 * tol if kind != "Q" else 1e-7
+    assert _relres_oracle(xh, b, sigma, kind) <= bound
+
+
+def test_autotune_with_preconditioner():
+    """The autotuner times candidates on the preconditioned solve when given
+    one; its choice is applied to the lattice and the solve still converges to
+    the oracle's residual."""
+    require_gpu()
+    from paper_1008_3647_amd import Lattice, Precond
+    from paper_1008_3647_amd.autotune import tune
+    nx, ntau = 8, 24
+    sigma = sigma_field(nx, ntau, 481)
+    b = gaussian_rhs(nx, ntau, [482, 483])
+    L = Lattice(nx, ntau, TAU, G, torch.complex128)
+    L.set_aux_field(to_dev(sigma))
+    pc = Precond("wce", wce_order=2)
+    bd = to_dev(b)
+    t = tune(L, bd, mixed=True, op="M", iters=4, reps=1, vec_blocks=(0, 64), cache=None,
+             precond=pc)
+    say({k: t[k] for k in ("slab", "vec_blocks")})
+    assert len(t["candidates"]) == 2 * len([s for s in (1, 2, 3, 4, 6, 8) if s <= ntau])
+    assert t["slab"] in (1, 2, 3, 4, 6, 8) and t["vec_blocks"] in (0, 64)
+    x, st = L.solve_bicgstab(bd, "M", pc, tol=1e-10, mixed=True)
+    assert st["status"] == 0
+    assert _relres_oracle(to_host(x), b, sigma, "M") <= 1.2e-10
