@@ -92,7 +92,11 @@ typedef struct {
  *              FP64 reductions; b and x are complex128 (lattice dtype C128).
  *   delta      reliable-update trigger: update when the inner residual has
  *              fallen below delta times its maximum since the last update.
- *   check_every  iterations between host convergence checks (>= 1).
+ *   check_every  iterations between check points (>= 1). Reliable updates
+ *              and restarts happen at check points. In BiCGStab the host reads
+ *              the flags of a check point at the next one (it never waits for
+ *              the device there), so a solve ends up to two intervals after
+ *              convergence on launches that do no work; CG reads them at once.
  *   eager      0: where the iteration is not fused into the streaming kernel
  *              (preconditioned solves, CG, Nx outside {8, 12, 16}), every
  *              check interval after the first replays a HIP graph captured

@@ -34,6 +34,39 @@ void DevBuf::release() {
   bytes = 0;
 }
 
+int FlagMirror::ensure(int n) {
+  if (host && n <= cap) return UFG_OK;
+  release();
+  if (hipHostMalloc(reinterpret_cast<void**>(&host), 2 * sizeof(int) * n,
+                    hipHostMallocDefault) != hipSuccess) {
+    host = nullptr;
+    (void)hipGetLastError();
+    set_error("hipHostMalloc failed for the solver flags");
+    return UFG_ENOMEM;
+  }
+  cap = n;
+  for (hipEvent_t& e : ev) {
+    if (hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess) {
+      e = nullptr;
+      (void)hipGetLastError();
+      release();
+      set_error("hipEventCreate failed");
+      return UFG_EHIP;
+    }
+  }
+  return UFG_OK;
+}
+
+void FlagMirror::release() {
+  for (hipEvent_t& e : ev) {
+    if (e) (void)hipEventDestroy(e);
+    e = nullptr;
+  }
+  if (host) (void)hipHostFree(host);
+  host = nullptr;
+  cap = 0;
+}
+
 int solve_bicgstab_impl(Lattice& L, const ufg_precond* p, int op, const void* b, void* x,
                         int nrhs, const ufg_solve_opts* o, ufg_solve_stats* st);
 int solve_cg_impl(Lattice& L, const ufg_precond* p, const void* b, void* x, int nrhs,

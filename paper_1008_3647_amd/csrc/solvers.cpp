@@ -311,6 +311,14 @@ int bicgstab_step(Lattice& L, const PcPlan& pc, int op, const C2<RO>* b, C2<RO>*
     cnt->mv += 2;
     return UFG_OK;
   };
+  // Check points do not wait for the device. The reliable update and the
+  // restart are issued at every check point as launches gated per rhs by
+  // their device flags; the flags are then copied behind them to pinned host
+  // memory, which the host reads at the next check point, when that copy has
+  // long completed. The loop so ends one check interval late, on launches that
+  // do nothing (every rhs is inactive by then).
+  UFG_TRY(L.flags.ensure(3 * nrhs));
+  int posted = 0;
   IntervalGraph G;
   for (it = 0; it < o.maxit && !done; ++it) {
     const bool check_it = (it + 1) % check == 0 || it + 1 == o.maxit;
@@ -385,15 +393,22 @@ int bicgstab_step(Lattice& L, const PcPlan& pc, int op, const C2<RO>* b, C2<RO>*
       UFG_TRY(classic_iteration());
     }
     if ((it + 1) % check == 0 || it + 1 == o.maxit) {
-      UFG_TRY(read_flags(L, K, hflags.data(), &done));
-      bool any_update = false, any_restart = false;
-      for (int i = 0; i < nrhs; ++i) {
-        any_update |= hflags[nrhs + i] != 0;
-        any_restart |= hflags[2 * nrhs + i] != 0;
+      UFG_TRY(reliable_update());
+      UFG_TRY(restart());
+      const int slot = posted & 1;
+      int* mirror = L.flags.host + slot * L.flags.cap;
+      UFG_HIP(hipMemcpyAsync(mirror, K.active, 3 * sizeof(int) * nrhs, hipMemcpyDeviceToHost,
+                             L.stream));
+      UFG_HIP(hipEventRecord(L.flags.ev[slot], L.stream));
+      ++posted;
+      if (posted >= 2) {  // the previous check point's flags
+        const int prev = slot ^ 1;
+        UFG_HIP(hipEventSynchronize(L.flags.ev[prev]));
+        const int* f = L.flags.host + prev * L.flags.cap;
+        done = true;
+        for (int i = 0; i < nrhs; ++i)
+          if (f[i]) done = false;
       }
-      if (any_update) UFG_TRY(reliable_update());
-      if (any_restart) UFG_TRY(restart());
-      if (any_update || any_restart) UFG_TRY(read_flags(L, K, hflags.data(), &done));
     }
   }
   if (kMixed) {

@@ -71,6 +71,17 @@ struct DevBuf {
   ~DevBuf() { release(); }
 };
 
+// Pinned host mirror of solver flags: two slots of `cap` ints, each with an
+// event recorded behind the copy into it.
+struct FlagMirror {
+  int* host = nullptr;
+  int cap = 0;
+  hipEvent_t ev[2] = {nullptr, nullptr};
+  int ensure(int n);
+  void release();
+  ~FlagMirror() { release(); }
+};
+
 struct Lattice {
   int nx = 0, ntau = 0, dtype = UFG_C128;
   int V = 0;        // nx^3
@@ -94,6 +105,7 @@ struct Lattice {
   DevBuf red;               // reduction partials
   DevBuf state;             // solver state
   DevBuf cheb;              // Chebyshev roots on device
+  FlagMirror flags;         // check-point flags read one interval late
   double lam_max_cache = -1.0;
   int lam_max_valid = 0;
 };

@@ -144,7 +144,9 @@ def test_lattice_16x400_against_oracle_reference(mixed):
     say(f"16x400 two-step mixed={mixed}")
     L = Lattice(nx, ntau, TAU, G, torch.complex128)
     L.set_aux_field(to_dev(sigma))
-    x, st = L.solve_bicgstab(to_dev(b), "two_step", tol=1e-10, mixed=mixed, maxit=20000)
+    # check interval as bench.py times it
+    x, st = L.solve_bicgstab(to_dev(b), "two_step", tol=1e-10, mixed=mixed, maxit=20000,
+                             check_every=40)
     say(st)
     assert st["status"] == 0 and max(st["relres"]) <= 1e-10
     x0 = to_host(x[0])
