@@ -766,6 +766,7 @@ int run_batched(std::vector<Lattice*>& Ls, const void* const* bu, void* const* x
   check += check & 1;
   std::vector<RhsState> hst(S);
   std::vector<int> hflags(3 * S);
+  FlagMirror mirror;
   std::vector<int> iters_step[2];
   std::vector<double> relres_step[2];
   std::vector<int> status(nprob, 0);
@@ -907,38 +908,38 @@ int run_batched(std::vector<Lattice*>& Ls, const void* const* bu, void* const* x
     UFG_HIP(hipMemcpyAsync(hflags.data(), K.active, sizeof(int) * 3 * S, hipMemcpyDeviceToHost, cs));
     UFG_HIP(hipStreamSynchronize(cs));
     done = std::all_of(hflags.begin(), hflags.begin() + S, [](int v) { return v == 0; });
+    // After each check interval the reliable update (x64 += x_in, r64 = b - A
+    // x64, r = r64) and the restart are issued as launches gated per system by
+    // their device flags; the flags are then copied behind them to pinned
+    // memory, which the host reads after issuing the next interval. A system
+    // inactive there stays inactive (only active systems raise update flags),
+    // so the work tables may drop it one interval late, and the loop ends one
+    // interval late on launches that do nothing.
+    UFG_TRY(mirror.ensure(3 * S));
     for (int n = 0; n < launches && !done; ++n) {
       UFG_HIP(hipGraphLaunch(G.e, cs));
-      UFG_HIP(hipMemcpyAsync(hflags.data(), K.active, sizeof(int) * 3 * S, hipMemcpyDeviceToHost,
-                             cs));
-      UFG_HIP(hipStreamSynchronize(cs));
-      bool any_update = false, any_restart = false;
-      for (int s = 0; s < S; ++s) {
-        any_update |= hflags[S + s] != 0;
-        any_restart |= hflags[2 * S + s] != 0;
-      }
-      if (any_update) {  // reliable update: x64 += x_in, r64 = b - A x64, r = r64
-        vop(4, K.update, VA);
-        UFG_TRY(residual(K.update));
-        vop(5, K.update, VA);
-        UFG_TRY(k_finalize_seg(cs, FIN_UPDATE, vpart, vf, vc, K.update, K));
-      }
-      if (any_restart) {
-        vop(6, K.restart, VA);
-        UFG_TRY(k_finalize_seg(cs, FIN_RESTART, vpart, vf, vc, K.restart, K));
-      }
+      vop(4, K.update, VA);
+      UFG_TRY(residual(K.update));
+      vop(5, K.update, VA);
+      UFG_TRY(k_finalize_seg(cs, FIN_UPDATE, vpart, vf, vc, K.update, K));
+      vop(6, K.restart, VA);
+      UFG_TRY(k_finalize_seg(cs, FIN_RESTART, vpart, vf, vc, K.restart, K));
       UFG_HIP(hipGetLastError());
-      UFG_HIP(hipMemcpyAsync(hflags.data(), K.active, sizeof(int) * 3 * S, hipMemcpyDeviceToHost,
-                             cs));
-      UFG_HIP(hipStreamSynchronize(cs));
-      const int nactive = (int)std::count_if(hflags.begin(), hflags.begin() + S,
-                                             [](int v) { return v != 0; });
+      const int slot = n & 1;
+      UFG_HIP(hipMemcpyAsync(mirror.host + slot * mirror.cap, K.active, sizeof(int) * 3 * S,
+                             hipMemcpyDeviceToHost, cs));
+      UFG_HIP(hipEventRecord(mirror.ev[slot], cs));
+      if (n == 0) continue;
+      UFG_HIP(hipEventSynchronize(mirror.ev[slot ^ 1]));
+      const int* f = mirror.host + (slot ^ 1) * mirror.cap;
+      const int nactive = (int)std::count_if(f, f + S, [](int v) { return v != 0; });
       done = nactive == 0;
       // once half of the covered systems have stopped, drop them from the work
       // tables so that the tail of the batch launches only the live work
       if (!done && 2 * nactive <= in_tables) {
         std::vector<char> live(S);
-        for (int s = 0; s < S; ++s) live[s] = hflags[s] != 0;
+        for (int s = 0; s < S; ++s) live[s] = f[s] != 0;
+        UFG_HIP(hipStreamSynchronize(cs));  // the tables are in use until here
         make_tables(live);
         UFG_TRY(upload_tables());
         UFG_TRY(capture());
