@@ -385,7 +385,7 @@ def main():
     tuned = None
     if not a.no_tune:
         from paper_1008_3647_amd.autotune import tune
-        t = tune(L, b, mixed=True, op="M", cache=None)
+        t = tune(L, b, mixed=True, op="M", cache=None, precond=pc)
         tuned = dict(slab=t["slab"], vec_blocks=t["vec_blocks"])
 
     # Check interval of the unpreconditioned solve: a check point costs an
