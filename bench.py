@@ -40,7 +40,7 @@ def parse():
     ap.add_argument("--precond", default="none", choices=["none", "wce2"])
     ap.add_argument("--slab", type=int, default=0, help="--mv-only: slab size (0 = default)")
     ap.add_argument("--mv-warmup-ms", type=float, default=500.0,
-                    help="--mv-only: wall time of warm-up launches before the timed ones")
+                    help="wall time of apply_M warm-up launches before the timed ones")
     ap.add_argument("--no-secondary", action="store_true",
                     help="skip the WCE2-preconditioned solve reported beside the primary one")
     ap.add_argument("--no-tune", action="store_true",
@@ -470,11 +470,20 @@ def main():
         Lm.set_aux_field(sigma)
         xs = [b.to(dt) for _ in range(ROT)]
         ys = [torch.empty_like(xs[0]) for _ in range(ROT)]
-        # warm-up touches every buffer pair with both operators
+        # warm-up: every buffer pair with both operators, then launches for
+        # `mv_warmup_ms` of wall time so that the timed launches run at the
+        # clocks of a busy device
         for i in range(2 * ROT):
             Lm.apply_M(xs[i % ROT], ys[i % ROT])
             Lm.apply_Mdag(xs[i % ROT], ys[i % ROT])
         torch.cuda.synchronize()
+        t_end = time.perf_counter() + a.mv_warmup_ms * 1e-3
+        i = 0
+        while time.perf_counter() < t_end:
+            for _ in range(20):
+                Lm.apply_M(xs[i % ROT], ys[i % ROT])
+                i += 1
+            torch.cuda.synchronize()
         e0 = torch.cuda.Event(enable_timing=True)
         e1 = torch.cuda.Event(enable_timing=True)
         res = {}
