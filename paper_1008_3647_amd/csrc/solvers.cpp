@@ -319,6 +319,7 @@ int bicgstab_step(Lattice& L, const PcPlan& pc, int op, const C2<RO>* b, C2<RO>*
   // do nothing (every rhs is inactive by then).
   UFG_TRY(L.flags.ensure(3 * nrhs));
   int posted = 0;
+  Counters at_prev_post;  // the counters when the previous flags were posted
   IntervalGraph G;
   for (it = 0; it < o.maxit && !done; ++it) {
     const bool check_it = (it + 1) % check == 0 || it + 1 == o.maxit;
@@ -401,6 +402,7 @@ int bicgstab_step(Lattice& L, const PcPlan& pc, int op, const C2<RO>* b, C2<RO>*
                              L.stream));
       UFG_HIP(hipEventRecord(L.flags.ev[slot], L.stream));
       ++posted;
+      const Counters at_post = *cnt;
       if (posted >= 2) {  // the previous check point's flags
         const int prev = slot ^ 1;
         UFG_HIP(hipEventSynchronize(L.flags.ev[prev]));
@@ -408,7 +410,11 @@ int bicgstab_step(Lattice& L, const PcPlan& pc, int op, const C2<RO>* b, C2<RO>*
         done = true;
         for (int i = 0; i < nrhs; ++i)
           if (f[i]) done = false;
+        // every rhs was inactive when those flags were taken: what was issued
+        // since then did no work and is not counted
+        if (done) *cnt = at_prev_post;
       }
+      at_prev_post = at_post;
     }
   }
   if (kMixed) {

@@ -115,6 +115,12 @@ def test_bicgstab_check_interval(op_name, mixed):
         x, st = L.solve_bicgstab(to_dev(b), op_name, tol=tol, mixed=mixed, check_every=check)
         say(st)
         assert st["status"] == 0
+        if not mixed:
+            # the interval the loop issues after every rhs stopped (the host
+            # reads check-point flags one interval late) is not counted: the
+            # launched iterations end at the check point that confirmed
+            n = max(st["iters"])
+            assert st["mv"] == 2 * check * (-(-n // check))
         xh = to_host(x)
         assert _relres_oracle(xh, b, sigma, op_name) <= 1.2 * tol
         sols.append(xh)
@@ -242,5 +248,33 @@ def test_autotune_with_preconditioner():
     assert len(t["candidates"]) == 2 * len([s for s in (1, 2, 3, 4, 6, 8) if s <= ntau])
     assert t["slab"] in (1, 2, 3, 4, 6, 8) and t["vec_blocks"] in (0, 64)
     x, st = L.solve_bicgstab(bd, "M", pc, tol=1e-10, mixed=True)
+    assert st["status"] == 0
+    assert _relres_oracle(to_host(x), b, sigma, "M") <= 1.2e-10
+
+
+@pytest.mark.parametrize("mixed", [False, True])
+@pytest.mark.parametrize("check", [1, 4, 10])
+def test_bicgstab_iteration_cap_then_fresh_solve(mixed, check):
+    """A solve stopped by the iteration cap reports status 1 with the capped
+    iteration count and its true residual (checked by the oracle), whatever
+    the check interval (the host reads check-point flags one interval late).
+    A following solve on the same lattice starts from a clean state and
+    converges."""
+    require_gpu()
+    from paper_1008_3647_amd import Lattice
+    nx, ntau = 8, 40
+    sigma = sigma_field(nx, ntau, 491)
+    b = gaussian_rhs(nx, ntau, [492, 493])
+    L = Lattice(nx, ntau, TAU, G, torch.complex128)
+    L.set_aux_field(to_dev(sigma))
+    say(f"cap mixed={mixed} check={check}")
+    x, st = L.solve_bicgstab(to_dev(b), "M", tol=1e-12, maxit=15, mixed=mixed, check_every=check)
+    say(st)
+    assert st["status"] == 1
+    assert st["iters"][0] == 15
+    rel = _relres_oracle(to_host(x), b, sigma, "M")
+    assert rel == pytest.approx(max(st["relres"]), rel=1e-6)
+    assert rel > 1e-12
+    x, st = L.solve_bicgstab(to_dev(b), "M", tol=1e-10, mixed=mixed, check_every=check)
     assert st["status"] == 0
     assert _relres_oracle(to_host(x), b, sigma, "M") <= 1.2e-10
