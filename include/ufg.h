@@ -93,10 +93,10 @@ typedef struct {
  *   delta      reliable-update trigger: update when the inner residual has
  *              fallen below delta times its maximum since the last update.
  *   check_every  iterations between check points (>= 1). Reliable updates
- *              and restarts happen at check points. In BiCGStab the host reads
- *              the flags of a check point at the next one (it never waits for
- *              the device there), so a solve ends up to two intervals after
- *              convergence on launches that do no work; CG reads them at once.
+ *              and restarts happen at check points. The host reads the flags
+ *              of a check point at the next one (it never waits for the device
+ *              there), so a solve ends up to two intervals after convergence
+ *              on launches that do no work (not counted in the statistics).
  *   eager      0: where the iteration is not fused into the streaming kernel
  *              (preconditioned solves, CG, Nx outside {8, 12, 16}), every
  *              check interval after the first replays a HIP graph captured

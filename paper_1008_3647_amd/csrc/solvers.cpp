@@ -490,7 +490,10 @@ int cg_solve(Lattice& L, const PcPlan& pc, const C2<RO>* b, C2<RO>* x, int nrhs,
   UFG_TRY(k_finalize(L, FIN_CG_INIT_RZ, nvb, nullptr, K));
   UFG_TRY(k_convert<RI, RI>(L, V.z, V.p, nrhs, nullptr));
 
+  Counters pc_cost;  // what one refresh of z adds to the counters
   auto reliable_update = [&]() -> int {
+    UFG_HIP(hipMemcpyAsync(K.restart, K.update, sizeof(int) * nrhs, hipMemcpyDeviceToDevice,
+                           L.stream));
     if (kMixed) {
       UFG_TRY(k_promote(L, reinterpret_cast<double2*>(x), reinterpret_cast<float2*>(V.x), nrhs,
                         K.update));
@@ -503,12 +506,15 @@ int cg_solve(Lattice& L, const PcPlan& pc, const C2<RO>* b, C2<RO>* x, int nrhs,
       UFG_TRY(k_reduce<RI>(L, V.r, nullptr, 0, K.update, K));
     }
     UFG_TRY(k_finalize(L, FIN_UPDATE, nvb, K.update, K));
-    // the search direction is kept; rz is refreshed from the new residual
+    // the search direction is kept; z and rz are refreshed from the new
+    // residual of the updated systems (their set travels in the restart
+    // flags, which CG does not use otherwise)
     if (need_pc) {
-      UFG_TRY(pc_apply<RI>(L, pc, UFG_OP_Q, V.r, V.z, nrhs, K.active, cnt));
-      UFG_TRY(k_reduce<RI>(L, V.r, V.z, 1, K.active, K));
+      pc_cost = Counters{};
+      UFG_TRY(pc_apply<RI>(L, pc, UFG_OP_Q, V.r, V.z, nrhs, K.restart, &pc_cost));
+      UFG_TRY(k_reduce<RI>(L, V.r, V.z, 1, K.restart, K));
     }
-    return k_finalize(L, FIN_CG_INIT_RZ, nvb, K.active, K);
+    return k_finalize(L, FIN_CG_INIT_RZ, nvb, K.restart, K);
   };
 
   std::vector<int> hflags(3 * nrhs);
@@ -528,6 +534,28 @@ int cg_solve(Lattice& L, const PcPlan& pc, const C2<RO>* b, C2<RO>* x, int nrhs,
     UFG_TRY(k_finalize(L, FIN_CG_BETA, nvb, K.active, K));
     return k_cg_p<RI>(L, V.z, V.p, K);
   };
+  // Check points do not wait for the device (as in BiCGStab): the reliable
+  // update runs as launches gated per rhs by the device flags, and the flags
+  // are read from pinned memory at the next check point. A refresh of z is
+  // counted when the flags show that it had work.
+  UFG_TRY(L.flags.ensure(3 * nrhs));
+  int posted = 0, last_read = 0;
+  long long refreshes = 0;
+  Counters at_prev_post;
+  auto read_posted = [&](int k) -> int {  // flags of the k-th check point (1-based)
+    const int slot = (k - 1) & 1;
+    UFG_HIP(hipEventSynchronize(L.flags.ev[slot]));
+    const int* f = L.flags.host + slot * L.flags.cap;
+    done = true;
+    bool refreshed = false;
+    for (int i = 0; i < nrhs; ++i) {
+      if (f[i]) done = false;
+      if (f[2 * nrhs + i]) refreshed = true;
+    }
+    if (refreshed) ++refreshes;
+    last_read = k;
+    return UFG_OK;
+  };
   IntervalGraph G;
   for (int it = 0; it < o.maxit && !done; ++it) {
     // whole check intervals after the first one replay a captured interval
@@ -544,15 +572,25 @@ int cg_solve(Lattice& L, const PcPlan& pc, const C2<RO>* b, C2<RO>* x, int nrhs,
       UFG_TRY(iteration());
     }
     if ((it + 1) % check == 0 || it + 1 == o.maxit) {
-      UFG_TRY(read_flags(L, K, hflags.data(), &done));
-      bool any_update = false;
-      for (int i = 0; i < nrhs; ++i) any_update |= hflags[nrhs + i] != 0;
-      if (any_update) {
-        UFG_TRY(reliable_update());
-        UFG_TRY(read_flags(L, K, hflags.data(), &done));
+      UFG_TRY(reliable_update());
+      const int slot = posted & 1;
+      UFG_HIP(hipMemcpyAsync(L.flags.host + slot * L.flags.cap, K.active, 3 * sizeof(int) * nrhs,
+                             hipMemcpyDeviceToHost, L.stream));
+      UFG_HIP(hipEventRecord(L.flags.ev[slot], L.stream));
+      ++posted;
+      const Counters at_post = *cnt;
+      if (posted >= 2) {
+        UFG_TRY(read_posted(posted - 1));
+        // every rhs had stopped there: the interval issued since did no work
+        if (done) *cnt = at_prev_post;
       }
+      at_prev_post = at_post;
     }
   }
+  if (posted > last_read) UFG_TRY(read_posted(posted));
+  cnt->mv += refreshes * pc_cost.mv;
+  cnt->m0inv += refreshes * pc_cost.m0inv;
+  cnt->sca += refreshes * pc_cost.sca;
   if (kMixed) {
     UFG_TRY(k_promote(L, reinterpret_cast<double2*>(x), reinterpret_cast<float2*>(V.x), nrhs,
                       nullptr));
