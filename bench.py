@@ -45,7 +45,8 @@ def parse():
                     help="skip the WCE2-preconditioned solve reported beside the primary one")
     ap.add_argument("--no-tune", action="store_true",
                     help="skip the launch-shape autotuner (run before the timed region)")
-    ap.add_argument("--report", choices=["config2", "batched", "batched_solve", "force"],
+    ap.add_argument("--report",
+                    choices=["config2", "batched", "batched_solve", "force", "mv_sweep"],
                     help="print the measurement table of another workload (markdown) "
                          "instead of the JSON line")
     ap.add_argument("--mv-only", action="store_true",
@@ -354,11 +355,68 @@ def report_force(a):
     return 0
 
 
+def report_mv_sweep(a):
+    """apply_M / apply_Mdag bandwidth across lattice sizes and right-hand-side
+    counts (library-default launch shapes). Each timed loop cycles through
+    enough (x, y) pairs for a working set of at least 1.25 GB (as the main
+    measurement does; at most 16 pairs), far above the 256 MB Infinity Cache;
+    smaller working sets are marked cache-resident."""
+    import torch
+    from synthetic import sigma_field, gaussian_rhs
+    from paper_1008_3647_amd import Lattice
+    shapes = [(8, 160, 1), (8, 160, 8), (12, 200, 1), (12, 200, 8), (16, 100, 8), (16, 400, 1),
+              (16, 400, 2), (16, 400, 4), (16, 400, 8), (16, 800, 8), (16, 400, 16),
+              (16, 1600, 8)]
+    print("| lattice | rhs | dtype | MB per launch | apply_M us | GB/s | of 8 TB/s "
+          "| apply_Mdag us | GB/s | operands |")
+    print("|---|---|---|---|---|---|---|---|---|---|")
+    for nx, ntau, nrhs in shapes:
+        N = nx ** 3 * ntau
+        sigma = torch.from_numpy(sigma_field(nx, ntau, 7001)).cuda()
+        b = torch.from_numpy(gaussian_rhs(nx, ntau, list(range(7002, 7002 + nrhs)))).cuda()
+        for dt, c, f in ((torch.complex64, 8, 4), (torch.complex128, 16, 8)):
+            L = Lattice(nx, ntau, 0.05, 5.0, dt)
+            L.set_aux_field(sigma)
+            alg = N * (nrhs * 2 * c + f)
+            pair = 2 * N * nrhs * c
+            rot = max(1, min(16, -(-1_250_000_000 // pair)))
+            xs = [b.to(dt) for _ in range(rot)]
+            ys = [torch.empty_like(xs[0]) for _ in range(rot)]
+            res = []
+            for fn in (L.apply_M, L.apply_Mdag):
+                t_end = time.perf_counter() + 0.2
+                i = 0
+                while time.perf_counter() < t_end:
+                    for _ in range(10):
+                        fn(xs[i % rot], ys[i % rot])
+                        i += 1
+                    torch.cuda.synchronize()
+                e0 = torch.cuda.Event(enable_timing=True)
+                e1 = torch.cuda.Event(enable_timing=True)
+                n = 100
+                e0.record()
+                for i in range(n):
+                    fn(xs[i % rot], ys[i % rot])
+                e1.record()
+                torch.cuda.synchronize()
+                us = e0.elapsed_time(e1) / n * 1e3
+                res.append((us, alg / us / 1e3))
+            resident = "HBM" if rot * pair > 300_000_000 else "cache-resident"
+            name = "c64" if dt == torch.complex64 else "c128"
+            print(f"| {nx}^3 x {ntau} | {nrhs} | {name} | {alg / 1e6:.1f} | {res[0][0]:.1f} | "
+                  f"{res[0][1]:.0f} | {res[0][1] / 8000:.2f} | {res[1][0]:.1f} | {res[1][1]:.0f} | "
+                  f"{resident} |", flush=True)
+            del xs, ys, L
+            torch.cuda.empty_cache()
+    return 0
+
+
 def main():
     a = parse()
     if a.report:
         return {"config2": report_config2, "batched": report_batched,
-                "batched_solve": report_batched_solve, "force": report_force}[a.report](a)
+                "batched_solve": report_batched_solve, "force": report_force,
+                "mv_sweep": report_mv_sweep}[a.report](a)
     if a.mv_only:
         return mv_only(a)
     if a.gpus != 1:
