@@ -323,7 +323,7 @@ __global__ void __launch_bounds__(NX * NX)
     // chunk (field, aux, reduction weights) are loaded ahead of its stores
     // (loads cannot be moved across buffer stores). complex128 with a
     // reduction uses half-slice chunks to stay within the register file.
-    constexpr int ZC = ((sizeof(R) == 8 && (GENERAL || RED != 0)) || RED == 4) ? NX / 2 : NX;
+    constexpr int ZC = (sizeof(R) == 8 && (GENERAL || RED != 0)) ? NX / 2 : NX;
 #pragma unroll
     for (int z0 = 0; z0 < NX; z0 += ZC) {
       R F[DIR > 0 ? ZC : 1];
