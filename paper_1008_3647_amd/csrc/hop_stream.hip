@@ -33,6 +33,7 @@
 // one partial per workgroup.
 #include "hop_stream.h"
 #include "krylov.h"
+#include "krylov_fin.h"
 #include "split_line.h"
 
 namespace ufg {
@@ -284,7 +285,67 @@ __global__ void __launch_bounds__(NX * NX)
   b.pre = make_rsrc(a.pre, fbytes);
   b.post = make_rsrc(a.post, fbytes);
   const int vo = l * ES, fo = l * FS;
-  const SrcScal<R> q = src_scalars<R, SRC>(a, r);
+  SrcScal<R> q = src_scalars<R, SRC>(a, r);
+  if constexpr (SRC == 2 && RED == 4) {
+    if (a.fin_part) {  // the alpha step of the rhs state, see HopArgs
+      // thread 0 fetches the state and flags while every thread sums partials
+      RhsState* st = reinterpret_cast<RhsState*>(const_cast<void*>(a.st));
+      int* fl = a.fin_flags;
+      RhsState qs{};
+      int act = 0, upd = 0, rst = 0;
+      if (l == 0) {
+        qs = st[r];
+        act = fl[r];
+        upd = fl[a.nrhs + r];
+        rst = fl[2 * a.nrhs + r];
+      }
+      double v[8];
+#pragma unroll
+      for (int j = 0; j < 8; ++j) v[j] = 0.0;
+      for (int bi = l; bi < a.fin_nblk; bi += P) {
+        const double* pp = a.fin_part + ((long long)r * a.fin_nblk + bi) * 4;
+#pragma unroll
+        for (int j = 0; j < 4; ++j) v[j] += pp[j];
+      }
+      for (int bi = l; bi < a.fin_nblk2; bi += P) {
+        const double* pp = a.fin_part2 + ((long long)r * a.fin_nblk2 + bi) * 4;
+#pragma unroll
+        for (int j = 0; j < 4; ++j) v[4 + j] += pp[j];
+      }
+      constexpr int NW = (P + 63) / 64;
+      double* sm = reinterpret_cast<double*>(smem_raw);
+      const int lane = l & 63, wid = l >> 6;
+#pragma unroll
+      for (int j = 0; j < 8; ++j) {
+        const double w = wsum(v[j]);
+        if (lane == 0) sm[wid * 8 + j] = w;
+      }
+      __syncthreads();
+      if (l == 0) {
+        double s8[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+        for (int w = 0; w < NW; ++w)
+#pragma unroll
+          for (int j = 0; j < 8; ++j) s8[j] += sm[w * 8 + j];
+        apply_fin(FIN_ALPHA_XR, s8, qs, act, upd, rst, a.fin_prm);
+        if (sb == 0) {
+          st[r] = qs;
+          fl[r] = act;
+          fl[a.nrhs + r] = upd;
+          fl[2 * a.nrhs + r] = rst;
+        }
+        sm[NW * 8] = qs.alpha.x;
+        sm[NW * 8 + 1] = qs.alpha.y;
+        sm[NW * 8 + 2] = act ? 1.0 : 0.0;
+      }
+      __syncthreads();
+      const double alx = sm[NW * 8], aly = sm[NW * 8 + 1];
+      const bool live = sm[NW * 8 + 2] != 0.0;
+      __syncthreads();  // the LDS slice is written next
+      if (!live) return;
+      q.ar = R(alx);
+      q.ai = R(aly);
+    }
+  }
   const int count = t1 - t0;
   // first output slice, step, and the halo slice that feeds it
   const int tfirst = (DIR < 0) ? t0 : t1 - 1;
@@ -761,6 +822,12 @@ template <typename R>
 int launch_hop_stream(const Lattice& L, const HopArgs<R>& args) {
   HopArgs<R> a = args;
   if (a.beta.x == 0.0 && a.beta.y == 0.0) a.aux = nullptr;
+  if (a.fin_part && !(a.src_mode == 2 && a.red_mode == 4 && a.fin_part2 && a.fin_flags &&
+                      a.st && a.fin_nblk > 0 && a.fin_nblk2 > 0)) {
+    set_error("streaming kernel: the fused alpha step needs source 2, reduction 4 and its "
+              "partials, state and flags");
+    return UFG_EINVAL;
+  }
   // M-type applies the field to the source slice, M^T-type to the output slice
   const bool fields_ok = (a.shift < 0) ? (a.pre != nullptr && a.post == nullptr)
                                        : (a.post != nullptr && a.pre == nullptr);

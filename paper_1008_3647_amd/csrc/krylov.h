@@ -18,15 +18,6 @@ struct RhsState {
   int iters, updates, conv, status;
 };
 
-struct KrylovParams {
-  double tol;
-  double delta2;  // reliable-update threshold squared
-  int mixed;
-  int bicg;       // 1: BiCGStab (rho = <rhat, r> refreshed at updates)
-  int unprec;     // CG without preconditioner: <r, z> = |r|^2
-  int limit_omega;  // BiCGStab: keep |cos(t, s)| >= 0.7 (complex spectra)
-};
-
 struct KrylovState {
   int nrhs = 0;
   RhsState* st = nullptr;
@@ -35,6 +26,7 @@ struct KrylovState {
   int* restart = nullptr;
   double* part = nullptr;   // [nrhs][nblk][4] (8 per block for the streaming reduction mode 4)
   double* part2 = nullptr;  // [nrhs][vector blocks][4]: partials kept across one operator launch
+  double* part3 = nullptr;  // [nrhs][operator blocks][4]: partials read by the next operator launch
   KrylovParams prm{};
 };
 

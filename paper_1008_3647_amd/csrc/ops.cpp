@@ -44,14 +44,17 @@ int krylov_state(Lattice& L, int nrhs, KrylovState* K, int slot_red) {
   const size_t flag_bytes = sizeof(int) * nrhs;
   const size_t red_bytes = sizeof(double) * 8 * (size_t)nblk * nrhs;
   const size_t red2_bytes = sizeof(double) * 4 * (size_t)vec_blocks(L, nrhs) * nrhs;
+  const size_t red3_bytes = sizeof(double) * 4 * (size_t)hop_blocks_per_rhs(L) * nrhs;
   DevBuf& b = L.work[slot_red];
-  UFG_TRY(b.ensure(st_bytes + 3 * flag_bytes + red_bytes + red2_bytes + 256));
+  UFG_TRY(b.ensure(st_bytes + 3 * flag_bytes + red_bytes + red2_bytes + red3_bytes + 256));
   char* p = reinterpret_cast<char*>(b.p);
   K->nrhs = nrhs;
   K->part = reinterpret_cast<double*>(p);
   p += red_bytes;
   K->part2 = reinterpret_cast<double*>(p);
   p += red2_bytes;
+  K->part3 = reinterpret_cast<double*>(p);
+  p += red3_bytes;
   K->st = reinterpret_cast<RhsState*>(p);
   p += st_bytes;
   K->active = reinterpret_cast<int*>(p);

@@ -129,6 +129,16 @@ enum HopShift { kShiftM = -1, kShiftNone = 0, kShiftMdag = +1 };
 //   dst_t = alpha * base + beta * aux_t               (aux may be null)
 // sgn_t = s_{ts} for shift -1, s_t for shift +1, +1 for shift 0.
 // `gate` (may be null): rhs r is skipped unless gate[r] != 0.
+// Parameters of the Krylov scalar updates (shared by every rhs of a solve).
+struct KrylovParams {
+  double tol;
+  double delta2;  // reliable-update threshold squared
+  int mixed;
+  int bicg;       // 1: BiCGStab (rho = <rhat, r> refreshed at updates)
+  int unprec;     // CG without preconditioner: <r, z> = |r|^2
+  int limit_omega;  // BiCGStab: keep |cos(t, s)| >= 0.7 (complex spectra)
+};
+
 template <typename R>
 struct HopArgs {
   const C2<R>* src = nullptr;
@@ -160,6 +170,21 @@ struct HopArgs {
   const C2<R>* fv = nullptr;
   C2<R>* fpnew = nullptr;
   const void* st = nullptr;  // RhsState array
+  // Finalize performed by the launch (streaming kernel, src_mode 2 with
+  // red_mode 4): before forming s, every workgroup sums the partials of its
+  // rhs (fin_part [nrhs][fin_nblk][4] from the previous operator launch,
+  // fin_part2 [nrhs][fin_nblk2][4] from the vector update before it) in a
+  // fixed order and applies the BiCGStab alpha step (FIN_ALPHA_XR) to the rhs
+  // state `st`; the workgroup of slab 0 stores the new state and the flags
+  // fin_flags = active, update, restart ([3][nrhs]). That step changes none
+  // of the state fields that alpha and the active flag derive from, so a
+  // workgroup that reads the state after slab 0 stored it derives the same.
+  const double* fin_part = nullptr;
+  const double* fin_part2 = nullptr;
+  int fin_nblk = 0;
+  int fin_nblk2 = 0;
+  int* fin_flags = nullptr;
+  KrylovParams fin_prm{};
 };
 
 template <typename R>
