@@ -227,6 +227,15 @@ __device__ __forceinline__ BScal<R> bsrc_scalars(const BSrc<R>& b, int seg) {
   return q;
 }
 
+// Non-temporal load of one element (operands the launch reads once).
+template <typename R>
+__device__ __forceinline__ C2<R> ldnt(const C2<R>* p) {
+  C2<R> v;
+  v.x = __builtin_nontemporal_load(&p->x);
+  v.y = __builtin_nontemporal_load(&p->y);
+  return v;
+}
+
 // z-line of the source at element offset o (segment offset included)
 template <typename R, int NX, int SRC>
 __device__ __forceinline__ void bsource(const C2<R>* src, const BSrc<R>& b, const BScal<R>& q,
@@ -332,11 +341,11 @@ __global__ void __launch_bounds__(bop_threads(NX))
         C2<R> B[RES ? NX : 1], Q[NX];
         if (RES) {
 #pragma unroll
-          for (int z = 0; z < NX; ++z) B[RES ? z : 0] = aux[o + z * P];
+          for (int z = 0; z < NX; ++z) B[RES ? z : 0] = ldnt<R>(aux + o + z * P);
         }
         if (red_mode == 1 || SRC == 3) {
 #pragma unroll
-          for (int z = 0; z < NX; ++z) Q[z] = redw[o + z * P];
+          for (int z = 0; z < NX; ++z) Q[z] = ldnt<R>(redw + o + z * P);
         }
 #pragma unroll
         for (int z = 0; z < NX; ++z) {
@@ -345,7 +354,9 @@ __global__ void __launch_bounds__(bop_threads(NX))
             const C2<R> bb = B[RES ? z : 0];
             out = mk<R>(bb.x - out.x, bb.y - out.y);
           }
-          dst[o + z * P] = out;
+          // y is not re-read by this launch
+          __builtin_nontemporal_store(out.x, &dst[o + z * P].x);
+          __builtin_nontemporal_store(out.y, &dst[o + z * P].y);
           if (red_mode == 1) {  // <w, y>
             a0 += double(Q[z].x) * out.x + double(Q[z].y) * out.y;
             a1 += double(Q[z].x) * out.y - double(Q[z].y) * out.x;
