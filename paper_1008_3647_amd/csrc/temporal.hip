@@ -196,10 +196,14 @@ __global__ void __launch_bounds__(kModes* kChunks)
     C2<R> prev = carry[c][ml];
 #pragma unroll 8
     for (int k = s0; k < s1; ++k) {
+      // last use of v here, and u is not re-read by this launch
       const long long i = at(k);
-      const C2<R> q = v[i];
+      const C2<R> q =
+          C2<R>{__builtin_nontemporal_load(&v[i].x), __builtin_nontemporal_load(&v[i].y)};
       prev = C2<R>{q.x + lam * prev.x, q.y + lam * prev.y};
-      u[i] = subtract ? C2<R>{prev.x - q.x, prev.y - q.y} : prev;
+      const C2<R> o = subtract ? C2<R>{prev.x - q.x, prev.y - q.y} : prev;
+      __builtin_nontemporal_store(o.x, &u[i].x);
+      __builtin_nontemporal_store(o.y, &u[i].y);
     }
   }
 }
