@@ -52,6 +52,19 @@ __device__ void bsum4(double a0, double a1, double a2, double a3, double* out) {
   }
 }
 
+// Non-temporal access of one element (operands a kernel touches for the last
+// time, or x, which only the update kernels touch): keeps the cache for the
+// vectors the next launches read.
+template <typename R>
+__device__ __forceinline__ C2<R> ldnt(const C2<R>* p) {
+  return c2<R>(__builtin_nontemporal_load(&p->x), __builtin_nontemporal_load(&p->y));
+}
+template <typename R>
+__device__ __forceinline__ void stnt(C2<R> v, C2<R>* p) {
+  __builtin_nontemporal_store(v.x, &p->x);
+  __builtin_nontemporal_store(v.y, &p->y);
+}
+
 #define KR_LOOP(n) \
   for (long long i = blockIdx.x * 256ll + threadIdx.x; i < (n); i += (long long)gridDim.x * 256)
 
@@ -104,11 +117,13 @@ __global__ void __launch_bounds__(256) bicg_xr_kernel(C2<R>* x, const C2<R>* pha
   double d0 = 0, d1 = 0, d2 = 0;
   KR_LOOP(n) {
     const long long j = off + i;
-    const C2<R> pv = phat[j], sv = shat[j], ss = s[j], tv = t[j], h = rhat[j];
-    C2<R> xv = x[j];
+    // phat, shat, s and t are used for the last time in this iteration
+    const C2<R> pv = ldnt<R>(phat + j), sv = ldnt<R>(shat + j), ss = ldnt<R>(s + j);
+    const C2<R> tv = ldnt<R>(t + j), h = rhat[j];
+    C2<R> xv = ldnt<R>(x + j);
     xv.x += (ar * pv.x - ai * pv.y) + (wr * sv.x - wi * sv.y);
     xv.y += (ar * pv.y + ai * pv.x) + (wr * sv.y + wi * sv.x);
-    x[j] = xv;
+    stnt<R>(xv, x + j);
     const C2<R> rv = c2<R>(ss.x - (wr * tv.x - wi * tv.y), ss.y - (wr * tv.y + wi * tv.x));
     r[j] = rv;
     d0 += double(h.x) * rv.x + double(h.y) * rv.y;
@@ -134,12 +149,13 @@ __global__ void __launch_bounds__(256) bicg_xr_fused_kernel(C2<R>* x, const C2<R
   double d0 = 0, d1 = 0, d2 = 0;
   KR_LOOP(n) {
     const long long j = off + i;
-    const C2<R> pv = p[j], vv = v[j], tv = t[j], h = rhat[j], rv = r[j];
+    // p and v are read again by the p update after the check point, t is not
+    const C2<R> pv = p[j], vv = v[j], tv = ldnt<R>(t + j), h = rhat[j], rv = r[j];
     const C2<R> sv = c2<R>(rv.x - (ar * vv.x - ai * vv.y), rv.y - (ar * vv.y + ai * vv.x));
-    C2<R> xv = x[j];
+    C2<R> xv = ldnt<R>(x + j);
     xv.x += (ar * pv.x - ai * pv.y) + (wr * sv.x - wi * sv.y);
     xv.y += (ar * pv.y + ai * pv.x) + (wr * sv.y + wi * sv.x);
-    x[j] = xv;
+    stnt<R>(xv, x + j);
     const C2<R> rn = c2<R>(sv.x - (wr * tv.x - wi * tv.y), sv.y - (wr * tv.y + wi * tv.x));
     r[j] = rn;
     d0 += double(h.x) * rn.x + double(h.y) * rn.y;
@@ -167,12 +183,15 @@ __global__ void __launch_bounds__(256) bicg_xrp_kernel(C2<R>* x, C2<R>* p, C2<R>
   double d2 = 0;
   KR_LOOP(n) {
     const long long j = off + i;
-    const C2<R> pv = p[j], vv = v[j], tv = t[j], rv = r[j];
-    C2<R> xv = x[j];
+    // x is touched only here, v and t for the last time in this iteration:
+    // non-temporal, so that r and p stay cached for the next launches
+    const C2<R> pv = p[j], rv = r[j];
+    const C2<R> vv = ldnt<R>(v + j), tv = ldnt<R>(t + j);
+    C2<R> xv = ldnt<R>(x + j);
     const C2<R> sv = c2<R>(rv.x - (ar * vv.x - ai * vv.y), rv.y - (ar * vv.y + ai * vv.x));
     xv.x += (ar * pv.x - ai * pv.y) + (wr * sv.x - wi * sv.y);
     xv.y += (ar * pv.y + ai * pv.x) + (wr * sv.y + wi * sv.x);
-    x[j] = xv;
+    stnt<R>(xv, x + j);
     const C2<R> rn = c2<R>(sv.x - (wr * tv.x - wi * tv.y), sv.y - (wr * tv.y + wi * tv.x));
     r[j] = rn;
     const R dx = pv.x - (wr * vv.x - wi * vv.y);
@@ -288,13 +307,14 @@ __global__ void __launch_bounds__(256) cg_xr_kernel(C2<R>* x, const C2<R>* p, C2
   double d2 = 0;
   KR_LOOP(n) {
     const long long j = off + i;
-    const C2<R> pv = p[j], wv = w[j];
-    C2<R> xv = x[j], rv = r[j];
+    // w is used for the last time, x only here
+    const C2<R> pv = p[j], wv = ldnt<R>(w + j);
+    C2<R> xv = ldnt<R>(x + j), rv = r[j];
     xv.x += ar * pv.x - ai * pv.y;
     xv.y += ar * pv.y + ai * pv.x;
     rv.x -= ar * wv.x - ai * wv.y;
     rv.y -= ar * wv.y + ai * wv.x;
-    x[j] = xv;
+    stnt<R>(xv, x + j);
     r[j] = rv;
     d2 += double(rv.x) * rv.x + double(rv.y) * rv.y;
   }
