@@ -440,13 +440,16 @@ __global__ void __launch_bounds__(256)
     if (op == 9) {  // x += alpha p + omega s, r = s - omega t, s = r - alpha v
       const R ar = R(q.alpha.x), ai = R(q.alpha.y), wr = R(q.omega.x), wi = R(q.omega.y);
       BV_LOOP(item) {
-        const C2<R> pv = Pp[o + i], rv = Rr[o + i], vv = Vv[o + i], tv = Tt[o + i],
+        // t is used for the last time and x only here: non-temporal (p and v
+        // are read again by the p update after the check point)
+        const C2<R> pv = Pp[o + i], rv = Rr[o + i], vv = Vv[o + i], tv = ldnt<R>(Tt + o + i),
                     h = Rh[o + i];
         const C2<R> sv = mk<R>(rv.x - (ar * vv.x - ai * vv.y), rv.y - (ar * vv.y + ai * vv.x));
-        C2<R> xv = X[o + i];
+        C2<R> xv = ldnt<R>(X + o + i);
         xv.x += (ar * pv.x - ai * pv.y) + (wr * sv.x - wi * sv.y);
         xv.y += (ar * pv.y + ai * pv.x) + (wr * sv.y + wi * sv.x);
-        X[o + i] = xv;
+        __builtin_nontemporal_store(xv.x, &X[o + i].x);
+        __builtin_nontemporal_store(xv.y, &X[o + i].y);
         const C2<R> rn = mk<R>(sv.x - (wr * tv.x - wi * tv.y), sv.y - (wr * tv.y + wi * tv.x));
         Rr[o + i] = rn;
         a0 += double(h.x) * rn.x + double(h.y) * rn.y;
@@ -458,12 +461,16 @@ __global__ void __launch_bounds__(256)
       const R br = R(q.beta.x), bi = R(q.beta.y);
       C2<R>* Pn = reinterpret_cast<C2<R>*>(A.pn);
       BV_LOOP(item) {
-        const C2<R> pv = Pp[o + i], rv = Rr[o + i], vv = Vv[o + i], tv = Tt[o + i];
+        // the old p, v and t are used for the last time and x only here:
+        // non-temporal, so that the cache keeps r and the new p
+        const C2<R> pv = ldnt<R>(Pp + o + i), rv = Rr[o + i], vv = ldnt<R>(Vv + o + i),
+                    tv = ldnt<R>(Tt + o + i);
         const C2<R> sv = mk<R>(rv.x - (ar * vv.x - ai * vv.y), rv.y - (ar * vv.y + ai * vv.x));
-        C2<R> xv = X[o + i];
+        C2<R> xv = ldnt<R>(X + o + i);
         xv.x += (ar * pv.x - ai * pv.y) + (wr * sv.x - wi * sv.y);
         xv.y += (ar * pv.y + ai * pv.x) + (wr * sv.y + wi * sv.x);
-        X[o + i] = xv;
+        __builtin_nontemporal_store(xv.x, &X[o + i].x);
+        __builtin_nontemporal_store(xv.y, &X[o + i].y);
         const C2<R> rn = mk<R>(sv.x - (wr * tv.x - wi * tv.y), sv.y - (wr * tv.y + wi * tv.x));
         Rr[o + i] = rn;
         const R dx = pv.x - (wr * vv.x - wi * vv.y);
