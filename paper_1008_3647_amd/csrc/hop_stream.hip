@@ -639,8 +639,7 @@ __global__ void __launch_bounds__(NX * NX)
           out.y += br * u.y + bi * u.x;
         }
       }
-      __builtin_nontemporal_store(out.x, &a.dst[o + z * P].x);
-      __builtin_nontemporal_store(out.y, &a.dst[o + z * P].y);
+      a.dst[o + z * P] = out;
     }
   }
 }
@@ -719,8 +718,7 @@ __global__ void __launch_bounds__(NX * NX)
     slice_T3<R, NX, 1>(cf, lds, l, X);  // U^3T
 #pragma unroll
     for (int z = 0; z < NX; ++z) {
-      __builtin_nontemporal_store(X[z].x, &a.dst[o + z * P].x);
-      __builtin_nontemporal_store(X[z].y, &a.dst[o + z * P].y);
+      a.dst[o + z * P] = X[z];
     }
   }
 }
