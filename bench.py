@@ -128,35 +128,100 @@ def measured_traffic():
     return d.get("bytes_per_launch")
 
 
-def oracle_residual(sigma, b, x0):
-    """||b_0 - M^T M x_0|| / ||b_0|| with the oracle's FP64 operators."""
+def oracle_residuals(sigma, b, x):
+    """||b_k - M^T M x_k|| / ||b_k|| for every right-hand side, with the
+    oracle's FP64 operators."""
     import oracle
-    mx = oracle.apply_M(x0, sigma, 0.05, 5.0)
-    qx = oracle.apply_Mdag(mx, sigma, 0.05, 5.0)
-    return float(np.linalg.norm(b[0] - qx) / np.linalg.norm(b[0]))
+    out = []
+    for bk, xk in zip(b, x):
+        mx = oracle.apply_M(xk, sigma, 0.05, 5.0)
+        qx = oracle.apply_Mdag(mx, sigma, 0.05, 5.0)
+        out.append(float(np.linalg.norm(bk - qx) / np.linalg.norm(bk)))
+    return out
 
 
-def cpu_baseline(sigma, b, iters_gpu, budget_s):
-    """The oracle's FP64 two-step BiCGStab on right-hand side 0, run for a
-    bounded number of iterations; seconds per iteration scaled to the GPU
-    solve's iteration count and to all right-hand sides."""
+def oracle_errors(x):
+    """max |x_k - x_oracle,k| / max |x_oracle,k| on the stored oracle samples
+    of every right-hand side (tests/golden/lattice_16x400_reference.npz, written
+    by tests/golden/make_reference_solutions.py from oracle/ only); None where
+    the file holds no sample for a right-hand side."""
+    ref = np.load(os.path.join(ROOT, "tests", "golden", "lattice_16x400_reference.npz"))
+    idx = ref["sample_index"]
+    out = []
+    for k in range(x.shape[0]):
+        key = f"x{k}_sample"
+        if key not in ref.files:
+            out.append(None)
+            continue
+        xs = x[k].reshape(-1)[idx]
+        rs = ref[key]
+        out.append(float(np.max(np.abs(xs - rs)) / np.max(np.abs(rs))))
+    return out
+
+
+def _cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    import platform
+    return platform.processor() or "unknown CPU"
+
+
+def _oracle_iterations(args):
+    """Worker process: one continuous run of the oracle's FP64 BiCGStab for
+    M^T y = b_k, `n` iterations (tolerance unreachable); returns seconds per
+    iteration with the run's initial and final residual applications taken out."""
+    k, n = args
     import oracle
     from oracle import solvers as osol
-    tau, g = 0.05, 5.0
-    M = lambda v: oracle.apply_M(v, sigma, tau, g)  # noqa: E731
-    Mt = lambda v: oracle.apply_Mdag(v, sigma, tau, g)  # noqa: E731
-    t0 = time.time()
-    n = 0
-    chunk = 5
-    while time.time() - t0 < budget_s:
-        osol.bicgstab(Mt, b[0], tol=1e-30, maxit=chunk)
-        n += chunk
-    dt = (time.time() - t0) / n
-    total_iters = sum(iters_gpu)
-    return dict(value=dt * total_iters * b.shape[0], unit="s", cores=1, kind="oracle",
-                sample=f"{n} BiCGStab iterations of the numpy FP64 oracle on 1 of {b.shape[0]} "
-                       f"right-hand sides ({dt:.3f} s/iteration), scaled to the GPU solve's "
-                       f"{total_iters} iterations x {b.shape[0]} right-hand sides")
+    from synthetic import sigma_field, gaussian_rhs, WORKLOADS
+    w = WORKLOADS["lattice_16x400"]
+    sigma = sigma_field(w["nx"], w["ntau"], w["sigma_seed"])
+    b = gaussian_rhs(w["nx"], w["ntau"], [w["rhs_seeds"][k]])[0]
+    Mt = lambda v: oracle.apply_Mdag(v, sigma, 0.05, 5.0)  # noqa: E731
+    t0 = time.perf_counter()
+    Mt(b)
+    t_mv = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    osol.bicgstab(Mt, b, tol=1e-30, maxit=n)
+    total = time.perf_counter() - t0
+    return (total - 2 * t_mv) / n, t_mv
+
+
+def cpu_oracle_rate(nrhs, budget_s):
+    """Seconds per BiCGStab iteration of the numpy FP64 oracle on this host,
+    one right-hand side per worker process, all right-hand sides at once (as
+    many processes as right-hand sides, up to the CPUs this process may use).
+    Runs before the GPU is touched (the workers are forked)."""
+    import multiprocessing as mp
+    ncpu = len(os.sched_getaffinity(0))
+    procs = max(1, min(nrhs, ncpu))
+    # calibrate the iteration count on one short run
+    rate1, _ = _oracle_iterations((0, 3))
+    n = max(5, int(budget_s / max(rate1, 1e-3)))
+    ctx = mp.get_context("fork")
+    with ctx.Pool(procs) as pool:
+        res = pool.map(_oracle_iterations, [(k, n) for k in range(procs)])
+    rate = max(r for r, _ in res)
+    return dict(rate=rate, procs=procs, iters=n, ncpu=ncpu, model=_cpu_model())
+
+
+def cpu_baseline(oracle_rate, iters_gpu, nrhs):
+    total = sum(iters_gpu)
+    waves = -(-nrhs // oracle_rate["procs"])
+    return dict(value=oracle_rate["rate"] * total * waves, unit="s", cores=oracle_rate["procs"],
+                kind="oracle",
+                sample=f"{oracle_rate['iters']} iterations of one continuous numpy FP64 oracle "
+                       f"BiCGStab run per right-hand side, {oracle_rate['procs']} right-hand sides "
+                       f"at once in {oracle_rate['procs']} single-threaded processes on "
+                       f"{oracle_rate['model']} ({oracle_rate['ncpu']} CPUs available): "
+                       f"{oracle_rate['rate']:.3f} s per iteration (slowest process), "
+                       f"extrapolated to the GPU solve's {total} iterations x {nrhs} "
+                       f"right-hand sides")
 
 
 # ---------------------------------------------------------------------------
@@ -423,6 +488,9 @@ def main():
         print(f"bench.py runs on one GPU only (asked for --gpus {a.gpus}); the multi-GPU "
               "time-slab sharding of this solver is a design note, not built.", file=sys.stderr)
         return 2
+    # the oracle leg's timing runs first, in forked worker processes, before
+    # anything touches the GPU
+    orate = None if a.no_cpu_baseline else cpu_oracle_rate(8, a.cpu_seconds)
     import torch
     from synthetic import sigma_field, gaussian_rhs, WORKLOADS
     from paper_1008_3647_amd import Lattice, Precond
@@ -440,11 +508,20 @@ def main():
 
     L = Lattice(nx, ntau, 0.05, 5.0, torch.complex128)
     L.set_aux_field(sigma)
-    tuned = None
+    tuned = tuned64 = None
+    SHAPE = ("slab", "vec_blocks", "xcd_group", "rhs_inner")
     if not a.no_tune:
         from paper_1008_3647_amd.autotune import tune
+        # each precision gets the launch shape tuned for itself
+        t = tune(L, b, mixed=False, op="M", cache=None, precond=pc)
+        tuned64 = {k: t[k] for k in SHAPE}
         t = tune(L, b, mixed=True, op="M", cache=None, precond=pc)
-        tuned = dict(slab=t["slab"], vec_blocks=t["vec_blocks"])
+        tuned = {k: t[k] for k in SHAPE}
+
+    def shape(tn):
+        if tn is not None:
+            L.tune(tn["slab"], tn["vec_blocks"], xcd_group=tn["xcd_group"],
+                   rhs_inner=tn["rhs_inner"])
 
     # Check interval of the unpreconditioned solve: a check point costs an
     # iteration in the unmerged form plus the gated reliable-update launches
@@ -457,6 +534,7 @@ def main():
         return L.solve_bicgstab(b, "two_step", precond=pc, tol=tol, mixed=mixed, maxit=20000,
                                 check_every=check_every)
 
+    shape(tuned)
     for _ in range(a.warmup):
         solve(True)
     torch.cuda.synchronize()
@@ -467,7 +545,8 @@ def main():
     t_mixed = (time.perf_counter() - t0) / a.steps
     ok = st["status"] == 0 and max(st["relres"]) <= tol
 
-    # all-FP64 comparison on the same GPU
+    # all-FP64 comparison on the same GPU, in its own tuned launch shape
+    shape(tuned64)
     solve(False)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -484,25 +563,30 @@ def main():
     if a.precond == "none" and not a.no_secondary:
         pcw = Precond("wce", wce_order=2)
 
-        tuned_w = None
+        tuned_w = tuned_w64 = None
         if not a.no_tune:
             # the preconditioned solve has its own launch-shape optimum (the
-            # basis-change launches follow the slab choice too)
+            # basis-change launches follow the slab choice too), per precision
             from paper_1008_3647_amd.autotune import tune
+            t = tune(L, b, mixed=False, op="M", cache=None, precond=pcw)
+            tuned_w64 = {k: t[k] for k in SHAPE}
             t = tune(L, b, mixed=True, op="M", cache=None, precond=pcw)
-            tuned_w = dict(slab=t["slab"], vec_blocks=t["vec_blocks"])
+            tuned_w = {k: t[k] for k in SHAPE}
 
         def solve_w(mixed):
             return L.solve_bicgstab(b, "two_step", precond=pcw, tol=tol, mixed=mixed, maxit=20000)
 
+        shape(tuned_w)
         solve_w(True)
-        solve_w(False)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         for _ in range(a.steps):
             xw, stw = solve_w(True)
         torch.cuda.synchronize()
         tw = (time.perf_counter() - t0) / a.steps
+        shape(tuned_w64)
+        solve_w(False)
+        torch.cuda.synchronize()
         t0 = time.perf_counter()
         xw64, stw64 = solve_w(False)
         torch.cuda.synchronize()
@@ -512,7 +596,7 @@ def main():
                          fp64_iters=list(stw64["iters"]),
                          fp64_relres_steps=list(stw64["relres"]),
                          converged=bool(stw["status"] == 0 and max(stw["relres"]) <= tol),
-                         tuning=tuned_w,
+                         tuning=tuned_w, tuning_fp64=tuned_w64,
                          max_rel_diff_vs_unpreconditioned=float(
                              (xw - x64).abs().max().item() / x64.abs().max().item()))
 
@@ -574,7 +658,7 @@ def main():
             roofline = dict(bound="hbm", achieved=r["GBs"], peak=HBM_PEAK_GBS,
                             unit="GB/s", frac=round(r["GBs"] / HBM_PEAK_GBS, 4),
                             traffic=measured_traffic(),
-                            kernel="hop_stream_kernel<float,16,-1,false,0,0> (apply_M, complex64, 8 rhs)",
+                            kernel="hop_stream_kernel<float,16,-1,false,0,0> (apply_M, complex64, 8 rhs, library-default launch shape: one slice per workgroup, XCD slab groups of 10)",
                             alg_bytes_per_launch=alg, launch_us=r["us"],
                             working_set="6 rotating (x, y) pairs, 1.3 GB > 256 MB Infinity Cache",
                             copy_GBs=copy_gbs, frac_of_copy=round(r["GBs"] / copy_gbs, 4),
@@ -600,6 +684,10 @@ def main():
                    "precond": a.precond, "precision": "fp32-refined",
                    "check_every": check_every},
         "converged": bool(ok),
+        "residual_reading": "tol 1e-10 holds per step (||b - M^T y||/||b|| and "
+                            "||y - M x||/||y||, worst rhs, in relres_steps); the residual of "
+                            "M^T M x = b (relres_normal, and relres_normal_oracle per rhs "
+                            "recomputed by the oracle) is bounded by tol (1 + ||M^T||)",
         "iters": list(st["iters"]),
         "relres_steps": list(st["relres"]),
         "relres_normal": st["relres_normal"],
@@ -612,13 +700,17 @@ def main():
         "secondary": secondary,
         "mv": mv,
         "tuning": tuned,
+        "tuning_fp64": tuned64,
         "roofline": roofline,
     }
+    # accuracy against the FP64 oracle, every right-hand side: forward error on
+    # the stored oracle samples and the two-step residual with the oracle's M
+    xh = x.cpu().numpy()
+    out["max_rel_err_vs_oracle"] = oracle_errors(xh)
+    out["max_rel_err_vs_oracle_fp64_solve"] = oracle_errors(x64.cpu().numpy())
     if not a.no_cpu_baseline:
-        # the oracle leg: its timing (cpu_baseline) and its check of the GPU
-        # solution (the oracle's M recomputes the two-step residual of rhs 0)
-        out["cpu_baseline"] = cpu_baseline(sigma_h, b_h, st["iters"], a.cpu_seconds)
-        out["relres_normal_oracle_rhs0"] = oracle_residual(sigma_h, b_h, x[0].cpu().numpy())
+        out["relres_normal_oracle"] = oracle_residuals(sigma_h, b_h, xh)
+        out["cpu_baseline"] = cpu_baseline(orate, st["iters"], nrhs)
     else:
         out["cpu_baseline"] = None
     print(json.dumps(out), flush=True)

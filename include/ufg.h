@@ -260,6 +260,20 @@ int lattice_tune(ufg_lattice L, int slab, int vec_blocks);
  */
 int lattice_tune_slabs(ufg_lattice L, int nslab);
 
+/*
+ * lattice_tune_order -- workgroup numbering of the streaming M / M^T and
+ *   basis-change kernels. group >= 1: groups of `group` consecutive slabs go
+ *   round-robin to the eight XCDs, so a slab's halo slice and its field slab
+ *   are read through one XCD's L2; each XCD takes its groups right-hand side
+ *   by right-hand side (rhs_inner = 0) or, group by group, every right-hand
+ *   side of a group in turn (rhs_inner = 1). group = 0: contiguous runs of
+ *   (slab, rhs) pairs per XCD, rhs fastest (rhs_inner ignored); group = -1:
+ *   the library default (complex64 lattices: groups of 10, rhs_inner 0;
+ *   complex128 lattices: 0). group: -1..Ntau. Same result guarantee as
+ *   lattice_tune (the numbering changes no arithmetic).
+ */
+int lattice_tune_order(ufg_lattice L, int group, int rhs_inner);
+
 /* lattice_info -- nx, ntau, dtype, A of a handle (host pointers, any may be NULL). */
 int lattice_info(ufg_lattice L, int* nx, int* ntau, int* dtype, double* A);
 

@@ -1,7 +1,8 @@
 """Autotuners for launch shapes.
 
-tune(): per lattice, the slab size of the streaming M / M^T kernel and the
-workgroups per right-hand side of the Krylov vector kernels. tune_batched():
+tune(): per lattice, the slab size and workgroup numbering of the streaming
+M / M^T kernels and the workgroups per right-hand side of the Krylov vector
+kernels. tune_batched():
 the persistent launch shape of solve_batched for a set of problems.
 
 Each candidate is timed on the real workload: a BiCGStab run of a fixed number
@@ -57,39 +58,64 @@ def candidate_slabs(L: Lattice):
     return [s for s in (1, 2, 3, 4, 6, 8) if s <= L.ntau]
 
 
+# workgroup numberings of the streaming kernels: (xcd_group, rhs_inner);
+# (0, False) is the contiguous per-XCD numbering (see lattice_tune_order)
+ORDERS = ((0, False), (5, False), (10, False), (5, True), (10, True))
+
+
+def _time_solve(L, b, op, precond, mixed, iters, reps):
+    L.solve_bicgstab(b, op, precond=precond, tol=1e-30, maxit=2, mixed=mixed)  # warm-up
+    best_t = float("inf")
+    for _ in range(reps):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        L.solve_bicgstab(b, op, precond=precond, tol=1e-30, maxit=iters, mixed=mixed,
+                         check_every=iters)
+        torch.cuda.synchronize()
+        best_t = min(best_t, time.perf_counter() - t0)
+    return best_t
+
+
 def tune(L: Lattice, b: torch.Tensor, mixed=False, op="M", iters=16, reps=2,
-         vec_blocks=(0, 32, 64, 128, 256, 512), cache: str | None = DEFAULT_CACHE,
-         force=False, verbose=False, precond=None):
-    """Pick (slab, vec_blocks) for solves of `b` on `L` (with `precond`, whose
-    basis-change launches follow the same slab choice); returns a dict with the
-    choice and the timings of every candidate."""
+         vec_blocks=(0, 32, 64, 128, 256, 512), orders=ORDERS,
+         cache: str | None = DEFAULT_CACHE, force=False, verbose=False, precond=None):
+    """Pick the launch shape for solves of `b` on `L` (with `precond`, whose
+    basis-change launches follow the same slab choice): slices per slab and
+    workgroup numbering of the streaming kernels first (vector kernels at their
+    default), then the workgroups per rhs of the vector kernels for that
+    choice. Returns a dict with the choice and the timings of every candidate."""
     nrhs = b.shape[0]
-    key = _key(L, nrhs, mixed, precond)
+    key = "v2|" + _key(L, nrhs, mixed, precond)
     data = _load(cache) if cache else {}
     if not force and key in data:
         best = data[key]
-        L.tune(best["slab"], best["vec_blocks"])
+        L.tune(best["slab"], best["vec_blocks"], xcd_group=best["xcd_group"],
+               rhs_inner=best["rhs_inner"])
         return dict(best, cached=True)
     results = []
+
+    def run(slab, vb, grp, ri):
+        L.tune(slab, vb, xcd_group=grp, rhs_inner=ri)
+        t = _time_solve(L, b, op, precond, mixed, iters, reps)
+        results.append(dict(slab=slab, vec_blocks=vb, xcd_group=grp, rhs_inner=ri, seconds=t))
+        if verbose:
+            print(f"tune slab={slab} vec_blocks={vb} group={grp} rhs_inner={ri}: "
+                  f"{t * 1e3:.2f} ms", flush=True)
+        return results[-1]
+
+    streaming = L.nx in (8, 12, 16)
     for slab in candidate_slabs(L):
-        for vb in vec_blocks:
-            L.tune(slab, vb)
-            L.solve_bicgstab(b, op, precond=precond, tol=1e-30, maxit=2, mixed=mixed)  # warm-up
-            best_t = float("inf")
-            for _ in range(reps):
-                torch.cuda.synchronize()
-                t0 = time.perf_counter()
-                L.solve_bicgstab(b, op, precond=precond, tol=1e-30, maxit=iters, mixed=mixed,
-                                 check_every=iters)
-                torch.cuda.synchronize()
-                best_t = min(best_t, time.perf_counter() - t0)
-            results.append(dict(slab=slab, vec_blocks=vb, seconds=best_t))
-            if verbose:
-                print(f"tune slab={slab} vec_blocks={vb}: {best_t * 1e3:.2f} ms", flush=True)
+        for grp, ri in (orders if streaming else ((0, False),)):
+            run(slab, 0, grp, ri)
+    first = min(results, key=lambda d: d["seconds"])
+    for vb in vec_blocks:
+        if vb != 0:
+            run(first["slab"], vb, first["xcd_group"], first["rhs_inner"])
     best = min(results, key=lambda d: d["seconds"])
-    L.tune(best["slab"], best["vec_blocks"])
-    choice = dict(slab=best["slab"], vec_blocks=best["vec_blocks"], seconds=best["seconds"],
-                  iters=iters)
+    L.tune(best["slab"], best["vec_blocks"], xcd_group=best["xcd_group"],
+           rhs_inner=best["rhs_inner"])
+    choice = {k: best[k] for k in ("slab", "vec_blocks", "xcd_group", "rhs_inner", "seconds")}
+    choice["iters"] = iters
     if cache:
         data[key] = choice
         _store(cache, data)

@@ -392,6 +392,17 @@ int lattice_tune_slabs(ufg_lattice h, int nslab) {
   return UFG_OK;
 }
 
+int lattice_tune_order(ufg_lattice h, int group, int rhs_inner) {
+  Lattice* L = check_handle(h);
+  UFG_CHECK(L != nullptr, "lattice_tune_order: NULL handle");
+  UFG_CHECK(group >= -1 && group <= L->ntau, "lattice_tune_order: group must be -1..ntau");
+  UFG_CHECK(rhs_inner == 0 || rhs_inner == 1, "lattice_tune_order: rhs_inner must be 0 or 1");
+  UFG_HIP(hipStreamSynchronize(L->stream));
+  L->xcd_group = group;
+  L->xcd_rhs_inner = rhs_inner;
+  return UFG_OK;
+}
+
 int lattice_info(ufg_lattice h, int* nx, int* ntau, int* dtype, double* A) {
   Lattice* L = check_handle(h);
   UFG_CHECK(L != nullptr, "lattice_info: NULL handle");

@@ -43,6 +43,10 @@ int stream_slab(const Lattice& L);
 // Slabs per right-hand side: slab s of nslab covers slices [s ntau / nslab,
 // (s + 1) ntau / nslab), so every slab holds floor or ceil of ntau / nslab.
 int stream_nslab(const Lattice& L);
+// Slab groups per XCD of the workgroup numbering (0: contiguous (slab, rhs)
+// runs per XCD with the rhs fastest), and the grid of a launch over nrhs.
+int stream_group(const Lattice& L);
+int stream_grid(const Lattice& L, int nrhs);
 bool stream_supported(const Lattice& L);
 template <typename R>
 int launch_hop_stream(const Lattice& L, const HopArgs<R>& a);

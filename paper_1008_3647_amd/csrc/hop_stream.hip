@@ -8,10 +8,15 @@
 // slice per slab is loaded twice (at two slices per slab the L2 misses come to
 // about 1.2 times the algorithmic bytes).
 //
-// Workgroups are numbered so that each XCD receives a contiguous run of
-// (slab, rhs) pairs with the rhs index fastest: the eight right-hand sides of
-// a slab run together on one XCD and share the field slab and the halo slices
-// through that XCD's L2.
+// Workgroup numbering (see stream_item): by default consecutive slabs are
+// gathered into groups of G that go round-robin to the eight XCDs, and each
+// XCD walks its groups right-hand side by right-hand side. Every rhs of a slab
+// then runs on the same XCD (the field slab is read from HBM once), the halo
+// slice of a slab is the last slice of the previous slab on the same XCD
+// (except at group edges), and the workgroups resident at any moment cover one
+// contiguous address window of each vector. The earlier numbering, contiguous
+// runs of (slab, rhs) pairs per XCD with the rhs fastest (G = 0), spreads the
+// resident workgroups over the eight rhs blocks of every vector.
 //
 // exp(-tau K) along one axis is the symmetric circulant T. T commutes with the
 // reflections i -> -i and i -> Nx/2 - i (mod Nx), so in the basis of their
@@ -234,6 +239,41 @@ __device__ __forceinline__ void scale_field(__amdgpu_buffer_rsrc_t f, int so, in
   }
 }
 
+// Block -> (rhs r, slab sb); false if the block has no item (it exits).
+// xg = 0: contiguous runs of (slab, rhs) per XCD, rhs fastest (grid nslab*nrhs).
+// xg > 0: slab groups of xg go round-robin to the XCDs (blocks are dispatched
+// to XCD blockIdx % 8); the q-th block of XCD j takes item q of the list
+// "for r: for the slabs of XCD j's groups" (ri = 0) or "for XCD j's groups:
+// for r: for the group's slabs" (ri = 1); grid stream_grid().
+__device__ __forceinline__ bool stream_item(int nslab, int nrhs, int xg, int ri, int& r,
+                                            int& sb) {
+  const int b = blockIdx.x;
+  if (xg <= 0) {
+    const int full = (int)gridDim.x & ~7;
+    int lid = b;
+    if (lid < full) lid = (lid & 7) * (full >> 3) + (lid >> 3);
+    r = lid % nrhs;
+    sb = lid / nrhs;
+    return true;
+  }
+  const int j = b & 7, q = b >> 3;
+  if (ri) {
+    const int per = nrhs * xg;  // blocks per group
+    const int m = q / per, k = q - m * per;
+    r = k / xg;
+    sb = (8 * m + j) * xg + (k - r * xg);
+    return sb < nslab;
+  }
+  const int F = nslab / xg, rem = nslab - F * xg;  // full groups, slabs of the partial one
+  int nj = xg * (F / 8 + ((j < (F & 7)) ? 1 : 0));
+  if (rem > 0 && (F & 7) == j) nj += rem;
+  if (q >= nrhs * nj) return false;
+  r = q / nj;
+  const int k = q - r * nj;
+  sb = (k / xg) * 8 * xg + j * xg + (k % xg);
+  return true;
+}
+
 __device__ __forceinline__ double wsum(double v) {
 #pragma unroll
   for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
@@ -248,23 +288,26 @@ __device__ __forceinline__ double wsum(double v) {
 // from which the output phase reads the thread's own z-line.
 template <typename R, int NX, int DIR, bool GENERAL, int SRC, int RED>
 __global__ void __launch_bounds__(NX * NX)
-    hop_stream_kernel(HopArgs<R> a, SplitCoef<R, NX> c, int ntau, int nslab) {
+    hop_stream_kernel(HopArgs<R> a, SplitCoef<R, NX> c, int ntau, int nslab, int xg, int ri) {
   constexpr int P = NX * NX, V = NX * NX * NX;
   constexpr int ES = sizeof(C2<R>), FS = sizeof(R);
   // Single-use operand slices are loaded non-temporal (measured: faster for
   // every complex64 variant and the fused complex128 ones, slower for the
   // plain complex128 operator, which keeps the default policy).
   constexpr int kNTA = (sizeof(R) == 4 || SRC != 0 || RED != 0) ? kAuxNT : 0;
+  // plain complex64 operator: the first output slice's source (and, for M^T,
+  // its field) is loaded together with the halo, before the halo's transform
+  // (one more z-line of registers; the fused variants would lose a wave per
+  // SIMD to it)
+  constexpr bool EARLY = sizeof(R) == 4 && SRC == 0 && RED == 0 && !GENERAL;
   extern __shared__ __align__(16) unsigned char smem_raw[];
   C2<R>* lds = reinterpret_cast<C2<R>*>(smem_raw);
 
-  // XCD-aware numbering: contiguous logical ids per XCD, rhs fastest
-  const int nb = gridDim.x;
-  const int full = nb & ~7;
-  int lid = blockIdx.x;
-  if (lid < full) lid = (lid & 7) * (full >> 3) + (lid >> 3);
-  const int r = lid % a.nrhs;
-  const int sb = lid / a.nrhs;
+  int r, sb;
+  if (!stream_item(nslab, a.nrhs, xg, ri, r, sb)) return;
+  // M^T walks time downwards: with slab groups the XCD takes its slabs in
+  // decreasing order, so a slab's halo (the next slab) was loaded first
+  if (DIR > 0 && xg > 0) sb = nslab - 1 - sb;
   if (a.gate && a.gate[r] == 0) return;
 
   const int l = threadIdx.x;
@@ -357,8 +400,21 @@ __global__ void __launch_bounds__(NX * NX)
   // stays in the LDS slice (each thread reads back only its own z-line, which
   // is also the first thing it writes in the next transform).
   C2<R> X[NX];
+  C2<R> Y[EARLY ? NX : 1];
   const int ly = l / NX, lx = l - (l / NX) * NX;
   load_source<R, NX, SRC, 0>(b, q, th * V * ES, vo, X);
+  R F0[EARLY && DIR > 0 ? NX : 1];
+  if constexpr (EARLY) {
+    if (count > 1)
+      load_source<R, NX, SRC, kNTA>(b, q, tfirst * V * ES, vo, Y);
+    else
+      load_source<R, NX, SRC, 0>(b, q, tfirst * V * ES, vo, Y);
+    if constexpr (DIR > 0) {  // and its output field
+#pragma unroll
+      for (int z = 0; z < NX; ++z)
+        F0[z] = bload_real<R>(b.post, fo, tfirst * V * FS + z * P * FS);
+    }
+  }
   if (DIR < 0) scale_field<R, NX>(b.pre, th * V * FS, fo, X);
   slice_T3<R, NX, 0, true>(c, lds, l, X);
   for (int k = 0; k < count; ++k) {
@@ -366,10 +422,20 @@ __global__ void __launch_bounds__(NX * NX)
     const int so = t * V * ES;  // slice byte offset (uniform)
     // the last slice of the slab is the halo of the neighbouring slab: it
     // stays cacheable, the others are streamed
-    if (k + 1 < count)
-      load_source<R, NX, SRC, kNTA>(b, q, so, vo, X);
-    else
-      load_source<R, NX, SRC, 0>(b, q, so, vo, X);
+    bool have = false;
+    if constexpr (EARLY) {
+      if (k == 0) {
+#pragma unroll
+        for (int z = 0; z < NX; ++z) X[z] = Y[z];
+        have = true;
+      }
+    }
+    if (!have) {
+      if (k + 1 < count)
+        load_source<R, NX, SRC, kNTA>(b, q, so, vo, X);
+      else
+        load_source<R, NX, SRC, 0>(b, q, so, vo, X);
+    }
     if (SRC == 1) {
 #pragma unroll
       for (int z = 0; z < NX; ++z) bstore<R, false>(X[z], a.fpnew + rbase, b.fpnew, vo, so + z * P * ES);
@@ -389,9 +455,14 @@ __global__ void __launch_bounds__(NX * NX)
     for (int z0 = 0; z0 < NX; z0 += ZC) {
       R F[DIR > 0 ? ZC : 1];
       if (DIR > 0) {  // M^T-type: the field multiplies the output slice
+        if (EARLY && k == 0) {
 #pragma unroll
-        for (int j = 0; j < ZC; ++j)
-          F[j] = sgn * bload_real<R>(b.post, fo, t * V * FS + (z0 + j) * P * FS);
+          for (int j = 0; j < ZC; ++j) F[j] = sgn * F0[EARLY && DIR > 0 ? z0 + j : 0];
+        } else {
+#pragma unroll
+          for (int j = 0; j < ZC; ++j)
+            F[j] = sgn * bload_real<R>(b.post, fo, t * V * FS + (z0 + j) * P * FS);
+        }
       }
       C2<R> U[GENERAL ? ZC : 1];
       if (GENERAL && a.aux) {
@@ -510,7 +581,7 @@ int launch_one(const Lattice& L, const HopArgs<R>& a, const SplitCoef<R, NX>& c,
     attr = true;
   }
   hipLaunchKernelGGL((hop_stream_kernel<R, NX, DIR, GENERAL, SRC, RED>), grid, dim3(NX * NX),
-                     lds, L.stream, a, c, L.ntau, nslab);
+                     lds, L.stream, a, c, L.ntau, nslab, stream_group(L), L.xcd_rhs_inner);
   UFG_HIP(hipGetLastError());
   return UFG_OK;
 }
@@ -520,7 +591,7 @@ int launch_dir(const Lattice& L, const HopArgs<R>& a, const SplitCoef<R, NX>& c)
   const int nslab = stream_nslab(L);
   const size_t lds = size_t(lds_slice_elems<NX>()) * sizeof(C2<R>);
   const bool general = (a.alpha.x != 1.0 || a.alpha.y != 0.0 || a.aux != nullptr);
-  const dim3 grid(nslab * a.nrhs);
+  const dim3 grid(stream_grid(L, a.nrhs));
   // instantiated combinations: plain apply (any reduction), the residual form
   // b - A x, and the two fused BiCGStab sources with their reductions
   if (a.src_mode == 1 && a.red_mode == 1 && !general)
@@ -566,16 +637,12 @@ int launch_nx(const Lattice& L, const HopArgs<R>& a) {
 // change of a weak-coupling application takes over the vector update).
 template <typename R, int NX, bool FWD, bool GENERAL, int SRC>
 __global__ void __launch_bounds__(NX * NX)
-    basis_kernel(HopArgs<R> a, SplitCoef<R, NX> c, int ntau, int nslab) {
+    basis_kernel(HopArgs<R> a, SplitCoef<R, NX> c, int ntau, int nslab, int xg, int ri) {
   constexpr int P = NX * NX, V = NX * NX * NX;
   extern __shared__ __align__(16) unsigned char smem_raw[];
   C2<R>* lds = reinterpret_cast<C2<R>*>(smem_raw);
-  const int nb = gridDim.x;
-  const int full = nb & ~7;
-  int lid = blockIdx.x;
-  if (lid < full) lid = (lid & 7) * (full >> 3) + (lid >> 3);
-  const int r = lid % a.nrhs;
-  const int sb = lid / a.nrhs;
+  int r, sb;
+  if (!stream_item(nslab, a.nrhs, xg, ri, r, sb)) return;
   if (a.gate && a.gate[r] == 0) return;
   const int l = threadIdx.x;
   const int t0 = (int)((long long)sb * ntau / nslab);
@@ -667,16 +734,12 @@ struct PairArgs {
 template <typename R, int NX>
 __global__ void __launch_bounds__(NX * NX)
     basis_pair_kernel(PairArgs<R> a, SplitCoef<R, NX> cb, SplitCoef<R, NX> cf, int ntau,
-                      int nslab) {
+                      int nslab, int xg, int ri) {
   constexpr int P = NX * NX, V = NX * NX * NX;
   extern __shared__ __align__(16) unsigned char smem_raw[];
   C2<R>* lds = reinterpret_cast<C2<R>*>(smem_raw);
-  const int nb = gridDim.x;
-  const int full = nb & ~7;
-  int lid = blockIdx.x;
-  if (lid < full) lid = (lid & 7) * (full >> 3) + (lid >> 3);
-  const int r = lid % a.nrhs;
-  const int sb = lid / a.nrhs;
+  int r, sb;
+  if (!stream_item(nslab, a.nrhs, xg, ri, r, sb)) return;
   if (a.gate && a.gate[r] == 0) return;
   const int l = threadIdx.x;
   const int t0 = (int)((long long)sb * ntau / nslab);
@@ -744,8 +807,9 @@ int launch_basis_pair_nx(const Lattice& L, const PairArgs<R>& a) {
                                 hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
     attr = true;
   }
-  hipLaunchKernelGGL((basis_pair_kernel<R, NX>), dim3(nslab * a.nrhs), dim3(NX * NX), lds,
-                     L.stream, a, cb, cf, L.ntau, nslab);
+  hipLaunchKernelGGL((basis_pair_kernel<R, NX>), dim3(stream_grid(L, a.nrhs)), dim3(NX * NX),
+                     lds, L.stream, a, cb, cf, L.ntau, nslab, stream_group(L),
+                     L.xcd_rhs_inner);
   UFG_HIP(hipGetLastError());
   return UFG_OK;
 }
@@ -760,7 +824,7 @@ int launch_basis_one(const Lattice& L, const HopArgs<R>& a, const SplitCoef<R, N
     attr = true;
   }
   hipLaunchKernelGGL((basis_kernel<R, NX, FWD, GENERAL, SRC>), grid, dim3(NX * NX), lds,
-                     L.stream, a, c, L.ntau, nslab);
+                     L.stream, a, c, L.ntau, nslab, stream_group(L), L.xcd_rhs_inner);
   UFG_HIP(hipGetLastError());
   return UFG_OK;
 }
@@ -776,7 +840,7 @@ int launch_basis_nx(const Lattice& L, const HopArgs<R>& a, bool forward) {
   for (auto& v : c.oa) v = R(h[k++]);
   const int nslab = stream_nslab(L);
   const size_t lds = size_t(lds_slice_elems<NX>()) * sizeof(C2<R>);
-  const dim3 grid(nslab * a.nrhs);
+  const dim3 grid(stream_grid(L, a.nrhs));
   const bool general = (a.alpha.x != 1.0 || a.alpha.y != 0.0 || a.aux != nullptr);
   if (forward && a.src_mode == 1 && !general)
     return launch_basis_one<R, NX, true, false, 1>(L, a, c, grid, lds, nslab);
@@ -797,9 +861,11 @@ int launch_basis_nx(const Lattice& L, const HopArgs<R>& a, bool forward) {
 
 int stream_slab(const Lattice& L) {
   if (L.slab > 0) return std::min(L.slab, L.ntau);
-  // two slices per workgroup measured best at 16^3 x 400; lattices below 2^20
-  // sites take one, which doubles the workgroups of their short launches
-  if ((long long)L.V * L.ntau < (1ll << 20)) return 1;
+  // complex128 lattices: two slices per workgroup measured best at
+  // 16^3 x 400 (the FP64 solve); lattices below 2^20 sites take one, which
+  // doubles the workgroups of their short launches. complex64 lattices: one,
+  // with slab groups (stream_group), measured best for apply_M.
+  if (L.dtype == UFG_C64 || (long long)L.V * L.ntau < (1ll << 20)) return 1;
   return std::min(2, L.ntau);
 }
 
@@ -807,6 +873,34 @@ int stream_nslab(const Lattice& L) {
   if (L.nslab > 0) return std::min(L.nslab, L.ntau);
   const int slab = stream_slab(L);
   return (L.ntau + slab - 1) / slab;
+}
+
+int stream_group(const Lattice& L) {
+  if (L.xcd_group >= 0) return std::min(L.xcd_group, stream_nslab(L));
+  // complex64 lattices: groups of ten slabs (apply_M at 16^3 x 400, 8 rhs:
+  // 48.8 us at two slices per workgroup in the contiguous numbering, 43.1 us
+  // at one slice per workgroup in groups of 5 or 10). complex128 lattices keep
+  // the contiguous numbering (their field slab, 32 KB, is then shared by the
+  // eight right-hand sides at once; in groups it was re-read per rhs).
+  if (L.dtype == UFG_C64) return std::min(10, stream_nslab(L));
+  return 0;
+}
+
+int stream_grid(const Lattice& L, int nrhs) {
+  const int nslab = stream_nslab(L), xg = stream_group(L);
+  if (xg <= 0) return nslab * nrhs;
+  if (L.xcd_rhs_inner) {
+    const int groups = (nslab + xg - 1) / xg;
+    return 8 * ((groups + 7) / 8) * nrhs * xg;
+  }
+  const int F = nslab / xg, rem = nslab - F * xg;
+  int most = 0;
+  for (int j = 0; j < 8; ++j) {
+    int nj = xg * (F / 8 + ((j < (F & 7)) ? 1 : 0));
+    if (rem > 0 && (F & 7) == j) nj += rem;
+    most = std::max(most, nj);
+  }
+  return 8 * nrhs * most;
 }
 
 bool stream_supported(const Lattice& L) {

@@ -101,6 +101,8 @@ struct Lattice {
   int slab = 0;                    // time slices per workgroup of the streaming kernel (0: default)
   int nslab = 0;                   // slabs per rhs of the streaming kernel (0: from slab)
   int vec_blocks = 0;              // workgroups per rhs of the vector kernels (0: default)
+  int xcd_group = -1;              // slab groups per XCD of the streaming kernels (-1: default)
+  int xcd_rhs_inner = 0;           // 1: an XCD takes every rhs of a slab group in turn
   DevBuf work[24];          // vector workspaces (solver / preconditioner)
   DevBuf red;               // reduction partials
   DevBuf state;             // solver state

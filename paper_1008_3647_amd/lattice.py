@@ -2,8 +2,9 @@
 
 Method names follow the C ABI (create_lattice / set_aux_field / apply_M /
 apply_Mdag / apply_precond / solve_cg_normal / solve_bicgstab /
-force_dS_dsigma); each one checks shapes, dtypes and devices and then makes
-exactly one library call.
+force_dS_dsigma); each one checks the dtype, shape, device and contiguity of
+every tensor it passes (inputs, out=, x0=) before it makes exactly one
+library call, since the C ABI receives bare pointers and cannot.
 """
 from __future__ import annotations
 
@@ -63,6 +64,27 @@ class Lattice:
             raise ValueError(f"{name} must end in shape {self.shape}, got {tuple(x.shape)}")
         return x.numel() // (self.ntau * self.nx ** 3)
 
+    def _like(self, t, ref, name):
+        """`t` must be a contiguous CUDA tensor of ref's dtype, shape and device
+        (the library writes through it as ref's layout)."""
+        if not isinstance(t, torch.Tensor) or t.device != ref.device:
+            raise TypeError(f"{name} must be a CUDA tensor on {ref.device}")
+        if t.dtype != ref.dtype:
+            raise TypeError(f"{name} must have dtype {ref.dtype}, got {t.dtype}")
+        if tuple(t.shape) != tuple(ref.shape):
+            raise ValueError(f"{name} must have shape {tuple(ref.shape)}, got {tuple(t.shape)}")
+        if not t.is_contiguous():
+            raise ValueError(f"{name} must be contiguous")
+        return t
+
+    def _out(self, out, x, name="out"):
+        if out is None:
+            return torch.empty_like(x, memory_format=torch.contiguous_format)
+        self._like(out, x, name)
+        if out.data_ptr() == x.data_ptr():
+            raise ValueError(f"{name} must not alias the input")
+        return out
+
     def new_vectors(self, nrhs, dtype=None):
         return torch.empty((nrhs,) + self.shape, dtype=dtype or self.dtype, device=self.device)
 
@@ -91,23 +113,23 @@ class Lattice:
 
     def apply_M(self, x, out=None):
         n = self._vec(x, "x")
-        y = torch.empty_like(x) if out is None else out
-        self._vec(y, "out")
+        y = self._out(out, x)
         L.check(self._lib.apply_M(self._h, C.c_void_p(x.data_ptr()), C.c_void_p(y.data_ptr()), n),
                 "apply_M")
         return y
 
     def apply_Mdag(self, x, out=None):
         n = self._vec(x, "x")
-        y = torch.empty_like(x) if out is None else out
-        self._vec(y, "out")
+        y = self._out(out, x)
         L.check(self._lib.apply_Mdag(self._h, C.c_void_p(x.data_ptr()), C.c_void_p(y.data_ptr()),
                                      n), "apply_Mdag")
         return y
 
     def apply_precond(self, x, precond: Precond, op="M", out=None):
         n = self._vec(x, "x")
-        y = torch.empty_like(x) if out is None else out
+        if op not in _OPS:
+            raise ValueError(f"op must be one of {sorted(_OPS)}")
+        y = self._out(out, x)
         p = precond.to_c()
         L.check(self._lib.apply_precond(self._h, C.byref(p), _OPS[op], C.c_void_p(x.data_ptr()),
                                         C.c_void_p(y.data_ptr()), n), "apply_precond")
@@ -120,7 +142,7 @@ class Lattice:
                         mixed=False, delta=0.1, check_every=10, x0=None, graph=True):
         dt = self._solve_dtype(mixed)
         n = self._vec(b, "b", dt)
-        x = torch.empty_like(b) if x0 is None else x0
+        x = self._out(x0, b, "x0") if x0 is not None else torch.empty_like(b)
         o = L.solve_opts(tol, maxit, mixed, delta, check_every, x0 is not None, not graph)
         st = L.ufg_solve_stats()
         p = precond.to_c() if precond else None
@@ -135,7 +157,9 @@ class Lattice:
                        graph=True):
         dt = self._solve_dtype(mixed)
         n = self._vec(b, "b", dt)
-        x = torch.empty_like(b) if x0 is None else x0
+        if op not in _OPS:
+            raise ValueError(f"op must be one of {sorted(_OPS)}")
+        x = self._out(x0, b, "x0") if x0 is not None else torch.empty_like(b)
         o = L.solve_opts(tol, maxit, mixed, delta, check_every, x0 is not None, not graph)
         st = L.ufg_solve_stats()
         p = precond.to_c() if precond else None
@@ -145,11 +169,14 @@ class Lattice:
         L.check(code, "solve_bicgstab")
         return x, st.as_dict()
 
-    def tune(self, slab=0, vec_blocks=0, nslab=0):
-        """Launch parameters (0 = library default); see lattice_tune and
-        lattice_tune_slabs in ufg.h (nslab, when given, overrides slab)."""
+    def tune(self, slab=0, vec_blocks=0, nslab=0, xcd_group=-1, rhs_inner=False):
+        """Launch parameters (0 = library default, xcd_group -1 = default); see
+        lattice_tune, lattice_tune_slabs and lattice_tune_order in ufg.h (nslab,
+        when given, overrides slab)."""
         L.check(self._lib.lattice_tune(self._h, int(slab), int(vec_blocks)), "lattice_tune")
         L.check(self._lib.lattice_tune_slabs(self._h, int(nslab)), "lattice_tune_slabs")
+        L.check(self._lib.lattice_tune_order(self._h, int(xcd_group), int(bool(rhs_inner))),
+                "lattice_tune_order")
 
     def norm2(self, x):
         """||x_r||^2 per right-hand side (host list), FP64 accumulation."""
@@ -161,8 +188,17 @@ class Lattice:
 
     def force_dS_dsigma(self, X, y, out=None):
         n = self._vec(X, "X")
-        self._vec(y, "y")
-        g = torch.empty(self.shape, dtype=torch.float64, device=self.device) if out is None else out
+        self._like(y, X, "y")
+        if out is None:
+            g = torch.empty(self.shape, dtype=torch.float64, device=X.device)
+        else:
+            g = out
+            if not isinstance(g, torch.Tensor) or g.device != X.device:
+                raise TypeError(f"out must be a CUDA tensor on {X.device}")
+            if g.dtype != torch.float64:
+                raise TypeError(f"out must have dtype torch.float64, got {g.dtype}")
+            if tuple(g.shape) != self.shape or not g.is_contiguous():
+                raise ValueError(f"out must be contiguous with shape {self.shape}")
         L.check(self._lib.force_dS_dsigma(self._h, C.c_void_p(X.data_ptr()),
                                           C.c_void_p(y.data_ptr()), n, C.c_void_p(g.data_ptr())),
                 "force_dS_dsigma")

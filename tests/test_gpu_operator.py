@@ -106,6 +106,8 @@ def test_invalid_arguments_are_rejected():
         L.tune(nslab=5)  # more slabs than Ntau
     with pytest.raises(UfgError):
         L.tune(vec_blocks=5000)
+    with pytest.raises(UfgError):
+        L.tune(xcd_group=-2)
 
 
 @pytest.mark.parametrize("dtype", [torch.complex128, torch.complex64])
@@ -138,6 +140,66 @@ def test_apply_every_slab_size(nx, dtype):
         L.tune(0, 0, nslab=nslab)
         assert rel_err(to_host(L.apply_M(xd)), ref) < TOL[dtype], nslab
         assert rel_err(to_host(L.apply_Mdag(xd)), refd) < TOL[dtype], nslab
+
+
+@pytest.mark.parametrize("dtype", [torch.complex128, torch.complex64])
+@pytest.mark.parametrize("nx", [8, 16])
+def test_apply_every_xcd_group(nx, dtype):
+    """The workgroup numbering (slab groups per XCD, lattice_tune_order) only
+    moves work between workgroups: every group size, with slab sizes that leave
+    a partial last group and XCDs without work, must give the oracle's operator
+    and bit-identical outputs for M, M^T and the basis changes of a WCE1
+    application."""
+    require_gpu()
+    from paper_1008_3647_amd import Lattice, Precond
+    ntau, nrhs = 23, 3
+    sigma = sigma_field(nx, ntau, 440 + nx)
+    x = gaussian_rhs(nx, ntau, range(450, 450 + nrhs))
+    xin = x.astype(np.complex64).astype(np.complex128) if dtype == torch.complex64 else x
+    ref = _oracle(oracle.apply_M, xin, sigma)
+    refd = _oracle(oracle.apply_Mdag, xin, sigma)
+    L = Lattice(nx, ntau, TAU, G, dtype)
+    L.set_aux_field(to_dev(sigma))
+    xd = to_dev(x, dtype)
+    pc = Precond("wce", wce_order=1)
+    first = None
+    orders = [(0, False)] + [(g, ri) for g in (1, 2, 3, 5, 7, 23) for ri in (False, True)]
+    for slab in (1, 2, 5):
+        for group, ri in orders:
+            say(f"xcd-group parity nx={nx} slab={slab} group={group} rhs_inner={ri} {dtype}")
+            L.tune(slab, 0, xcd_group=group, rhs_inner=ri)
+            y = to_host(L.apply_M(xd))
+            yd = to_host(L.apply_Mdag(xd))
+            w = to_host(L.apply_precond(xd, pc, "M"))
+            assert rel_err(y, ref) < TOL[dtype], (slab, group)
+            assert rel_err(yd, refd) < TOL[dtype], (slab, group)
+            if first is None or first[0] != slab:
+                first = (slab, y, yd, w)
+            else:
+                assert np.array_equal(y, first[1]) and np.array_equal(yd, first[2]), (slab, group)
+                assert np.array_equal(w, first[3]), (slab, group)
+
+
+@pytest.mark.parametrize("group,rhs_inner", [(0, False), (1, False), (4, False), (3, True)])
+def test_solve_with_xcd_group(group, rhs_inner):
+    """Fused reductions leave one partial per (rhs, slab) whatever workgroup
+    computes it: two-step solves under each numbering converge to the oracle's
+    residual bound."""
+    require_gpu()
+    from paper_1008_3647_amd import Lattice
+    nx, ntau, nrhs = 8, 23, 2
+    sigma = sigma_field(nx, ntau, 460)
+    b = gaussian_rhs(nx, ntau, range(461, 461 + nrhs))
+    L = Lattice(nx, ntau, TAU, G, torch.complex128)
+    L.set_aux_field(to_dev(sigma))
+    L.tune(1, 0, xcd_group=group, rhs_inner=rhs_inner)
+    for mixed in (False, True):
+        x, st = L.solve_bicgstab(to_dev(b), "two_step", tol=1e-10, mixed=mixed)
+        assert st["status"] == 0, (group, mixed)
+        xh = to_host(x)
+        for i in range(nrhs):
+            r = b[i] - oracle.apply_Q(xh[i], sigma, TAU, G)
+            assert np.linalg.norm(r) / np.linalg.norm(b[i]) < 1e-9, (group, mixed, i)
 
 
 @pytest.mark.parametrize("mixed", [False, True])

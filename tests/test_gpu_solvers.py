@@ -244,9 +244,14 @@ def test_autotune_with_preconditioner():
     bd = to_dev(b)
     t = tune(L, bd, mixed=True, op="M", iters=4, reps=1, vec_blocks=(0, 64), cache=None,
              precond=pc)
-    say({k: t[k] for k in ("slab", "vec_blocks")})
-    assert len(t["candidates"]) == 2 * len([s for s in (1, 2, 3, 4, 6, 8) if s <= ntau])
+    from paper_1008_3647_amd.autotune import ORDERS
+    say({k: t[k] for k in ("slab", "vec_blocks", "xcd_group", "rhs_inner")})
+    # every (slab, numbering) at the default vector shape, then the other
+    # vector shape for the best of them
+    nslabs = len([s for s in (1, 2, 3, 4, 6, 8) if s <= ntau])
+    assert len(t["candidates"]) == nslabs * len(ORDERS) + 1
     assert t["slab"] in (1, 2, 3, 4, 6, 8) and t["vec_blocks"] in (0, 64)
+    assert (t["xcd_group"], t["rhs_inner"]) in ORDERS
     x, st = L.solve_bicgstab(bd, "M", pc, tol=1e-10, mixed=True)
     assert st["status"] == 0
     assert _relres_oracle(to_host(x), b, sigma, "M") <= 1.2e-10
