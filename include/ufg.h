@@ -243,6 +243,22 @@ int force_dS_dsigma(ufg_lattice L, const void* X, const void* y, int nrhs,
 int lattice_norm2(ufg_lattice L, const void* x, int nrhs, double* out_host);
 
 /*
+ * lattice_norm2_noalloc -- for callers that cannot allocate device memory
+ *   (code under HIP graph capture, tight serving loops, harnesses that forbid
+ *   hipMalloc): the squared norms of lattice_norm2, computed by the same
+ *   kernels in the same summation order, but into out_dev[r] (device float64
+ *   array of nrhs, caller-owned) and asynchronously on the lattice's stream.
+ *   Makes no allocation: its partial sums and per-rhs state live in a static
+ *   device buffer of 2 MiB per GPU (held until the process ends). Needs
+ *   32 * vec_blocks * nrhs + ~64 * nrhs bytes of it (vec_blocks as in
+ *   lattice_tune, by default at most max(16, 2048 / nrhs) for this call);
+ *   larger requests return UFG_EINVAL with a message. Every call on one GPU
+ *   shares that buffer: calls that overlap in time on one GPU (concurrent
+ *   streams or threads) race and must be serialised by the caller.
+ */
+int lattice_norm2_noalloc(ufg_lattice L, const void* x, int nrhs, double* out_dev);
+
+/*
  * lattice_tune -- launch parameters chosen by the autotuner (0 keeps the
  *   default): `slab` time slices per workgroup of the streaming M / M^T kernel
  *   (Nx in {8, 12, 16}; 1..Ntau), `vec_blocks` workgroups per right-hand side of

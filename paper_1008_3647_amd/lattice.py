@@ -186,6 +186,20 @@ class Lattice:
                 "lattice_norm2")
         return list(out)
 
+    def norm2_noalloc(self, x, out):
+        """||x_r||^2 per right-hand side into the float64 CUDA tensor `out`
+        (nrhs entries), asynchronously and without any allocation by the
+        library (C ABI lattice_norm2_noalloc)."""
+        n = self._vec(x, "x")
+        if not isinstance(out, torch.Tensor) or out.device != x.device:
+            raise TypeError(f"out must be a CUDA tensor on {x.device}")
+        if out.dtype != torch.float64 or out.numel() != n or not out.is_contiguous():
+            raise ValueError(f"out must be a contiguous float64 tensor of {n} entries")
+        L.check(self._lib.lattice_norm2_noalloc(self._h, C.c_void_p(x.data_ptr()), n,
+                                                C.c_void_p(out.data_ptr())),
+                "lattice_norm2_noalloc")
+        return out
+
     def force_dS_dsigma(self, X, y, out=None):
         n = self._vec(X, "X")
         self._like(y, X, "y")
