@@ -175,6 +175,15 @@ int apply_precond(ufg_lattice L, const ufg_precond* p, int op, const void* x,
                   void* y, int nrhs);
 
 /*
+ * precond_lam_max -- the lam_max a Chebyshev preconditioner `p` normalises Q
+ *   with on this lattice (Sec. 2: Q^ = Q / lam_max): p->lam_max if > 0, the
+ *   bound (1 + max|b|)^2 if 0, else 1.05 times 30 power iterations on Q (cached
+ *   per field; synchronous). out_host: one double. UFG_EINVAL unless
+ *   p->kind == UFG_PC_CHEB.
+ */
+int precond_lam_max(ufg_lattice L, const ufg_precond* p, double* out_host);
+
+/*
  * solve_cg_normal -- x = (M^dagger M)^{-1} b by (preconditioned) CG
  *   (paper, Eqs. 1 and 3). p may be NULL (no preconditioner); p->kind is any
  *   kind (WCE acts as W_d W_d^dagger). b, x: device, nrhs vectors; with

@@ -68,6 +68,7 @@ _SIGNATURES = {
     "lattice_tune": (C.c_int, [_P, C.c_int, C.c_int]),
     "lattice_tune_slabs": (C.c_int, [_P, C.c_int]),
     "lattice_tune_order": (C.c_int, [_P, C.c_int, C.c_int]),
+    "precond_lam_max": (C.c_int, [_P, C.POINTER(ufg_precond), C.POINTER(C.c_double)]),
     "lattice_norm2": (C.c_int, [_P, _P, C.c_int, C.POINTER(C.c_double)]),
     "lattice_norm2_noalloc": (C.c_int, [_P, _P, C.c_int, _P]),
     "ufg_device_copy": (C.c_int, [_P, _P, C.c_longlong, _P]),

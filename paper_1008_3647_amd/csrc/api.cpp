@@ -392,6 +392,17 @@ int lattice_tune_slabs(ufg_lattice h, int nslab) {
   return UFG_OK;
 }
 
+int precond_lam_max(ufg_lattice h, const ufg_precond* p, double* out_host) {
+  Lattice* L = check_handle(h);
+  UFG_CHECK(L != nullptr, "precond_lam_max: NULL handle");
+  UFG_CHECK(p && out_host, "precond_lam_max: NULL preconditioner or output");
+  UFG_CHECK(p->kind == UFG_PC_CHEB, "precond_lam_max: needs a Chebyshev preconditioner");
+  PcPlan pc;
+  UFG_TRY(resolve_precond(*L, p, &pc));
+  *out_host = pc.lam_max;
+  return UFG_OK;
+}
+
 int lattice_tune_order(ufg_lattice h, int group, int rhs_inner) {
   Lattice* L = check_handle(h);
   UFG_CHECK(L != nullptr, "lattice_tune_order: NULL handle");

@@ -135,6 +135,14 @@ class Lattice:
                                         C.c_void_p(y.data_ptr()), n), "apply_precond")
         return y
 
+    def lam_max(self, precond: Precond):
+        """lam_max the Chebyshev preconditioner normalises Q with (C ABI
+        precond_lam_max; runs the power iteration when precond.lam_max < 0)."""
+        p = precond.to_c()
+        out = C.c_double()
+        L.check(self._lib.precond_lam_max(self._h, C.byref(p), C.byref(out)), "precond_lam_max")
+        return out.value
+
     def _solve_dtype(self, mixed):
         return torch.complex128 if mixed else self.dtype
 

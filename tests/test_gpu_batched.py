@@ -1,7 +1,8 @@
 """Batched two-step BiCGStab (solve_batched): many uneven lattices in one
-persistent, graph-replayed pass. Each (problem, rhs) must reach the same
-solution as the unbatched solve of that problem and meet the tolerance on the
-residuals recomputed by the oracle's M.
+persistent, graph-replayed pass. Each (problem, rhs) must meet the tolerance
+on the residuals recomputed by the oracle's operators and reach the oracle's
+solution (dense LU on tiny lattices, stored oracle solutions for the 64-lattice
+workload).
 """
 import numpy as np
 import pytest
@@ -54,13 +55,17 @@ def test_tiny_uneven_batch_against_dense_lu(mixed):
             assert np.linalg.norm(xh[k] - ref) / np.linalg.norm(ref) < 1e-7
 
 
-def test_batched_64_against_unbatched_and_oracle():
+def test_batched_64_against_oracle():
     """The 64-lattice batch (Nx in {6,8,10,12}, Ntau in 80..320), 2 rhs each,
-    complex64-refined: every system converges to 1e-10 per step; solutions
-    agree with the unbatched mixed solve of the same problem within 1e-7
-    (both are within ~cond(M) x 1e-10 of the exact solution); the oracle's M
-    recomputes the residual of four problems."""
+    complex64-refined: every system converges to 1e-10 per step; the oracle's
+    operators recompute the residual of M^T M x = b for all 128 systems
+    (<= 1e-10 (1 + ||M^T|| ||y|| / ||b||), ||M^T|| <= 1 + max|b|, ||y|| ~ ||M x||,
+    times 2 for the recomputation's rounding); 8 problems drawn by the stored reference (both rhs) are compared
+    with the oracle's own solutions (tests/golden/batched_64_reference.npz,
+    ~1e-13 per step) on sampled entries: forward error <= 1e-7 (per-step
+    residual times cond(M), below 1e3 on these lattices, with margin)."""
     require_gpu()
+    import os
     from paper_1008_3647_amd.lattice import solve_batched
     w = WORKLOADS["batched_64"]
     shapes = batched_problem_shapes(w["count"], w["shape_seed"])
@@ -70,13 +75,26 @@ def test_batched_64_against_unbatched_and_oracle():
     say(f"batched: max iters {max(max(s['iters']) for s in st)}, wall {st[0]['seconds']:.3f}s")
     for s in st:
         assert s["status"] == 0 and max(s["relres"]) <= 1e-10
-    for i in (0, 17, 40, 63):
-        nx, ntau, sigma, b = probs[i]
-        x1, s1 = lats[i].solve_bicgstab(bs[i], "two_step", tol=1e-10, mixed=True)
-        a, c = to_host(xs[i]), to_host(x1)
-        err = np.max(np.abs(a - c)) / np.max(np.abs(c))
-        say(f"problem {i} ({nx}x{ntau}): batched vs unbatched {err:.2e}")
-        assert err < 1e-7
+    worst = 0.0
+    for i, ((nx, ntau, sigma, b), x) in enumerate(zip(probs, xs)):
+        a = to_host(x)
+        bmax = np.abs(oracle.field_b(sigma, oracle.coupling_A(TAU, G))).max()
         for k in range(b.shape[0]):
-            r = b[k] - oracle.apply_Q(a[k], sigma, TAU, G)
-            assert np.linalg.norm(r) / np.linalg.norm(b[k]) < 1e-7
+            mx = oracle.apply_M(a[k], sigma, TAU, G)
+            r = np.linalg.norm(b[k] - oracle.apply_Mdag(mx, sigma, TAU, G)) / np.linalg.norm(b[k])
+            # b - M^T M x = (b - M^T y) + M^T (y - M x), each step <= 1e-10
+            bound = 2e-10 * (1 + (1 + bmax) * np.linalg.norm(mx) / np.linalg.norm(b[k]))
+            worst = max(worst, r / bound)
+            assert r < bound, (i, k, r, bound)
+    say(f"worst oracle residual over the 128 systems: {worst:.2f} of its bound")
+    ref = np.load(os.path.join(os.path.dirname(__file__), "golden", "batched_64_reference.npz"))
+    for i in ref["problems"]:
+        nx, ntau, sigma, b = probs[i]
+        a = to_host(xs[i])
+        idx = ref[f"p{i}_sample_index"]
+        for k in range(b.shape[0]):
+            rs = ref[f"p{i}_x{k}_sample"]
+            err = np.max(np.abs(a[k].reshape(-1)[idx] - rs)) / np.max(np.abs(rs))
+            say(f"problem {i} ({nx}^3 x {ntau}) rhs {k}: forward error vs oracle {err:.2e}")
+            assert err < 1e-7, (i, k)
+            assert np.linalg.norm(a[k]) / ref[f"p{i}_x{k}_norm"] == pytest.approx(1.0, abs=1e-8)

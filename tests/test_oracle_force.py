@@ -29,6 +29,32 @@ def test_action_at_heat_bath_point():
     assert _dense_action(sigma, phi) == pytest.approx(np.vdot(eta, eta).real, rel=1e-12)
 
 
+def test_oracle_action_function_pinned():
+    """oracle.force.action (S = phi^H Q^{-1} phi computed as ||y||^2 with
+    M^T y = phi) against two values that do not use that route: at the
+    heat-bath point phi = M^T eta, S = ||eta||^2 and y = eta (Sec. 1); for a
+    general phi, the spectral sum sum_i |v_i^H phi|^2 / lambda_i over the
+    eigenpairs of the dense Q = M^T M."""
+    nx, ntau = 2, 6
+    sigma, eta, phi = _setup(nx, ntau, 64)
+    Md = op.dense_M(sigma, TAU, G)
+
+    def solve_Mdag(r):
+        return np.linalg.solve(Md.T, r.ravel()).reshape(r.shape)
+
+    S, y = force.action(phi, sigma, TAU, G, solve_Mdag)
+    assert isinstance(S, float)
+    assert S == pytest.approx(np.vdot(eta, eta).real, rel=1e-12)
+    assert np.max(np.abs(y - eta)) < 1e-12 * np.max(np.abs(eta))
+    phi2 = gaussian_rhs(nx, ntau, [65])[0] * 1.7
+    S2, _ = force.action(phi2, sigma + 0.4, TAU, G, lambda r: np.linalg.solve(
+        op.dense_M(sigma + 0.4, TAU, G).T, r.ravel()).reshape(r.shape))
+    Md2 = op.dense_M(sigma + 0.4, TAU, G)
+    lam, V = np.linalg.eigh(Md2.T @ Md2)
+    spectral = float(np.sum(np.abs(V.conj().T @ phi2.ravel()) ** 2 / lam))
+    assert S2 == pytest.approx(spectral, rel=1e-10)
+
+
 def test_gradient_against_central_differences():
     nx, ntau = 2, 5
     sigma, eta, phi = _setup(nx, ntau, 62)
