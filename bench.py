@@ -346,6 +346,11 @@ def report_batched(a):
     print(f"| all systems converged | {all(s['status'] == 0 for s in st)} |")
     print(f"| iterations per system (both steps): min / median / max | "
           f"{min(iters)} / {int(np.median(iters))} / {max(iters)} |")
+    print(f"| host synchronisations per batched solve (both steps) | {st[0]['host_syncs']} |")
+    print(f"| host submissions per batched solve (graph launches, kernel launches, copies) | "
+          f"{st[0]['host_submits']} |")
+    print(f"| iterations per host synchronisation (longest system) | "
+          f"{max(iters) / st[0]['host_syncs']:.0f} |")
     print(f"| max relative difference, batched vs sequential solution | {max(diffs):.1e} |")
     return 0
 

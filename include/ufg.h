@@ -125,6 +125,9 @@ typedef struct {
   double seconds;            /* wall time of the call                         */
   double paper_mv;           /* MV count under the paper's cost model         */
   int status;
+  long long host_syncs;      /* solve_batched: host waits for the device      */
+  long long host_submits;    /* solve_batched: graph launches, kernel launches
+                                and copies the host issued (0 elsewhere)      */
 } ufg_solve_stats;
 
 /*
@@ -208,8 +211,10 @@ int solve_bicgstab(ufg_lattice L, const ufg_precond* p, int op, const void* b,
  *   then M x = y; paper, Eq. 2), one lattice each (lattices may differ in Nx
  *   and Ntau), nrhs[i] right-hand sides per problem. Every phase of an
  *   iteration is one persistent launch over a work table covering all
- *   problems, the iteration body is replayed from a captured HIP graph, and
- *   every (problem, rhs) keeps its own device state and stops on its own.
+ *   problems; whole check intervals, with their reliable updates and restarts
+ *   gated on device flags, are replayed from captured HIP graphs, the host
+ *   reading the flags once per ~100 iterations (solve_batched_tune); every
+ *   (problem, rhs) keeps its own device state and stops on its own.
  *   Ls[i]: complex128 lattices (fields installed). b[i], x[i]: device
  *   complex128 vectors [nrhs[i]][Ntau][Nx]^3 of lattice i. o->mixed: complex64
  *   inner iteration with FP64 reliable updates (else complex128 inner).
@@ -226,12 +231,15 @@ int solve_batched(const ufg_lattice* Ls, int nprob, const void* const* b,
  * solve_batched_tune -- launch shape of solve_batched chosen by the autotuner
  *   (0 keeps the default): workgroups per compute unit of the persistent
  *   operator and vector launches (1..64; defaults 4 and 8), elements per vector
- *   work item (256..4194304; default 4096) and time slices per slab of the
- *   batched streaming operator (1..64; default 2). Process-wide; not thread
- *   safe against concurrent solves. Results do not depend on them beyond
- *   floating-point summation order.
+ *   work item (256..4194304; default 4096), time slices per slab of the
+ *   batched streaming operator (1..64; default 2) and iterations between host
+ *   reads of the convergence flags (1..100000, rounded to whole check
+ *   intervals; default 100). Process-wide; not thread safe against concurrent
+ *   solves. Results do not depend on them beyond floating-point summation
+ *   order (and the last point at which an unconverged system may stop).
  */
-int solve_batched_tune(int hop_blocks_per_cu, int vec_blocks_per_cu, long long chunk, int slab);
+int solve_batched_tune(int hop_blocks_per_cu, int vec_blocks_per_cu, long long chunk, int slab,
+                       int sync_iters);
 
 /*
  * force_dS_dsigma -- gradient of S = sum_r phi_r^dagger (M^dagger M)^{-1} phi_r

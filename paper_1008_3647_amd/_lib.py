@@ -37,13 +37,15 @@ class ufg_solve_stats(C.Structure):
     _fields_ = [("iters", C.c_int * 2), ("mv", C.c_longlong), ("m0inv", C.c_longlong),
                 ("sca_sweeps", C.c_longlong), ("reliable_updates", C.c_longlong),
                 ("relres", C.c_double * 2), ("relres_normal", C.c_double),
-                ("seconds", C.c_double), ("paper_mv", C.c_double), ("status", C.c_int)]
+                ("seconds", C.c_double), ("paper_mv", C.c_double), ("status", C.c_int),
+                ("host_syncs", C.c_longlong), ("host_submits", C.c_longlong)]
 
     def as_dict(self):
         return dict(iters=(self.iters[0], self.iters[1]), mv=self.mv, m0inv=self.m0inv,
                     sca_sweeps=self.sca_sweeps, reliable_updates=self.reliable_updates,
                     relres=(self.relres[0], self.relres[1]), relres_normal=self.relres_normal,
-                    seconds=self.seconds, paper_mv=self.paper_mv, status=self.status)
+                    seconds=self.seconds, paper_mv=self.paper_mv, status=self.status,
+                    host_syncs=self.host_syncs, host_submits=self.host_submits)
 
 
 _P = C.c_void_p
@@ -63,7 +65,7 @@ _SIGNATURES = {
     "solve_batched": (C.c_int, [C.POINTER(_P), C.c_int, C.POINTER(_P), C.POINTER(_P),
                                 C.POINTER(C.c_int), C.POINTER(ufg_precond),
                                 C.POINTER(ufg_solve_opts), C.POINTER(ufg_solve_stats)]),
-    "solve_batched_tune": (C.c_int, [C.c_int, C.c_int, C.c_longlong, C.c_int]),
+    "solve_batched_tune": (C.c_int, [C.c_int, C.c_int, C.c_longlong, C.c_int, C.c_int]),
     "force_dS_dsigma": (C.c_int, [_P, _P, _P, C.c_int, _P]),
     "lattice_tune": (C.c_int, [_P, C.c_int, C.c_int]),
     "lattice_tune_slabs": (C.c_int, [_P, C.c_int]),

@@ -75,7 +75,8 @@ int cheb_plan(int degree, double eps, std::vector<double2>* roots, double2* cf);
 int solve_batched_impl(const ufg_lattice* Ls, int nprob, const void* const* b, void* const* x,
                        const int* nrhs, const ufg_precond* p, const ufg_solve_opts* o,
                        ufg_solve_stats* st);
-int batched_tune(int hop_blocks_per_cu, int vec_blocks_per_cu, long long chunk, int slab);
+int batched_tune(int hop_blocks_per_cu, int vec_blocks_per_cu, long long chunk, int slab,
+                 int sync_iters);
 int euler_weights(int order, double p, double* w);
 
 // T_{xy} = (1/Nx) sum_m exp(-tau k_m^2 / 2) cos(k_m (x - y)), k_m = 2 pi m / Nx,
@@ -466,8 +467,8 @@ int solve_batched(const ufg_lattice* Ls, int nprob, const void* const* b, void* 
 }
 
 int solve_batched_tune(int hop_blocks_per_cu, int vec_blocks_per_cu, long long chunk,
-                       int slab) {
-  return batched_tune(hop_blocks_per_cu, vec_blocks_per_cu, chunk, slab);
+                       int slab, int sync_iters) {
+  return batched_tune(hop_blocks_per_cu, vec_blocks_per_cu, chunk, slab, sync_iters);
 }
 
 int ufg_device_copy(const void* src, void* dst, long long bytes, void* hip_stream) {

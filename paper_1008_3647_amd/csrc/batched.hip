@@ -7,10 +7,13 @@
 // operator launch per class of segments sharing Nx and T, over (segment, slab
 // group) items, with BiCGStab's p- and s-updates fused into it, and one vector
 // launch over (segment, chunk) items, so small lattices share the GPU instead
-// of each paying its own launches. The iteration body of one check interval is
-// captured once in a hipGraph and replayed; between replays the host reads the
-// flags and runs the reliable updates (FP64 residual of the outer complex128
-// vectors) and restarts for the segments that asked for them.
+// of each paying its own launches. Whole check intervals, each closed by the
+// check point's reliable updates (FP64 residual of the outer complex128
+// vectors) and restarts as launches gated per segment by its device flags, are
+// captured once in hipGraphs of one and of about 100 iterations' worth of
+// intervals and replayed; the host reads the flags once per replay of the
+// larger graph, and the work tables (with their sizes in device memory) are
+// compacted without a new capture.
 #include <algorithm>
 #include <chrono>
 #include <cmath>
@@ -49,6 +52,7 @@ int g_hop_blocks_per_cu = 4;
 int g_vec_blocks_per_cu = 8;
 long long g_chunk = 4096;
 int g_bop_slab = 2;
+int g_sync_iters = 100;  // iterations between host reads of the flags
 
 template <typename R>
 __device__ __forceinline__ const R* fld(const BSeg& g);
@@ -258,7 +262,9 @@ __device__ __forceinline__ void bsource(const C2<R>* src, const BSrc<R>& b, cons
   }
 }
 
-// y_t = x_t + s T^3(...) over the items [i0, i1) of one class.
+// y_t = x_t + s T^3(...) over the items [range[0], range[1]) of one class (the
+// range lives in device memory, so a captured launch follows the work tables
+// when they are compacted).
 // RES (SRC 0, R = double): y = b - M x on the outer FP64 vectors of the segment;
 // else SRC 0 applies the operator to bs.p. SRC 3 is the source of SRC 2 with
 // red_mode 4.
@@ -267,8 +273,9 @@ __device__ __forceinline__ void bsource(const C2<R>* src, const BSrc<R>& b, cons
 template <typename R, int NX, int DIR, bool RES, bool SPLIT, int SRC>
 __global__ void __launch_bounds__(bop_threads(NX))
     bop_kernel(BCoef<R, NX, SPLIT> c, const BSeg* __restrict__ segs,
-               const BHop* __restrict__ items, int i0, int i1, BSrc<R> bs, C2<R>* dst_cat,
+               const BHop* __restrict__ items, const int* range, BSrc<R> bs, C2<R>* dst_cat,
                int red_mode, const C2<R>* redw_cat, double* part, const int* gate, int slab) {
+  const int i0 = range[0], i1 = range[1];
   constexpr int P = NX * NX, V = NX * NX * NX, SL = NX * NX * (NX + 1), SG = bop_groups(NX);
   constexpr int SM = (SRC == 3) ? 2 : SRC;  // source mode
   extern __shared__ __align__(16) unsigned char smem_raw[];
@@ -421,8 +428,10 @@ struct BVecArgs {
 
 template <typename R>
 __global__ void __launch_bounds__(256)
-    bvec_kernel(int op, const BSeg* __restrict__ segs, const BVec* __restrict__ items, int nitems,
-                BVecArgs A, const RhsState* st, const int* gate, double* part) {
+    bvec_kernel(int op, const BSeg* __restrict__ segs, const BVec* __restrict__ items,
+                const int* nitems_dev, BVecArgs A, const RhsState* st, const int* gate,
+                double* part) {
+  const int nitems = *nitems_dev;
   __shared__ double scratch[16];
   C2<R>* X = reinterpret_cast<C2<R>*>(A.x);
   C2<R>* Rr = reinterpret_cast<C2<R>*>(A.r);
@@ -552,7 +561,9 @@ struct Dev {
 struct BClass {
   int nx = 0;
   std::vector<double> T, coef;  // coef: block form (Nx in {8, 12, 16}) or T
-  int i0 = 0, i1 = 0;           // item range in the operator table
+  int i0 = 0, i1 = 0;           // item range in the operator table (host copy)
+  int nmax = 0;                 // items of the class with every segment live
+  const int* range = nullptr;   // device copy of {i0, i1}
 };
 
 template <typename R, int NX, int DIR, bool RES, int SRC>
@@ -567,7 +578,8 @@ int launch_bop_nx(const BClass& k, int ncu, hipStream_t cs, bool prepare, const 
     UFG_HIP(hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
     return UFG_OK;
   }
-  const int n = k.i1 - k.i0;
+  // persistent grid sized for the full table; the live range is read on the device
+  const int n = k.nmax;
   if (n <= 0) return UFG_OK;
   BCoef<R, NX, SPLIT> c;
   if constexpr (SPLIT) {
@@ -581,7 +593,7 @@ int launch_bop_nx(const BClass& k, int ncu, hipStream_t cs, bool prepare, const 
   }
   const dim3 grid(std::max(1, std::min(n, ncu * g_hop_blocks_per_cu)));
   hipLaunchKernelGGL((bop_kernel<R, NX, DIR, RES, SPLIT, SRC>), grid, dim3(bop_threads(NX)), lds,
-                     cs, c, dseg, dhop, k.i0, k.i1, bsrc, dst, red_mode, redw, part, gate, slab);
+                     cs, c, dseg, dhop, k.range, bsrc, dst, red_mode, redw, part, gate, slab);
   UFG_HIP(hipGetLastError());
   return UFG_OK;
 }
@@ -688,9 +700,11 @@ int run_batched(std::vector<Lattice*>& Ls, const void* const* bu, void* const* x
   };
   const std::vector<char> all_segs(S, 1);
   make_tables(all_segs);
+  for (int c = 0; c < C; ++c) cls[c].nmax = cls[c].i1 - cls[c].i0;
+  const int nv_max = (int)vecs.size();
   // device memory
   const size_t vbytes = sizeof(C2<RI>) * (size_t)total;
-  Dev dvec[8], dr64, dy, dsegs, dhops, dvecs, dtab, dhpart, dvpart, dstate;
+  Dev dvec[8], dr64, dy, dsegs, dhops, dvecs, dtab, dhpart, dvpart, dstate, dcnt;
   for (auto& d : dvec) UFG_TRY(d.alloc(vbytes));
   UFG_TRY(dr64.alloc(sizeof(double2) * (size_t)total));
   UFG_TRY(dy.alloc(sizeof(double2) * (size_t)total));
@@ -701,6 +715,12 @@ int run_batched(std::vector<Lattice*>& Ls, const void* const* bu, void* const* x
   UFG_TRY(dhpart.alloc(sizeof(double) * 8 * hops.size()));
   UFG_TRY(dvpart.alloc(sizeof(double) * 4 * vecs.size()));
   UFG_TRY(dstate.alloc(sizeof(RhsState) * S + sizeof(int) * 3 * S));
+  UFG_TRY(dcnt.alloc(sizeof(int) * (2 * C + 1)));  // class item ranges, vector item count
+  int* cnt_dev = reinterpret_cast<int*>(dcnt.p);
+  for (int c = 0; c < C; ++c) cls[c].range = cnt_dev + 2 * c;
+  const int* nv_dev = cnt_dev + 2 * C;
+  std::vector<int> hcnt(2 * C + 1);
+  long long n_sync = 0, n_submit = 0;  // host synchronisations and submissions
   hipStream_t cs = nullptr;
   UFG_HIP(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking));
   struct StreamGuard {
@@ -710,9 +730,11 @@ int run_batched(std::vector<Lattice*>& Ls, const void* const* bu, void* const* x
     }
   } guard{cs};
   int* tab = reinterpret_cast<int*>(dtab.p);
-  int nv = 0;
-  dim3 vgrid(1);
-  // upload the tables (the device buffers were sized for all segments)
+  // persistent vector grid sized for the full table
+  const dim3 vgrid(std::max(1, std::min(nv_max, ncu * g_vec_blocks_per_cu)));
+  // upload the tables and their sizes (the device buffers were sized for all
+  // segments); captured launches read them from there. Synchronous: the host
+  // copies must stay alive until the transfer is done.
   auto upload_tables = [&]() -> int {
     UFG_HIP(hipMemcpyAsync(tab, htab.data(), sizeof(int) * 4 * S, hipMemcpyHostToDevice, cs));
     if (!hops.empty())
@@ -721,8 +743,16 @@ int run_batched(std::vector<Lattice*>& Ls, const void* const* bu, void* const* x
     if (!vecs.empty())
       UFG_HIP(hipMemcpyAsync(dvecs.p, vecs.data(), sizeof(BVec) * vecs.size(),
                              hipMemcpyHostToDevice, cs));
-    nv = (int)vecs.size();
-    vgrid = dim3(std::max(1, std::min(nv, ncu * g_vec_blocks_per_cu)));
+    for (int c = 0; c < C; ++c) {
+      hcnt[2 * c] = cls[c].i0;
+      hcnt[2 * c + 1] = cls[c].i1;
+    }
+    hcnt[2 * C] = (int)vecs.size();
+    UFG_HIP(hipMemcpyAsync(cnt_dev, hcnt.data(), sizeof(int) * (2 * C + 1),
+                           hipMemcpyHostToDevice, cs));
+    UFG_HIP(hipStreamSynchronize(cs));
+    n_submit += 4;
+    ++n_sync;
     return UFG_OK;
   };
   UFG_TRY(upload_tables());
@@ -856,8 +886,8 @@ int run_batched(std::vector<Lattice*>& Ls, const void* const* bu, void* const* x
       return UFG_OK;
     };
     auto vop = [&](int op, const int* gate, const BVecArgs& args) {
-      hipLaunchKernelGGL((bvec_kernel<RI>), vgrid, dim3(256), 0, cs, op, dseg, dvv, nv, args, K.st,
-                         gate, vpart);
+      hipLaunchKernelGGL((bvec_kernel<RI>), vgrid, dim3(256), 0, cs, op, dseg, dvv, nv_dev, args,
+                         K.st, gate, vpart);
     };
     // initial state: x = 0, r = b, rhat = r
     vop(3, nullptr, VA);
@@ -903,14 +933,30 @@ int run_batched(std::vector<Lattice*>& Ls, const void* const* bu, void* const* x
       }
       return UFG_OK;
     };
-    Graph G;
-    auto capture = [&]() -> int {
-      if (G.e) (void)hipGraphExecDestroy(G.e);
-      if (G.g) (void)hipGraphDestroy(G.g);
-      G.e = nullptr;
-      G.g = nullptr;
+    // the check point that closes an interval: reliable update (x64 += x_in,
+    // r64 = b - A x64, r = r64) and restart, gated per system by its flags
+    auto check_point = [&]() -> int {
+      vop(4, K.update, VA);
+      UFG_TRY(residual(K.update));
+      vop(5, K.update, VA);
+      UFG_TRY(k_finalize_seg(cs, FIN_UPDATE, vpart, vf, vc, K.update, K));
+      vop(6, K.restart, VA);
+      UFG_TRY(k_finalize_seg(cs, FIN_RESTART, vpart, vf, vc, K.restart, K));
+      return UFG_OK;
+    };
+    // Whole check intervals, check points included, are captured once: G1
+    // holds one interval, GU holds U of them (about g_sync_iters iterations).
+    // The work tables and their sizes live in device memory, so compacting
+    // them needs no new capture.
+    const int U = std::max(1, g_sync_iters / check);
+    Graph G1, GU;
+    auto capture = [&](Graph& G, int nint) -> int {
       UFG_HIP(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
-      const int brc = body();
+      int brc = UFG_OK;
+      for (int j = 0; j < nint && brc >= 0; ++j) {
+        brc = body();
+        if (brc >= 0) brc = check_point();
+      }
       hipGraph_t graph = nullptr;
       const hipError_t ec = hipStreamEndCapture(cs, &graph);
       G.g = graph;
@@ -919,48 +965,47 @@ int run_batched(std::vector<Lattice*>& Ls, const void* const* bu, void* const* x
       UFG_HIP(hipGraphInstantiate(&G.e, G.g, nullptr, nullptr, 0));
       return UFG_OK;
     };
-    UFG_TRY(capture());
+    UFG_TRY(capture(G1, 1));
+    if (U > 1) UFG_TRY(capture(GU, U));
     int in_tables = S;  // segments the current tables cover
     const int launches = (o.maxit + check - 1) / check;
     bool done = false;
     UFG_HIP(hipMemcpyAsync(hflags.data(), K.active, sizeof(int) * 3 * S, hipMemcpyDeviceToHost, cs));
     UFG_HIP(hipStreamSynchronize(cs));
+    n_submit += 4;  // initial vector pass, two finalizes, flag copy
+    ++n_sync;
     done = std::all_of(hflags.begin(), hflags.begin() + S, [](int v) { return v == 0; });
-    // After each check interval the reliable update (x64 += x_in, r64 = b - A
-    // x64, r = r64) and the restart are issued as launches gated per system by
-    // their device flags; the flags are then copied behind them to pinned
-    // memory, which the host reads after issuing the next interval. A system
-    // inactive there stays inactive (only active systems raise update flags),
-    // so the work tables may drop it one interval late, and the loop ends one
-    // interval late on launches that do nothing.
+    // The host replays U intervals (or single ones for the last, partial
+    // stretch before maxit), then reads the flags once. A system stops on the
+    // device at its own check point; the host only ends the loop and, once
+    // half of the covered systems have stopped, drops them from the work
+    // tables so that the tail of the batch launches only the live work.
     UFG_TRY(mirror.ensure(3 * S));
-    for (int n = 0; n < launches && !done; ++n) {
-      UFG_HIP(hipGraphLaunch(G.e, cs));
-      vop(4, K.update, VA);
-      UFG_TRY(residual(K.update));
-      vop(5, K.update, VA);
-      UFG_TRY(k_finalize_seg(cs, FIN_UPDATE, vpart, vf, vc, K.update, K));
-      vop(6, K.restart, VA);
-      UFG_TRY(k_finalize_seg(cs, FIN_RESTART, vpart, vf, vc, K.restart, K));
-      UFG_HIP(hipGetLastError());
-      const int slot = n & 1;
-      UFG_HIP(hipMemcpyAsync(mirror.host + slot * mirror.cap, K.active, sizeof(int) * 3 * S,
-                             hipMemcpyDeviceToHost, cs));
-      UFG_HIP(hipEventRecord(mirror.ev[slot], cs));
-      if (n == 0) continue;
-      UFG_HIP(hipEventSynchronize(mirror.ev[slot ^ 1]));
-      const int* f = mirror.host + (slot ^ 1) * mirror.cap;
+    int n = 0;
+    while (n < launches && !done) {
+      if (U > 1 && launches - n >= U) {
+        UFG_HIP(hipGraphLaunch(GU.e, cs));
+        n += U;
+        ++n_submit;
+      } else {
+        const int k = std::min(U, launches - n);
+        for (int j = 0; j < k; ++j) UFG_HIP(hipGraphLaunch(G1.e, cs));
+        n += k;
+        n_submit += k;
+      }
+      UFG_HIP(hipMemcpyAsync(mirror.host, K.active, sizeof(int) * 3 * S, hipMemcpyDeviceToHost,
+                             cs));
+      UFG_HIP(hipStreamSynchronize(cs));
+      ++n_submit;
+      ++n_sync;
+      const int* f = mirror.host;
       const int nactive = (int)std::count_if(f, f + S, [](int v) { return v != 0; });
       done = nactive == 0;
-      // once half of the covered systems have stopped, drop them from the work
-      // tables so that the tail of the batch launches only the live work
       if (!done && 2 * nactive <= in_tables) {
         std::vector<char> live(S);
         for (int s = 0; s < S; ++s) live[s] = f[s] != 0;
-        UFG_HIP(hipStreamSynchronize(cs));  // the tables are in use until here
         make_tables(live);
         UFG_TRY(upload_tables());
-        UFG_TRY(capture());
         in_tables = nactive;
       }
     }
@@ -971,6 +1016,8 @@ int run_batched(std::vector<Lattice*>& Ls, const void* const* bu, void* const* x
     vop(4, nullptr, VA);  // final x64 += x_in
     UFG_HIP(hipMemcpyAsync(hst.data(), K.st, sizeof(RhsState) * S, hipMemcpyDeviceToHost, cs));
     UFG_HIP(hipStreamSynchronize(cs));
+    n_submit += 2;
+    ++n_sync;
     iters_step[step].assign(nprob, 0);
     for (int s = 0; s < S; ++s) {
       const int i = seg_prob[s];
@@ -986,6 +1033,8 @@ int run_batched(std::vector<Lattice*>& Ls, const void* const* bu, void* const* x
     UFG_TRY(k_finalize_seg(cs, FIN_NORM, vpart, vf, vc, nullptr, K));
     UFG_HIP(hipMemcpyAsync(hst.data(), K.st, sizeof(RhsState) * S, hipMemcpyDeviceToHost, cs));
     UFG_HIP(hipStreamSynchronize(cs));
+    n_submit += (long long)C + 6;
+    ++n_sync;
     relres_step[step].assign(nprob, 0.0);
     for (int s = 0; s < S; ++s) {
       const int i = seg_prob[s];
@@ -1007,6 +1056,8 @@ int run_batched(std::vector<Lattice*>& Ls, const void* const* bu, void* const* x
       q.relres_normal = -1.0;
       q.paper_mv = 2.0 * (q.iters[0] + q.iters[1]);
       q.status = status[i];
+      q.host_syncs = n_sync;
+      q.host_submits = n_submit;
     }
   }
   return worst;
@@ -1043,15 +1094,18 @@ int solve_batched_impl(const ufg_lattice* Ls, int nprob, const void* const* b, v
   return rc;
 }
 
-int batched_tune(int hop_blocks_per_cu, int vec_blocks_per_cu, long long chunk, int slab) {
+int batched_tune(int hop_blocks_per_cu, int vec_blocks_per_cu, long long chunk, int slab,
+                 int sync_iters) {
   UFG_CHECK(hop_blocks_per_cu >= 0 && hop_blocks_per_cu <= 64, "bad hop blocks per CU");
   UFG_CHECK(vec_blocks_per_cu >= 0 && vec_blocks_per_cu <= 64, "bad vector blocks per CU");
   UFG_CHECK(chunk == 0 || (chunk >= 256 && chunk <= (1 << 22)), "bad chunk");
   UFG_CHECK(slab >= 0 && slab <= 64, "bad slab");
+  UFG_CHECK(sync_iters >= 0 && sync_iters <= 100000, "bad iterations per host check");
   g_hop_blocks_per_cu = hop_blocks_per_cu ? hop_blocks_per_cu : 4;
   g_vec_blocks_per_cu = vec_blocks_per_cu ? vec_blocks_per_cu : 8;
   g_chunk = chunk ? chunk : 4096;
   g_bop_slab = slab ? slab : 2;
+  g_sync_iters = sync_iters ? sync_iters : 100;
   return UFG_OK;
 }
 

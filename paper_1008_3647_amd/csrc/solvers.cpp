@@ -671,6 +671,8 @@ int bicgstab_dispatch(Lattice& L, const PcPlan& pc, int op, const void* bv, void
     st->relres_normal = relq;
     st->paper_mv = (double)(r1.iters + r2.iters) * (2.0 + 2.0 * pc.paper_cost());
     st->status = std::max(r1.status, r2.status);
+    st->host_syncs = 0;
+    st->host_submits = 0;
   }
   return std::max(r1.status, r2.status);
 }
@@ -697,6 +699,8 @@ int cg_dispatch(Lattice& L, const PcPlan& pc, const void* bv, void* xv, int nrhs
     st->relres_normal = relq;
     st->paper_mv = (double)r1.iters * (2.0 + pc.paper_cost());
     st->status = r1.status;
+    st->host_syncs = 0;
+    st->host_submits = 0;
   }
   return r1.status;
 }

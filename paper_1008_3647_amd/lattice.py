@@ -286,7 +286,8 @@ def solve_batched(lattices, bs, tol=1e-10, maxit=10000, mixed=True, delta=0.1, c
     return xs, [s.as_dict() for s in st]
 
 
-def solve_batched_tune(hop_blocks_per_cu=0, vec_blocks_per_cu=0, chunk=0, slab=0):
+def solve_batched_tune(hop_blocks_per_cu=0, vec_blocks_per_cu=0, chunk=0, slab=0, sync_iters=0):
     """Launch shape of batched solves (0 = default); see ufg.h."""
     L.check(L.load().solve_batched_tune(int(hop_blocks_per_cu), int(vec_blocks_per_cu),
-                                        int(chunk), int(slab)), "solve_batched_tune")
+                                        int(chunk), int(slab), int(sync_iters)),
+            "solve_batched_tune")
