@@ -84,6 +84,26 @@ def apply_cheb(v, sigma, tau, g, degree, eps, lam_max):
     return y
 
 
+def apply_sca_cheb(v, sigma, tau, g, degree, eps, lam_max, alpha=1.0):
+    """Strong coupling with the Chebyshev polynomial as a secondary filter
+    (paper, Sec. 4, closing remark; Sec. 2 for the polynomial).
+
+    Reading: the strong-coupling inverse S = (L^dagger D L)^{-1} ~ Q^{-1} is
+    applied first, and the Chebyshev approximation of 1/z then acts on the
+    S-preconditioned operator: P v = P_2n(S Q / lam_max) S v, with lam_max the
+    largest eigenvalue of S Q (real and positive: S Q is similar to the
+    Hermitian S^{1/2} Q S^{1/2}), so P ~ (S Q)^{-1} S = Q^{-1}. Factors in
+    bit-reversal order with c^{1/(2n)} each, as in apply_cheb.
+    """
+    D, L = sca_setup(sigma, tau, g, alpha)
+    roots = cheb_roots(degree, eps)
+    cf = cheb_constant(degree, eps) ** (1.0 / degree)
+    y = sca_apply(v, D, L)
+    for j in bit_reversal_order(degree):
+        y = cf * (sca_apply(apply_Q(y, sigma, tau, g), D, L) / lam_max - roots[j] * y)
+    return y
+
+
 # --------------------------------------------------------------------------
 # Strong-coupling approximation (paper, Sec. 4)
 

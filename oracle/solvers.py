@@ -109,6 +109,23 @@ def solve_cg_normal(b, apply_M, apply_Mdag, tol=1e-10, maxit=10000, precond=None
     return cg(Q, b, tol, maxit, precond)
 
 
+def solve_cg_split(b, apply_M, apply_Mdag, apply_E, apply_Edag, tol=1e-10, maxit=10000):
+    """CG on the normal equations with split preconditioning (paper, Sec. 5,
+    the remark after Table 2: (M0^dagger)^{-1} on the left and M0^{-1} on the
+    right of M^dagger M). With E ~ M^{-1} (E = M0^{-1} in the paper, or any
+    weak-coupling W_d) CG runs on the Hermitian positive-definite
+    A' = E^dagger M^dagger M E with right-hand side b' = E^dagger b, and
+    x = E z. The stop rule is CG's own residual, ||b' - A' z|| <= tol ||b'||;
+    the residual of the original system is reported beside it."""
+    Ap = lambda z: apply_Edag(apply_Mdag(apply_M(apply_E(z))))  # noqa: E731
+    bp = apply_Edag(b)
+    z, st = cg(Ap, bp, tol, maxit)
+    x = apply_E(z)
+    relq = _norm(b - apply_Mdag(apply_M(x))) / _norm(b)
+    return x, dict(iters=st["iters"], status=st["status"], relres_split=st["relres"],
+                   relres=relq)
+
+
 def solve_two_step(b, apply_M, apply_Mdag, tol=1e-10, maxit=10000,
                    precond_M=None, precond_Mdag=None):
     """M^dagger y = b, then M x = y, each by BiCGStab (paper, Eq. 2)."""

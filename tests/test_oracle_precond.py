@@ -203,3 +203,38 @@ def test_euler_weights_closed_form():
         terms = rng.standard_normal(d + 1)
         est = pc.euler_estimate(list(np.cumsum(terms)))
         assert est == pytest.approx(np.dot(pc.euler_weights(d), terms), rel=1e-13)
+
+
+@pytest.mark.parametrize("degree", [4, 8])
+def test_sca_chebyshev_filter_via_eigendecomposition(degree):
+    """apply_sca_cheb (P = P_2n(S Q / lam_max) S) against a dense route that
+    does not use its factor sweep: S = (L^T D L)^{-1} assembled per site from
+    the dense factors, H = S^{1/2} Q S^{1/2} = V diag(lam) V^H (Hermitian, similar
+    to S Q), P = S^{1/2} V p(lam / lam_max) V^H S^{1/2} with the scalar
+    polynomial p (cheb_scalar, pinned by the Chebyshev closed form). With
+    lam_max above the largest lam, P is Hermitian positive definite."""
+    nx, ntau, alpha, eps = 2, 6, 1.5, 1e-2
+    V = nx ** 3
+    N = V * ntau
+    sigma = sigma_field(nx, ntau, 91)
+    v = gaussian_rhs(nx, ntau, [92])[0]
+    D, L = pc.sca_setup(sigma, TAU, G, alpha)
+    S = np.zeros((N, N))
+    for n in range(V):
+        iz, iy, ix = np.unravel_index(n, (nx, nx, nx))
+        Ld, Dd = pc.sca_dense_factors(D[:, iz, iy, ix], L[:, iz, iy, ix])
+        Sn = np.linalg.inv(Ld @ Dd @ Ld.T)
+        idx = np.arange(ntau) * V + n
+        S[np.ix_(idx, idx)] = Sn
+    Md = op.dense_M(sigma, TAU, G)
+    w, U = np.linalg.eigh(S)
+    assert w.min() > 0
+    Sh = (U * np.sqrt(w)) @ U.T
+    lam, Vh = np.linalg.eigh(Sh @ (Md.T @ Md) @ Sh)
+    lam_max = 1.02 * lam[-1]
+    p = pc.cheb_scalar(lam / lam_max, degree, eps)
+    assert np.all(p.real > 0) and np.max(np.abs(p.imag)) < 1e-10 * np.max(np.abs(p))
+    P = Sh @ (Vh * p) @ Vh.conj().T @ Sh
+    got = pc.apply_sca_cheb(v, sigma, TAU, G, degree, eps, lam_max, alpha)
+    ref = (P @ v.ravel()).reshape(v.shape)
+    assert np.max(np.abs(got - ref)) < 1e-11 * np.max(np.abs(ref))

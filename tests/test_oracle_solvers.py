@@ -125,3 +125,35 @@ def test_paper_mv_table_follows_cost_model():
         assert int(r2["gain"]) == int(np.floor(min(cg) / int(r2["wce0"]) + 0.5))
     # the only mismatch is the printed 21,313 (model: 7,104 x 3 = 21,312)
     assert mismatches == [("10", "100", "sca", 21312, 21313)]
+
+
+def test_split_cg_against_dense_lu_and_pcg_iterates():
+    """solve_cg_split (E = M0^{-1} right, E^dagger left; Sec. 5 after Table 2):
+    (i) its solution is the dense-LU solution of M^T M x = b; (ii) in exact
+    arithmetic split CG is PCG with P = E E^dagger, so after k iterations both
+    hold the same iterate x_k (k = 1..4, against the oracle's cg with that
+    preconditioner) -- a missing E^dagger on the right-hand side or a missing E
+    on the result changes the iterates. (M0 is normal, so E E^dagger =
+    E^dagger E and the order of the two factors cannot be told apart here.)"""
+    nx, ntau = 2, 8
+    sigma = sigma_field(nx, ntau, 71)
+    b = gaussian_rhs(nx, ntau, [72])[0]
+    M, Mt = _ops(sigma)
+    E = lambda v: oracle.apply_M0inv(v, TAU)  # noqa: E731
+    Ed = lambda v: oracle.apply_M0inv_dag(v, TAU)  # noqa: E731
+    Md = op.dense_M(sigma, TAU, G)
+    x_lu = solvers.dense_two_step(Md, b.ravel()).reshape(b.shape)
+    x, st = solvers.solve_cg_split(b, M, Mt, E, Ed, tol=1e-13, maxit=2000)
+    assert st["status"] == 0
+    assert np.linalg.norm(x - x_lu) / np.linalg.norm(x_lu) < 1e-9
+    Q = lambda v: Mt(M(v))  # noqa: E731
+    for k in range(1, 5):
+        xs, _ = solvers.solve_cg_split(b, M, Mt, E, Ed, tol=1e-30, maxit=k)
+        xp, _ = solvers.cg(Q, b, tol=1e-30, maxit=k, precond=lambda r: E(Ed(r)))
+        assert np.linalg.norm(xs - xp) / np.linalg.norm(xp) < 1e-11, k
+    # without the final x = E z the iterate is z, not x
+    Ap = lambda z: Ed(Mt(M(E(z))))  # noqa: E731
+    z3, _ = solvers.cg(Ap, Ed(b), tol=1e-30, maxit=3)
+    xs3, _ = solvers.solve_cg_split(b, M, Mt, E, Ed, tol=1e-30, maxit=3)
+    assert np.linalg.norm(z3 - xs3) / np.linalg.norm(xs3) > 1e-3
+    assert np.linalg.norm(E(z3) - xs3) / np.linalg.norm(xs3) < 1e-13
