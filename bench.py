@@ -270,6 +270,11 @@ def report_config2(a):
     for alpha in (1.0, 1.5, 2.0, 3.0):
         cells.append(("CG", "sca", dict(alpha=alpha)))
     cells.append(("CG", "wce", dict(wce_order=1)))
+    for d in (8, 16):
+        cells.append(("CG", "sca_cheb", dict(degree=d, eps=1e-2 if d == 8 else 3e-3,
+                                              lam_max=-1.0, alpha=2.0)))
+    cells.append(("CG-split", "wce", dict(wce_order=0)))
+    cells.append(("CG-split", "wce", dict(wce_order=1)))
     cells.append(("BiCGStab", "none", {}))
     for d in (0, 1, 2, 4):
         cells.append(("BiCGStab", "wce", dict(wce_order=d)))
@@ -284,12 +289,15 @@ def report_config2(a):
         pc = Precond(kind, **kw) if kind != "none" else None
         if solver == "CG":
             run = lambda: L.solve_cg_normal(b, pc, tol=tol, maxit=20000)  # noqa: E731
+        elif solver == "CG-split":
+            run = lambda: L.solve_cg_split(b, pc, tol=tol, maxit=20000)  # noqa: E731
         else:
             run = lambda: L.solve_bicgstab(b, "two_step", pc, tol=tol, maxit=20000)  # noqa: E731
         run()  # warm-up (preconditioner setup, lambda_max estimate)
         (x, st), secs = _timed(run)
-        its = st["iters"][0] if solver == "CG" else "+".join(str(i) for i in st["iters"])
-        rr = st["relres"][0] if solver == "CG" else max(st["relres"])
+        cg = solver.startswith("CG")
+        its = st["iters"][0] if cg else "+".join(str(i) for i in st["iters"])
+        rr = st["relres"][0] if cg else max(st["relres"])
         desc = kind if not kw else kind + " " + ", ".join(f"{k}={v}" for k, v in kw.items()
                                                           if k != "lam_max")
         print(f"| {solver} | {desc} | {its} | {st['mv']} | {st['m0inv']} | {st['sca_sweeps']} | "

@@ -53,7 +53,7 @@ enum {
 };
 
 /* Preconditioner kinds (paper, Secs. 2-4). */
-enum { UFG_PC_NONE = 0, UFG_PC_CHEB = 1, UFG_PC_SCA = 2, UFG_PC_WCE = 3 };
+enum { UFG_PC_NONE = 0, UFG_PC_CHEB = 1, UFG_PC_SCA = 2, UFG_PC_WCE = 3, UFG_PC_SCA_CHEB = 4 };
 
 /*
  * Preconditioner description.
@@ -63,13 +63,17 @@ enum { UFG_PC_NONE = 0, UFG_PC_CHEB = 1, UFG_PC_SCA = 2, UFG_PC_WCE = 3 };
  *        lam_max == 0: the bound (1 + max|1 + A sin sigma|)^2 >= ||Q||;
  *        lam_max < 0: 30 power iterations on Q, times 1.05.
  *   SCA  (Sec. 4): (L^dagger D L)^{-1}, shift `alpha` (> 0).
+ *   SCA_CHEB (Sec. 4, closing remark: the Chebyshev approximation as a
+ *        secondary filter of SCA): P = P_2n(S Q / lam_max) S, S the SCA inverse
+ *        (shift `alpha`), the polynomial of CHEB with `degree` and `eps`;
+ *        lam_max > 0 used as given, else 1.05 times 30 power iterations on S Q.
  *   WCE  (Sec. 3): W_d = sum_{m<=d} w_m (-A M0^{-1} M1)^m M0^{-1}, d =
  *        `wce_order` (0..8); w_m = 1, or the Euler weights of Sec. 3.1 with
  *        parameter `euler_p` when `euler` != 0 (estimate S_{d,0}).
  * How a kind acts for each operator (apply_precond's `op`):
- *   op = UFG_OP_Q   : CHEB P(Q^), SCA (L^dagger D L)^{-1}, WCE W_d W_d^dagger
- *   op = UFG_OP_M   : WCE W_d;          CHEB/SCA  P M^dagger  (extension)
- *   op = UFG_OP_MDAG: WCE W_d^dagger;   CHEB/SCA  M P         (extension)
+ *   op = UFG_OP_Q   : CHEB P(Q^), SCA (L^dagger D L)^{-1}, SCA_CHEB P, WCE W_d W_d^dagger
+ *   op = UFG_OP_M   : WCE W_d;          CHEB/SCA/SCA_CHEB  P M^dagger  (extension)
+ *   op = UFG_OP_MDAG: WCE W_d^dagger;   CHEB/SCA/SCA_CHEB  M P         (extension)
  */
 typedef struct {
   int kind;
@@ -195,6 +199,20 @@ int precond_lam_max(ufg_lattice L, const ufg_precond* p, double* out_host);
 int solve_cg_normal(ufg_lattice L, const ufg_precond* p, const void* b,
                     void* x, int nrhs, const ufg_solve_opts* o,
                     ufg_solve_stats* st);
+
+/*
+ * solve_cg_split -- x = (M^dagger M)^{-1} b by CG with split preconditioning
+ *   (paper, Sec. 5, the remark after Table 2: (M0^dagger)^{-1} on the left and
+ *   M0^{-1} on the right): with E = W_d of the weak-coupling preconditioner p
+ *   (p->kind == UFG_PC_WCE; order 0 is E = M0^{-1}), CG runs on the Hermitian
+ *   positive-definite E^dagger M^dagger M E z = E^dagger b and returns x = E z.
+ *   tol applies to that system's residual ||E^dagger (b - M^dagger M x)||
+ *   relative to ||E^dagger b||; st->relres[0] reports ||b - M^dagger M x|| / ||b||.
+ *   Lattice dtype only (o->mixed = 0), x_0 = 0 (o->use_x0 = 0). Same
+ *   conventions as solve_cg_normal otherwise.
+ */
+int solve_cg_split(ufg_lattice L, const ufg_precond* p, const void* b, void* x, int nrhs,
+                   const ufg_solve_opts* o, ufg_solve_stats* st);
 
 /*
  * solve_bicgstab -- BiCGStab (van der Vorst, right preconditioned) for

@@ -16,7 +16,7 @@ LIB_PATH = os.path.join(_HERE, "libufg.so")
 
 UFG_C64, UFG_C128 = 0, 1
 UFG_OP_M, UFG_OP_MDAG, UFG_OP_TWO_STEP, UFG_OP_Q = 0, 1, 2, 3
-UFG_PC_NONE, UFG_PC_CHEB, UFG_PC_SCA, UFG_PC_WCE = 0, 1, 2, 3
+UFG_PC_NONE, UFG_PC_CHEB, UFG_PC_SCA, UFG_PC_WCE, UFG_PC_SCA_CHEB = 0, 1, 2, 3, 4
 UFG_OK, UFG_EINVAL, UFG_ENOMEM, UFG_EHIP = 0, -1, -2, -3
 UFG_NOT_CONVERGED, UFG_BREAKDOWN = 1, 2
 
@@ -60,6 +60,8 @@ _SIGNATURES = {
     "apply_precond": (C.c_int, [_P, C.POINTER(ufg_precond), C.c_int, _P, _P, C.c_int]),
     "solve_cg_normal": (C.c_int, [_P, C.POINTER(ufg_precond), _P, _P, C.c_int,
                                   C.POINTER(ufg_solve_opts), C.POINTER(ufg_solve_stats)]),
+    "solve_cg_split": (C.c_int, [_P, C.POINTER(ufg_precond), _P, _P, C.c_int,
+                                 C.POINTER(ufg_solve_opts), C.POINTER(ufg_solve_stats)]),
     "solve_bicgstab": (C.c_int, [_P, C.POINTER(ufg_precond), C.c_int, _P, _P, C.c_int,
                                  C.POINTER(ufg_solve_opts), C.POINTER(ufg_solve_stats)]),
     "solve_batched": (C.c_int, [C.POINTER(_P), C.c_int, C.POINTER(_P), C.POINTER(_P),
@@ -119,7 +121,7 @@ def check(code, where):
 @dataclass
 class Precond:
     """Preconditioner description (mirrors ufg_precond)."""
-    kind: str = "none"          # none | cheb | sca | wce
+    kind: str = "none"          # none | cheb | sca | wce | sca_cheb
     degree: int = 16
     eps: float = 1e-2
     lam_max: float = 0.0        # >0 given, 0 bound, <0 power iteration
@@ -129,7 +131,8 @@ class Precond:
     euler_p: float = 0.5
 
     def to_c(self):
-        kinds = {"none": UFG_PC_NONE, "cheb": UFG_PC_CHEB, "sca": UFG_PC_SCA, "wce": UFG_PC_WCE}
+        kinds = {"none": UFG_PC_NONE, "cheb": UFG_PC_CHEB, "sca": UFG_PC_SCA, "wce": UFG_PC_WCE,
+                 "sca_cheb": UFG_PC_SCA_CHEB}
         return ufg_precond(kinds[self.kind], self.degree, self.eps, self.lam_max, self.alpha,
                            self.wce_order, int(self.euler), self.euler_p)
 

@@ -71,6 +71,8 @@ int solve_bicgstab_impl(Lattice& L, const ufg_precond* p, int op, const void* b,
                         int nrhs, const ufg_solve_opts* o, ufg_solve_stats* st);
 int solve_cg_impl(Lattice& L, const ufg_precond* p, const void* b, void* x, int nrhs,
                   const ufg_solve_opts* o, ufg_solve_stats* st);
+int solve_cg_split_impl(Lattice& L, const ufg_precond* p, const void* b, void* x, int nrhs,
+                        const ufg_solve_opts* o, ufg_solve_stats* st);
 int cheb_plan(int degree, double eps, std::vector<double2>* roots, double2* cf);
 int solve_batched_impl(const ufg_lattice* Ls, int nprob, const void* const* b, void* const* x,
                        const int* nrhs, const ufg_precond* p, const ufg_solve_opts* o,
@@ -164,6 +166,7 @@ static int install_field(Lattice& L) {
   UFG_TRY(launch_sca_setup(L, 1.0));
   UFG_HIP(hipStreamSynchronize(L.stream));
   L.lam_max_valid = 0;
+  L.lam_max_sq_valid = 0;
   return UFG_OK;
 }
 
@@ -338,6 +341,13 @@ int solve_cg_normal(ufg_lattice h, const ufg_precond* p, const void* b, void* x,
   return solve_cg_impl(*L, p, b, x, nrhs, o, st);
 }
 
+int solve_cg_split(ufg_lattice h, const ufg_precond* p, const void* b, void* x, int nrhs,
+                   const ufg_solve_opts* o, ufg_solve_stats* st) {
+  Lattice* L = check_handle(h);
+  UFG_CHECK(L != nullptr, "solve_cg_split: NULL handle");
+  return solve_cg_split_impl(*L, p, b, x, nrhs, o, st);
+}
+
 int solve_bicgstab(ufg_lattice h, const ufg_precond* p, int op, const void* b, void* x, int nrhs,
                    const ufg_solve_opts* o, ufg_solve_stats* st) {
   Lattice* L = check_handle(h);
@@ -397,7 +407,8 @@ int precond_lam_max(ufg_lattice h, const ufg_precond* p, double* out_host) {
   Lattice* L = check_handle(h);
   UFG_CHECK(L != nullptr, "precond_lam_max: NULL handle");
   UFG_CHECK(p && out_host, "precond_lam_max: NULL preconditioner or output");
-  UFG_CHECK(p->kind == UFG_PC_CHEB, "precond_lam_max: needs a Chebyshev preconditioner");
+  UFG_CHECK(p->kind == UFG_PC_CHEB || p->kind == UFG_PC_SCA_CHEB,
+            "precond_lam_max: needs a Chebyshev preconditioner (plain or with SCA)");
   PcPlan pc;
   UFG_TRY(resolve_precond(*L, p, &pc));
   *out_host = pc.lam_max;

@@ -25,6 +25,7 @@ double PcPlan::paper_cost() const {
     case UFG_PC_CHEB: return 2.0 * degree;
     case UFG_PC_SCA: return 1.0;
     case UFG_PC_WCE: return 2.0 * (order + 1) + order;  // (d+1) 2 beta + d, beta = 1
+    case UFG_PC_SCA_CHEB: return 2.0 * degree + (degree + 1);  // 2d MV and d + 1 SCA (1 each)
     default: return 0.0;
   }
 }
@@ -181,8 +182,6 @@ int euler_weights(int order, double p, double* w) {
   return UFG_OK;
 }
 
-static int estimate_lam_max(Lattice& L, double* out);
-
 int resolve_precond(Lattice& L, const ufg_precond* p, PcPlan* out) {
   PcPlan pc;
   if (!p || p->kind == UFG_PC_NONE) {
@@ -211,6 +210,21 @@ int resolve_precond(Lattice& L, const ufg_precond* p, PcPlan* out) {
       UFG_CHECK(p->alpha > 0, "SCA needs alpha > 0");
       pc.alpha = p->alpha;
       if (L.sca_alpha != p->alpha) UFG_TRY(launch_sca_setup(L, p->alpha));
+      break;
+    case UFG_PC_SCA_CHEB:
+      UFG_CHECK(p->alpha > 0, "SCA needs alpha > 0");
+      pc.alpha = p->alpha;
+      pc.degree = p->degree;
+      pc.eps = p->eps;
+      if (cheb_plan(p->degree, p->eps, &pc.roots, &pc.cf) != UFG_OK) {
+        set_error("Chebyshev filter needs a power-of-two degree and 0 < eps < 1");
+        return UFG_EINVAL;
+      }
+      if (L.sca_alpha != p->alpha) UFG_TRY(launch_sca_setup(L, p->alpha));
+      if (p->lam_max > 0)
+        pc.lam_max = p->lam_max;
+      else
+        UFG_TRY(estimate_lam_max_sq(L, p->alpha, &pc.lam_max));
       break;
     case UFG_PC_WCE:
       UFG_CHECK(p->wce_order >= 0 && p->wce_order <= kMaxWceOrder, "WCE order must be 0..8");
@@ -430,12 +444,42 @@ static int cheb_apply(Lattice& L, const PcPlan& pc, const C2<R>* x, C2<R>* y, in
   return UFG_OK;
 }
 
+// y = P(S Q / lam_max) S x: the strong-coupling inverse S first, then the
+// Chebyshev factors of the S-preconditioned operator (bit-reversal order,
+// c^{1/2n} each). A factor is M, M^T, the SCA sweep and an axpby.
+template <typename R>
+static int sca_cheb_apply(Lattice& L, const PcPlan& pc, const C2<R>* x, C2<R>* y, int nrhs,
+                          const int* gate, Counters* cnt) {
+  int rc = 0;
+  C2<R>* t1 = slot_vec<R>(L, SLOT_PC0 + 3, nrhs, &rc);
+  UFG_TRY(rc);
+  C2<R>* t2 = slot_vec<R>(L, SLOT_PC0 + 5, nrhs, &rc);
+  UFG_TRY(rc);
+  UFG_TRY(launch_sca_apply<R>(L, x, y, nrhs, gate));
+  cnt->sca += 1;
+  const std::complex<double> cf(pc.cf.x, pc.cf.y);
+  for (size_t i = 0; i < pc.roots.size(); ++i) {
+    const std::complex<double> z(pc.roots[i].x, pc.roots[i].y);
+    const std::complex<double> al = cf / pc.lam_max, be = -cf * z;
+    UFG_TRY(op_apply<R>(L, UFG_OP_M, y, t1, nrhs, gate));
+    UFG_TRY(op_apply<R>(L, UFG_OP_MDAG, t1, t2, nrhs, gate));
+    UFG_TRY(launch_sca_apply<R>(L, t2, t1, nrhs, gate));
+    UFG_TRY(k_axpby<R>(L, double2{al.real(), al.imag()}, t1, double2{be.real(), be.imag()}, y,
+                       nrhs, gate));
+    cnt->mv += 2;
+    cnt->sca += 1;
+  }
+  return UFG_OK;
+}
+
 template <typename R>
 static int q_pc_apply(Lattice& L, const PcPlan& pc, const C2<R>* x, C2<R>* y, int nrhs,
                       const int* gate, Counters* cnt) {
   switch (pc.kind) {
     case UFG_PC_CHEB:
       return cheb_apply<R>(L, pc, x, y, nrhs, gate, cnt);
+    case UFG_PC_SCA_CHEB:
+      return sca_cheb_apply<R>(L, pc, x, y, nrhs, gate, cnt);
     case UFG_PC_SCA:
       cnt->sca += 1;
       return launch_sca_apply<R>(L, x, y, nrhs, gate);
@@ -484,18 +528,17 @@ int pc_apply(Lattice& L, const PcPlan& pc, int op, const C2<R>* x, C2<R>* y, int
   return op_apply<R>(L, UFG_OP_M, mid, y, nrhs, gate);
 }
 
-// lam_max of Q by 30 power iterations (FP64, deterministic start), times 1.05.
-static int estimate_lam_max(Lattice& L, double* out) {
-  if (L.lam_max_valid) {
-    *out = L.lam_max_cache;
-    return UFG_OK;
-  }
+// Largest eigenvalue of Q (sq = false) or of S Q (sq = true) by 30 power
+// iterations in FP64 from a deterministic start, times 1.05. S Q is similar to
+// the Hermitian S^{1/2} Q S^{1/2}, so its dominant eigenvalue is real and
+// positive and |A v| / |v| converges to it.
+static int power_lam_max(Lattice& L, bool sq, double* out) {
   int rc = 0;
   double2* v = slot_vec<double>(L, SLOT_POWER, 1, &rc);
   UFG_TRY(rc);
   double2* w = slot_vec<double>(L, SLOT_POWER2, 1, &rc);
   UFG_TRY(rc);
-  double2* tmp = slot_vec<double>(L, SLOT_PC0 + 4, 1, &rc);
+  double2* tmp = slot_vec<double>(L, SLOT_PC0 + 5, 1, &rc);
   UFG_TRY(rc);
   std::vector<double2> h(L.N);
   for (long long i = 0; i < L.N; ++i) h[i] = double2{1.0 + 0.5 * std::sin(0.7 * i), 0.0};
@@ -506,7 +549,12 @@ static int estimate_lam_max(Lattice& L, double* out) {
   double lam = 0.0;
   RhsState hs;
   for (int it = 0; it < 30; ++it) {
-    UFG_TRY(q_apply<double>(L, v, tmp, w, 1, nullptr));
+    if (sq) {
+      UFG_TRY(q_apply<double>(L, v, w, tmp, 1, nullptr));
+      UFG_TRY(launch_sca_apply<double>(L, tmp, w, 1, nullptr));
+    } else {
+      UFG_TRY(q_apply<double>(L, v, tmp, w, 1, nullptr));
+    }
     UFG_TRY(k_reduce<double>(L, w, nullptr, 0, nullptr, K));
     UFG_TRY(k_finalize(L, FIN_NORM, nvb, nullptr, K));
     UFG_HIP(hipMemcpyAsync(&hs, K.st, sizeof(RhsState), hipMemcpyDeviceToHost, L.stream));
@@ -516,13 +564,31 @@ static int estimate_lam_max(Lattice& L, double* out) {
       set_error("power iteration failed");
       return UFG_EHIP;
     }
-    // |Q v| / |v| with |v| = 1 after the first step
+    // |A v| / |v| with |v| = 1 after the first step
     if (it > 0) lam = nw;
     UFG_TRY(k_axpby<double>(L, double2{1.0 / nw, 0.0}, w, double2{0.0, 0.0}, v, 1, nullptr));
   }
-  L.lam_max_cache = 1.05 * lam;
-  L.lam_max_valid = 1;
+  *out = 1.05 * lam;
+  return UFG_OK;
+}
+
+int estimate_lam_max(Lattice& L, double* out) {
+  if (!L.lam_max_valid) {
+    UFG_TRY(power_lam_max(L, false, &L.lam_max_cache));
+    L.lam_max_valid = 1;
+  }
   *out = L.lam_max_cache;
+  return UFG_OK;
+}
+
+int estimate_lam_max_sq(Lattice& L, double alpha, double* out) {
+  if (!L.lam_max_sq_valid || L.lam_max_sq_alpha != alpha) {
+    if (L.sca_alpha != alpha) UFG_TRY(launch_sca_setup(L, alpha));
+    UFG_TRY(power_lam_max(L, true, &L.lam_max_sq_cache));
+    L.lam_max_sq_alpha = alpha;
+    L.lam_max_sq_valid = 1;
+  }
+  *out = L.lam_max_sq_cache;
   return UFG_OK;
 }
 

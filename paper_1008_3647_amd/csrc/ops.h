@@ -72,16 +72,22 @@ enum Slot {
   SLOT_OUTER_R = 12,
   SLOT_OUTER_Y = 13,
   SLOT_OUTER_T = 14,
-  SLOT_PC0 = 16,     // 16..19 preconditioner temporaries
-  SLOT_PSTATE = 20,
-  SLOT_POWER = 21,
-  SLOT_POWER2 = 22,
-  SLOT_STATE = 23
+  SLOT_PC0 = 16,     // 16..21 preconditioner temporaries
+  SLOT_PSTATE = 22,
+  SLOT_POWER = 23,
+  SLOT_POWER2 = 24,
+  SLOT_STATE = 25
 };
 
 template <typename R>
 C2<R>* slot_vec(Lattice& L, int slot, int nrhs, int* rc);
 
 int krylov_state(Lattice& L, int nrhs, KrylovState* K, int slot_red);
+
+// lam_max of Q (Chebyshev) or of S Q (strong coupling with the Chebyshev
+// filter, S for the SCA shift alpha): 30 power iterations, times 1.05, cached
+// per field.
+int estimate_lam_max(Lattice& L, double* out);
+int estimate_lam_max_sq(Lattice& L, double alpha, double* out);
 
 }  // namespace ufg

@@ -457,14 +457,46 @@ int bicgstab_step(Lattice& L, const PcPlan& pc, int op, const C2<RO>* b, C2<RO>*
 }
 
 // ---------------------------------------------------------------------------
-// CG on Q = M^T M with an HPD preconditioner.
+// CG on Q = M^T M with an HPD preconditioner; or, with `split` (a weak-coupling
+// plan E = W_d), CG with split preconditioning (paper, Sec. 5, the remark
+// after Table 2): CG on A' = E^T Q E with right-hand side b' = E^T b, whose
+// residual the stop rule measures, and x = E z at the end (no preconditioner,
+// no mixed precision, x_0 = 0).
 template <typename RI, typename RO>
 int cg_solve(Lattice& L, const PcPlan& pc, const C2<RO>* b, C2<RO>* x, int nrhs,
-             const ufg_solve_opts& o, Counters* cnt, StepResult* res) {
+             const ufg_solve_opts& o, Counters* cnt, StepResult* res,
+             const PcPlan* split = nullptr) {
   constexpr bool kMixed = !std::is_same<RI, RO>::value;
   const bool need_pc = pc.kind != UFG_PC_NONE;
+  if (split && (kMixed || need_pc || o.use_x0)) {
+    set_error("split-preconditioned CG: no second preconditioner, no mixed precision, x_0 = 0");
+    return UFG_EINVAL;
+  }
   Inner<RI> V;
   UFG_TRY(inner_vectors<RI>(L, nrhs, need_pc, kMixed, reinterpret_cast<C2<RI>*>(x), &V));
+  // split form: b' and two temporaries in solver slots the unpreconditioned
+  // iteration leaves free
+  C2<RI>* bsp = nullptr;
+  C2<RI>* ep = nullptr;
+  C2<RI>* qy = nullptr;
+  if (split) {
+    int src = 0;
+    bsp = slot_vec<RI>(L, SLOT_SOLVER0 + 7, nrhs, &src);
+    UFG_TRY(src);
+    ep = slot_vec<RI>(L, SLOT_SOLVER0 + 8, nrhs, &src);
+    UFG_TRY(src);
+    qy = slot_vec<RI>(L, SLOT_SOLVER0 + 9, nrhs, &src);
+    UFG_TRY(src);
+    UFG_TRY(pc_apply<RI>(L, *split, UFG_OP_MDAG, reinterpret_cast<const C2<RI>*>(b), bsp, nrhs,
+                         nullptr, cnt));
+    b = reinterpret_cast<const C2<RO>*>(bsp);
+  }
+  // w = A' v (split form) on the rhs of `gate`
+  auto split_apply = [&](const C2<RI>* v, C2<RI>* w, const int* gate) -> int {
+    UFG_TRY(pc_apply<RI>(L, *split, UFG_OP_M, v, ep, nrhs, gate, cnt));
+    UFG_TRY(q_apply<RI>(L, ep, V.tmp, qy, nrhs, gate));
+    return pc_apply<RI>(L, *split, UFG_OP_MDAG, qy, w, nrhs, gate, cnt);
+  };
   KrylovState K;
   UFG_TRY(krylov_state(L, nrhs, &K, SLOT_STATE));
   K.prm.tol = o.tol;
@@ -520,6 +552,11 @@ int cg_solve(Lattice& L, const PcPlan& pc, const C2<RO>* b, C2<RO>* x, int nrhs,
       UFG_TRY(q_residual<RO>(L, x, b, t64, r64, nrhs, K.update));
       UFG_TRY(k_demote(L, reinterpret_cast<const double2*>(r64), reinterpret_cast<float2*>(V.r),
                        nullptr, K, K.update));
+    } else if (split) {  // r' = b' - A' z
+      UFG_TRY(split_apply(V.x, V.w, K.update));
+      UFG_TRY(k_convert<RI, RI>(L, reinterpret_cast<const C2<RI>*>(b), V.r, nrhs, K.update));
+      UFG_TRY(k_axpby<RI>(L, double2{-1.0, 0.0}, V.w, double2{1.0, 0.0}, V.r, nrhs, K.update));
+      UFG_TRY(k_reduce<RI>(L, V.r, nullptr, 0, K.update, K));
     } else {
       UFG_TRY(q_residual<RI>(L, V.x, reinterpret_cast<const C2<RI>*>(b), V.tmp, V.r, nrhs,
                              K.update));
@@ -542,8 +579,14 @@ int cg_solve(Lattice& L, const PcPlan& pc, const C2<RO>* b, C2<RO>* x, int nrhs,
   bool done = false;
   UFG_TRY(read_flags(L, K, hflags.data(), &done));
   auto iteration = [&]() -> int {
-    UFG_TRY(q_apply<RI>(L, V.p, V.tmp, V.w, nrhs, K.active, 1, V.p, K.part));
-    UFG_TRY(k_finalize(L, FIN_CG_ALPHA, nhb, K.active, K));
+    if (split) {  // w = A' p and <p, w> over the vector blocks
+      UFG_TRY(split_apply(V.p, V.w, K.active));
+      UFG_TRY(k_reduce<RI>(L, V.p, V.w, 1, K.active, K));
+      UFG_TRY(k_finalize(L, FIN_CG_ALPHA, nvb, K.active, K));
+    } else {
+      UFG_TRY(q_apply<RI>(L, V.p, V.tmp, V.w, nrhs, K.active, 1, V.p, K.part));
+      UFG_TRY(k_finalize(L, FIN_CG_ALPHA, nhb, K.active, K));
+    }
     UFG_TRY(k_cg_xr<RI>(L, V.x, V.p, V.r, V.w, K));
     UFG_TRY(k_finalize(L, FIN_CG_R, nvb, K.active, K));
     cnt->mv += 2;
@@ -614,6 +657,10 @@ int cg_solve(Lattice& L, const PcPlan& pc, const C2<RO>* b, C2<RO>* x, int nrhs,
   if (kMixed) {
     UFG_TRY(k_promote(L, reinterpret_cast<double2*>(x), reinterpret_cast<float2*>(V.x), nrhs,
                       nullptr));
+  }
+  if (split) {  // x = E z (z was iterated in x's buffer)
+    UFG_TRY(pc_apply<RI>(L, *split, UFG_OP_M, V.x, ep, nrhs, nullptr, cnt));
+    UFG_TRY(k_convert<RI, RI>(L, ep, V.x, nrhs, nullptr));
   }
   std::vector<RhsState> st;
   UFG_TRY(read_states(L, K, &st));
@@ -705,7 +752,53 @@ int cg_dispatch(Lattice& L, const PcPlan& pc, const void* bv, void* xv, int nrhs
   return r1.status;
 }
 
+template <typename R>
+int cg_split_dispatch(Lattice& L, const PcPlan& E, const void* bv, void* xv, int nrhs,
+                      const ufg_solve_opts& o, ufg_solve_stats* st) {
+  Counters cnt;
+  StepResult r1;
+  PcPlan none;
+  const C2<R>* b = reinterpret_cast<const C2<R>*>(bv);
+  C2<R>* x = reinterpret_cast<C2<R>*>(xv);
+  UFG_TRY((cg_solve<R, R>(L, none, b, x, nrhs, o, &cnt, &r1, &E)));
+  double relq = 0;
+  UFG_TRY(true_relres<R>(L, UFG_OP_Q, x, b, nrhs, &relq));
+  if (st) {
+    st->iters[0] = r1.iters;
+    st->iters[1] = 0;
+    st->mv = cnt.mv;
+    st->m0inv = cnt.m0inv;
+    st->sca_sweeps = cnt.sca;
+    st->reliable_updates = r1.updates;
+    st->relres[0] = relq;
+    st->relres[1] = 0;
+    st->relres_normal = relq;
+    st->paper_mv = (double)r1.iters * (2.0 + 2.0 * E.paper_cost());
+    st->status = r1.status;
+    st->host_syncs = 0;
+    st->host_submits = 0;
+  }
+  return r1.status;
+}
+
 }  // namespace
+
+int solve_cg_split_impl(Lattice& L, const ufg_precond* p, const void* b, void* x, int nrhs,
+                        const ufg_solve_opts* o, ufg_solve_stats* st) {
+  UFG_TRY(validate_opts(L, o, nrhs));
+  UFG_CHECK(b && x && b != x, "solve_cg_split: b and x must be distinct device pointers");
+  UFG_CHECK(p && p->kind == UFG_PC_WCE, "solve_cg_split: the split factor is a weak-coupling W_d");
+  UFG_CHECK(!o->mixed && !o->use_x0, "solve_cg_split: no mixed precision, x_0 = 0");
+  PcPlan E;
+  UFG_TRY(resolve_precond(L, p, &E));
+  const auto t0 = std::chrono::steady_clock::now();
+  const int rc = (L.dtype == UFG_C128) ? cg_split_dispatch<double>(L, E, b, x, nrhs, *o, st)
+                                       : cg_split_dispatch<float>(L, E, b, x, nrhs, *o, st);
+  if (rc < 0) return rc;
+  UFG_HIP(hipStreamSynchronize(L.stream));
+  if (st) st->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+  return rc;
+}
 
 int solve_bicgstab_impl(Lattice& L, const ufg_precond* p, int op, const void* b, void* x,
                         int nrhs, const ufg_solve_opts* o, ufg_solve_stats* st) {

@@ -103,13 +103,16 @@ struct Lattice {
   int vec_blocks = 0;              // workgroups per rhs of the vector kernels (0: default)
   int xcd_group = -1;              // slab groups per XCD of the streaming kernels (-1: default)
   int xcd_rhs_inner = 0;           // 1: an XCD takes every rhs of a slab group in turn
-  DevBuf work[24];          // vector workspaces (solver / preconditioner)
+  DevBuf work[26];          // vector workspaces (solver / preconditioner)
   DevBuf red;               // reduction partials
   DevBuf state;             // solver state
   DevBuf cheb;              // Chebyshev roots on device
   FlagMirror flags;         // check-point flags read one interval late
   double lam_max_cache = -1.0;
   int lam_max_valid = 0;
+  double lam_max_sq_cache = -1.0;  // lam_max of S Q, for the SCA shift below
+  double lam_max_sq_alpha = 0.0;
+  int lam_max_sq_valid = 0;
 };
 
 template <typename R>

@@ -160,6 +160,20 @@ class Lattice:
         L.check(code, "solve_cg_normal")
         return x, st.as_dict()
 
+    def solve_cg_split(self, b, precond: Precond, tol=1e-10, maxit=10000, check_every=10,
+                       graph=True):
+        """CG with split preconditioning E^T Q E z = E^T b, x = E z, E = W_d of
+        the weak-coupling `precond` (C ABI solve_cg_split)."""
+        n = self._vec(b, "b")
+        x = torch.empty_like(b)
+        o = L.solve_opts(tol, maxit, False, 0.1, check_every, False, not graph)
+        st = L.ufg_solve_stats()
+        p = precond.to_c()
+        code = self._lib.solve_cg_split(self._h, C.byref(p), C.c_void_p(b.data_ptr()),
+                                        C.c_void_p(x.data_ptr()), n, C.byref(o), C.byref(st))
+        L.check(code, "solve_cg_split")
+        return x, st.as_dict()
+
     def solve_bicgstab(self, b, op="two_step", precond: Precond | None = None, tol=1e-10,
                        maxit=10000, mixed=False, delta=0.1, check_every=10, x0=None,
                        graph=True):

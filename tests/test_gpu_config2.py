@@ -26,7 +26,9 @@ TOL = 1e-10
 CG_CELLS = [("none", {}), ("cheb", dict(degree=8, eps=1e-2, lam_max=-1.0)),
             ("cheb", dict(degree=16, eps=3e-3, lam_max=-1.0)),
             ("cheb", dict(degree=32, eps=1e-3, lam_max=-1.0)),
-            ("sca", dict(alpha=2.0)), ("wce", dict(wce_order=1))]
+            ("sca", dict(alpha=2.0)), ("wce", dict(wce_order=1)),
+            ("sca_cheb", dict(degree=8, eps=1e-2, lam_max=-1.0, alpha=2.0)),
+            ("sca_cheb", dict(degree=16, eps=3e-3, lam_max=-1.0, alpha=2.0))]
 BICG_CELLS = [("none", {}), ("wce", dict(wce_order=0)), ("wce", dict(wce_order=1)),
               ("wce", dict(wce_order=2)), ("wce", dict(wce_order=2, euler=True)),
               ("wce", dict(wce_order=4)), ("wce", dict(wce_order=4, euler=True)),
@@ -83,3 +85,19 @@ def test_bicgstab_cell(setup, kind, kw):
         f"paper_mv {st['paper_mv']} {st['seconds']:.3f}s relres {st['relres']}")
     assert st["status"] == 0 and max(st["relres"]) <= TOL
     _check_solution(to_host(x), b, sigma, ref, True)
+
+
+@pytest.mark.parametrize("order", [0, 1])
+def test_split_cg_cell(setup, order):
+    """CG with split preconditioning (Sec. 5 after Table 2: W_d^T on the left,
+    W_d on the right; order 0 is the paper's M0^{-1}): converges to the oracle's
+    solution. Its stop rule is the split system's residual, so the original
+    residual is bounded by cond(W_d^T) times tol; the forward error against the
+    oracle reference is the pass criterion (<= 1e-6), as for the other cells."""
+    from paper_1008_3647_amd import Precond
+    L, sigma, b, bd, ref = setup
+    x, st = L.solve_cg_split(bd, Precond("wce", wce_order=order), tol=TOL, maxit=20000)
+    say(f"CG split W{order}: iters {st['iters'][0]} mv {st['mv']} m0inv {st['m0inv']} "
+        f"paper_mv {st['paper_mv']} {st['seconds']:.3f}s relres {st['relres'][0]:.2e}")
+    assert st["status"] == 0
+    _check_solution(to_host(x), b, sigma, ref, False)

@@ -198,3 +198,53 @@ def test_power_iteration_lam_max_against_dense_spectrum(nx, ntau):
     y = to_host(L.apply_precond(xd, p, "Q"))
     ref = pc.apply_cheb(x[0], sigma, TAU, G, 32, 1e-3, est)[None]
     assert rel_err(y, ref) < 2e-12
+
+
+@pytest.mark.parametrize("dtype", [torch.complex128, torch.complex64])
+@pytest.mark.parametrize("nx,ntau,nrhs", [(4, 12, 2), (8, 20, 1), (16, 5, 2)])
+def test_sca_chebyshev_filter(nx, ntau, nrhs, dtype):
+    """SCA with the Chebyshev filter (Sec. 4, closing remark): P_2n(S Q /
+    lam_max) S element-wise against the oracle, for Q and (complex128) the
+    BiCGStab extensions P M^T and M P; tolerance as for degree 8 Chebyshev
+    (the SCA sweeps are first-order recurrences like those of M0^{-1})."""
+    require_gpu()
+    from paper_1008_3647_amd import Precond
+    say(f"sca+cheb nx={nx} ntau={ntau} {dtype}")
+    L, sigma, x, xd = _setup(nx, ntau, nrhs, dtype, 760)
+    lam_max, eps, alpha = 3.0, 1e-2, 1.5
+    p = Precond("sca_cheb", degree=8, eps=eps, lam_max=lam_max, alpha=alpha)
+    tol = TOL[dtype] * (10 if dtype == torch.complex64 else 1)
+    y = to_host(L.apply_precond(xd, p, "Q"))
+    ref = np.stack([pc.apply_sca_cheb(xi, sigma, TAU, G, 8, eps, lam_max, alpha) for xi in x])
+    assert rel_err(y, ref) < tol
+    if dtype == torch.complex128:
+        yM = to_host(L.apply_precond(xd, p, "M"))
+        refM = np.stack([pc.apply_sca_cheb(oracle.apply_Mdag(xi, sigma, TAU, G), sigma, TAU, G,
+                                           8, eps, lam_max, alpha) for xi in x])
+        assert rel_err(yM, refM) < tol
+
+
+def test_sca_chebyshev_lam_max_against_dense_spectrum():
+    """lam_max < 0 estimates the largest eigenvalue of S Q by power iteration:
+    lam_true <= estimate <= 1.05 lam_true, lam_true from the dense Hermitian
+    S^{1/2} Q S^{1/2}."""
+    require_gpu()
+    from paper_1008_3647_amd import Precond
+    from oracle import operator as op
+    nx, ntau, alpha = 2, 8, 1.5
+    L, sigma, x, xd = _setup(nx, ntau, 1, torch.complex128, 770)
+    V, N = nx ** 3, nx ** 3 * ntau
+    D, Lb = pc.sca_setup(sigma, TAU, G, alpha)
+    S = np.zeros((N, N))
+    for n in range(V):
+        iz, iy, ix = np.unravel_index(n, (nx, nx, nx))
+        Ld, Dd = pc.sca_dense_factors(D[:, iz, iy, ix], Lb[:, iz, iy, ix])
+        idx = np.arange(ntau) * V + n
+        S[np.ix_(idx, idx)] = np.linalg.inv(Ld @ Dd @ Ld.T)
+    w, U = np.linalg.eigh(S)
+    Sh = (U * np.sqrt(w)) @ U.T
+    Md = op.dense_M(sigma, TAU, G)
+    lam_true = np.linalg.eigvalsh(Sh @ (Md.T @ Md) @ Sh)[-1]
+    est = L.lam_max(Precond("sca_cheb", degree=8, eps=1e-2, lam_max=-1.0, alpha=alpha))
+    say(f"S Q: lam_max dense {lam_true:.6f}, power iteration x 1.05 {est:.6f}")
+    assert lam_true <= est <= 1.05 * lam_true * (1 + 1e-12)
