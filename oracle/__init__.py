@@ -18,6 +18,7 @@ Modules
              strong coupling (Sec. 4)
   solvers  : CG on the normal equations, two-step BiCGStab        (Sec. 1, Eqs. 1-3)
   force    : pseudofermion action, force, leapfrog MD             (Sec. 1)
+  hmc      : heat bath, HMC trajectory, Metropolis step           (Sec. 1)
   costmodel: the paper's matrix-vector cost model                 (Sec. 5)
 
 Parity status: every function is pinned by a test in tests/test_oracle_*.py
@@ -30,4 +31,4 @@ from .operator import (  # noqa: F401
     dense_M, dense_M1, dense_expK,
 )
 from .freefield import apply_M0inv, apply_M0inv_dag, free_spectrum  # noqa: F401
-from . import precond, solvers, force, costmodel  # noqa: F401
+from . import precond, solvers, force, hmc, costmodel  # noqa: F401

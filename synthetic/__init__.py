@@ -21,6 +21,7 @@ __all__ = [
     "sigma_field",
     "gaussian_rhs",
     "gaussian_momenta",
+    "uniform_draws",
     "batched_problem_shapes",
     "sample_sites",
     "WORKLOADS",
@@ -53,6 +54,12 @@ def gaussian_momenta(nx: int, ntau: int, seed: int) -> np.ndarray:
     """MD momenta pi ~ N(0, 1) per site (paper, Sec. 1, MD Hamiltonian)."""
     rng = np.random.default_rng(seed)
     return rng.standard_normal((ntau, nx, nx, nx))
+
+
+def uniform_draws(seed: int, count: int) -> np.ndarray:
+    """Metropolis draws u, iid uniform on [0, 1) (paper, Sec. 1, accept/reject)."""
+    rng = np.random.default_rng(seed)
+    return rng.random(count)
 
 
 def batched_problem_shapes(count: int = 64, seed: int = 4000):
@@ -88,7 +95,7 @@ WORKLOADS = {
     "batched_64": dict(count=64, shape_seed=4000, sigma_seed0=4001, rhs_seed0=4101, nrhs=2),
     # force / molecular dynamics at Nx=12, Ntau=200
     "lattice_12x200": dict(nx=12, ntau=200, sigma_seed=5001, eta_seed=5002,
-                           site_seed=5003, momentum_seed=5004),
+                           site_seed=5003, momentum_seed=5004, metropolis_seed=5005),
 }
 TAU = 0.05
 G_COUPLING = 5.0
