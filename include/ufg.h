@@ -270,6 +270,82 @@ int force_dS_dsigma(ufg_lattice L, const void* X, const void* y, int nrhs,
                     double* grad_dev);
 
 /*
+ * HMC of the phi-algorithm (paper, Sec. 1). The MD Hamiltonian is
+ *   H = sum_{n,t} pi(n,t)^2 / 2 + S_p[sigma],  S_p = sum_r phi_r^dagger Q^{-1} phi_r,
+ * Q = M^dagger M, with phi held fixed during the molecular dynamics. Every
+ * force evaluation installs sigma (as set_aux_field), solves M^dagger y = phi
+ * and M X = y with BiCGStab (precond, tol, maxit, mixed as in solve_bicgstab),
+ * takes S_p = sum_r ||y_r||^2 (FP64) and the gradient of force_dS_dsigma.
+ * The integrator is leapfrog, kick-drift-kick with half kicks at both ends:
+ *   pi -= dt/2 g(sigma); nsteps times { sigma += dt pi; pi -= dt g(sigma) },
+ *   the last kick being dt/2 (nsteps + 1 force evaluations);
+ *   pi_dot = -dS_p/dsigma.
+ * The field updates and sum pi^2 run in library kernels (FP64, fixed
+ * summation order); nothing is drawn at random inside the library: eta, pi
+ * and the Metropolis draw u are inputs.
+ *
+ *   dt          step size (finite, > 0).  nsteps  leapfrog steps (1..1e6).
+ *   tol, maxit, mixed, check_every, precond:  every solve (check_every >= 1).
+ *   chrono      1: every solve starts from the previous force's solution (the
+ *               first y of hmc_trajectory from eta, which solves M^dagger y =
+ *               phi exactly); 0: every solve starts from x = 0.
+ */
+typedef struct {
+  double dt;
+  int nsteps;
+  double tol;
+  int maxit;
+  int mixed;
+  int check_every;
+  int chrono;
+} ufg_hmc_opts;
+
+typedef struct {
+  double S0, S1;        /* S_p at the start / at the MD end point             */
+  double K0, K1;        /* sum pi^2 / 2 at the start / at the MD end point    */
+  double dH;            /* (K1 - K0) + (S1 - S0)                              */
+  int accept;           /* hmc_trajectory: Metropolis decision; leapfrog: -1  */
+  int status;           /* 0, else the status (1, 2) of the first failed solve */
+  int forces;           /* force evaluations done                             */
+  long long solves;     /* BiCGStab solves                                    */
+  long long iters;      /* iterations summed over the solves (worst rhs)      */
+  long long mv;         /* applications of M or M^dagger                      */
+  double worst_relres;  /* largest true relative residual of any solve        */
+  double seconds;       /* wall time of the call                              */
+} ufg_hmc_result;
+
+/*
+ * hmc_leapfrog -- the MD part alone: integrates (sigma, pi) in place from the
+ *   given state for phi fixed.
+ *   sigma_dev, pi_dev: device float64 [Ntau][Nx]^3, distinct; overwritten with
+ *   the MD end point (with the start again if a solve fails: then
+ *   res->status > 0). phi_dev: device, lattice dtype, nphi vectors (complex128
+ *   when mixed). actions_host: NULL or host array of nsteps + 1 doubles, S_p
+ *   at every force evaluation. res: required; accept = -1. On return the
+ *   installed field is sigma_dev's. Synchronous. A negative return leaves
+ *   sigma and pi unspecified.
+ */
+int hmc_leapfrog(ufg_lattice L, const ufg_precond* precond, double* sigma_dev, double* pi_dev,
+                 const void* phi_dev, int nphi, const ufg_hmc_opts* o, double* actions_host,
+                 ufg_hmc_result* res);
+
+/*
+ * hmc_trajectory -- one trajectory of the phi-algorithm: heat bath
+ *   phi_r = M^dagger eta_r at the starting sigma (eta_r ~ exp(-eta^dagger eta),
+ *   so that phi ~ exp(-phi^dagger Q^{-1} phi)), the MD of hmc_leapfrog, then the
+ *   Metropolis step: accept iff u < exp(-dH) (probability min(1, exp(-dH))),
+ *   decided in FP64 on the host.
+ *   sigma_dev, pi_dev: device float64, distinct; on accept they hold the MD end
+ *   point, on reject (or a failed solve) the start, and the installed field
+ *   is the one they hold. eta_dev: device, lattice dtype, nphi vectors.
+ *   u: Metropolis draw in [0, 1). phi_out: NULL or device buffer like eta
+ *   that receives phi. actions_host, res: as hmc_leapfrog. Synchronous.
+ */
+int hmc_trajectory(ufg_lattice L, const ufg_precond* precond, double* sigma_dev, double* pi_dev,
+                   const void* eta_dev, int nphi, double u, const ufg_hmc_opts* o,
+                   void* phi_out, double* actions_host, ufg_hmc_result* res);
+
+/*
  * lattice_norm2 -- out_host[r] = ||x_r||^2 for nrhs vectors of the lattice dtype
  *   (FP64 accumulation, fixed summation order). The pseudofermion action of
  *   Sec. 1 is S = ||y||^2 with M^dagger y = phi. out_host: host array of nrhs

@@ -48,6 +48,23 @@ class ufg_solve_stats(C.Structure):
                     host_syncs=self.host_syncs, host_submits=self.host_submits)
 
 
+class ufg_hmc_opts(C.Structure):
+    _fields_ = [("dt", C.c_double), ("nsteps", C.c_int), ("tol", C.c_double),
+                ("maxit", C.c_int), ("mixed", C.c_int), ("check_every", C.c_int),
+                ("chrono", C.c_int)]
+
+
+class ufg_hmc_result(C.Structure):
+    _fields_ = [("S0", C.c_double), ("S1", C.c_double), ("K0", C.c_double),
+                ("K1", C.c_double), ("dH", C.c_double), ("accept", C.c_int),
+                ("status", C.c_int), ("forces", C.c_int), ("solves", C.c_longlong),
+                ("iters", C.c_longlong), ("mv", C.c_longlong), ("worst_relres", C.c_double),
+                ("seconds", C.c_double)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
 _P = C.c_void_p
 _SIGNATURES = {
     "create_lattice": (C.c_int, [C.c_int, C.c_int, C.c_double, C.c_double, C.c_int, _P,
@@ -73,6 +90,12 @@ _SIGNATURES = {
     "lattice_tune_slabs": (C.c_int, [_P, C.c_int]),
     "lattice_tune_order": (C.c_int, [_P, C.c_int, C.c_int]),
     "precond_lam_max": (C.c_int, [_P, C.POINTER(ufg_precond), C.POINTER(C.c_double)]),
+    "hmc_leapfrog": (C.c_int, [_P, C.POINTER(ufg_precond), _P, _P, _P, C.c_int,
+                               C.POINTER(ufg_hmc_opts), C.POINTER(C.c_double),
+                               C.POINTER(ufg_hmc_result)]),
+    "hmc_trajectory": (C.c_int, [_P, C.POINTER(ufg_precond), _P, _P, _P, C.c_int, C.c_double,
+                                 C.POINTER(ufg_hmc_opts), _P, C.POINTER(C.c_double),
+                                 C.POINTER(ufg_hmc_result)]),
     "lattice_norm2": (C.c_int, [_P, _P, C.c_int, C.POINTER(C.c_double)]),
     "lattice_norm2_noalloc": (C.c_int, [_P, _P, C.c_int, _P]),
     "ufg_device_copy": (C.c_int, [_P, _P, C.c_longlong, _P]),

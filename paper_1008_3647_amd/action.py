@@ -8,8 +8,8 @@ solve; then X = Q^{-1} phi and y = M X) and calls the library's force
 contraction
     dS/dsigma(n,t) = -2 A cos sigma(n,t) s_t sum_r Re[X_t(n) conj((e^{-tau K} y_{t+1})(n))].
 `leapfrog` integrates sigma_dot = pi, pi_dot = -dS/dsigma with a reversible
-symplectic leapfrog; its O(N) field updates are torch elementwise operations,
-every solve and force runs in libufg.
+symplectic leapfrog (libufg hmc_leapfrog); `Lattice.hmc_trajectory` adds the
+heat bath and the Metropolis step.
 """
 from __future__ import annotations
 
@@ -63,19 +63,15 @@ def heat_bath_phi(lattice: Lattice, eta):
 
 
 def leapfrog(sigma, pi, phi, lattice: Lattice, dt, nsteps, precond=None, tol=1e-11,
-             mixed=False):
-    """Leapfrog MD trajectory; returns (sigma, pi, list of S at every force)."""
-    sigma = sigma.detach().clone()
-    pi = pi.detach().clone()
-    S, g = force(sigma, phi, lattice, precond, tol, mixed)
-    actions = [S]
-    pi.sub_(g, alpha=0.5 * dt)
-    for step in range(nsteps):
-        sigma.add_(pi, alpha=dt)
-        S, g = force(sigma, phi, lattice, precond, tol, mixed)
-        actions.append(S)
-        pi.sub_(g, alpha=dt if step != nsteps - 1 else 0.5 * dt)
-    return sigma, pi, actions
+             mixed=False, chrono=True):
+    """Leapfrog MD trajectory (libufg hmc_leapfrog: every solve, force and
+    field update in the library); returns (sigma, pi, list of S at every force)."""
+    s, p, actions, res = lattice.hmc_leapfrog(sigma.contiguous(), pi.contiguous(), phi, dt,
+                                              nsteps, precond, tol=tol, mixed=mixed,
+                                              chrono=chrono)
+    if res["status"] != 0:
+        raise RuntimeError(f"a solve of the MD trajectory did not converge: {res}")
+    return s, p, actions
 
 
 def hamiltonian(pi, S):

@@ -16,7 +16,8 @@ CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libufg.so")
 SOURCES = ["api.cpp", "ops.cpp", "solvers.cpp", "split.cpp", "batched.hip", "hop.hip",
-           "hop_stream.hip", "temporal.hip", "krylov.hip", "noalloc.hip"]
+           "hop_stream.hip", "temporal.hip", "krylov.hip", "noalloc.hip",
+           "hmc.hip"]
 ARCH = "gfx950"
 
 

@@ -151,7 +151,7 @@ static int upload(hipStream_t s, T* dst, const std::vector<double>& src) {
   return UFG_OK;
 }
 
-static int install_field(Lattice& L) {
+int install_field(Lattice& L) {
   const int nblk = 512;
   int rc = L.red.ensure(nblk * sizeof(double));
   if (rc) return rc;
@@ -167,6 +167,22 @@ static int install_field(Lattice& L) {
   UFG_HIP(hipStreamSynchronize(L.stream));
   L.lam_max_valid = 0;
   L.lam_max_sq_valid = 0;
+  return UFG_OK;
+}
+
+int norm2_host(Lattice& L, const void* x, int nrhs, double* out_host) {
+  KrylovState K;
+  UFG_TRY(krylov_state(L, nrhs, &K, SLOT_PSTATE));
+  if (L.dtype == UFG_C128)
+    UFG_TRY(k_reduce<double>(L, (const double2*)x, nullptr, 0, nullptr, K));
+  else
+    UFG_TRY(k_reduce<float>(L, (const float2*)x, nullptr, 0, nullptr, K));
+  UFG_TRY(k_finalize(L, FIN_NORM, vec_blocks(L, nrhs), nullptr, K));
+  std::vector<RhsState> st(nrhs);
+  UFG_HIP(hipMemcpyAsync(st.data(), K.st, sizeof(RhsState) * nrhs, hipMemcpyDeviceToHost,
+                         L.stream));
+  UFG_HIP(hipStreamSynchronize(L.stream));
+  for (int i = 0; i < nrhs; ++i) out_host[i] = st[i].r2;
   return UFG_OK;
 }
 
@@ -368,19 +384,7 @@ int lattice_norm2(ufg_lattice h, const void* x, int nrhs, double* out_host) {
   Lattice* L = check_handle(h);
   UFG_CHECK(L != nullptr, "lattice_norm2: NULL handle");
   UFG_CHECK(x && out_host && nrhs >= 1, "lattice_norm2: bad pointers or nrhs");
-  KrylovState K;
-  UFG_TRY(krylov_state(*L, nrhs, &K, SLOT_PSTATE));
-  if (L->dtype == UFG_C128)
-    UFG_TRY(k_reduce<double>(*L, (const double2*)x, nullptr, 0, nullptr, K));
-  else
-    UFG_TRY(k_reduce<float>(*L, (const float2*)x, nullptr, 0, nullptr, K));
-  UFG_TRY(k_finalize(*L, FIN_NORM, vec_blocks(*L, nrhs), nullptr, K));
-  std::vector<RhsState> st(nrhs);
-  UFG_HIP(hipMemcpyAsync(st.data(), K.st, sizeof(RhsState) * nrhs, hipMemcpyDeviceToHost,
-                         L->stream));
-  UFG_HIP(hipStreamSynchronize(L->stream));
-  for (int i = 0; i < nrhs; ++i) out_host[i] = st[i].r2;
-  return UFG_OK;
+  return norm2_host(*L, x, nrhs, out_host);
 }
 
 int lattice_tune(ufg_lattice h, int slab, int vec_blocks) {

@@ -104,6 +104,7 @@ struct Lattice {
   int xcd_group = -1;              // slab groups per XCD of the streaming kernels (-1: default)
   int xcd_rhs_inner = 0;           // 1: an XCD takes every rhs of a slab group in turn
   DevBuf work[26];          // vector workspaces (solver / preconditioner)
+  DevBuf hmc[7];            // HMC trajectory: sigma0, pi0, grad, phi, y, X, partials
   DevBuf red;               // reduction partials
   DevBuf state;             // solver state
   DevBuf cheb;              // Chebyshev roots on device
@@ -213,6 +214,15 @@ int launch_m0_temporal(const Lattice& L, const C2<R>* v, C2<R>* u, int nrhs, boo
 
 // Field setup: b, sin, cos from sigma in both precisions; per-block max |b| into bmax_part.
 int launch_field_setup(Lattice& L, double* bmax_part, int nblk);
+
+// Everything derived from L.sigma (both precisions, max |b|, SCA blocks);
+// synchronizes the lattice stream.
+int install_field(Lattice& L);
+// out_host[r] = ||x_r||^2 (FP64, fixed order) for nrhs vectors of the lattice
+// dtype; synchronous.
+int norm2_host(Lattice& L, const void* x, int nrhs, double* out_host);
+int solve_bicgstab_impl(Lattice& L, const ufg_precond* p, int op, const void* b, void* x,
+                        int nrhs, const ufg_solve_opts* o, ufg_solve_stats* st);
 
 
 }  // namespace ufg

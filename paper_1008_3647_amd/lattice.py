@@ -200,6 +200,75 @@ class Lattice:
         L.check(self._lib.lattice_tune_order(self._h, int(xcd_group), int(bool(rhs_inner))),
                 "lattice_tune_order")
 
+    def _real_field(self, t, name):
+        if not isinstance(t, torch.Tensor) or t.device.type != "cuda":
+            raise TypeError(f"{name} must be a float64 CUDA tensor")
+        if t.dtype != torch.float64:
+            raise TypeError(f"{name} must have dtype torch.float64, got {t.dtype}")
+        if tuple(t.shape) != self.shape or not t.is_contiguous():
+            raise ValueError(f"{name} must be contiguous with shape {self.shape}")
+        return t
+
+    def _hmc_args(self, sigma, pi, vec, name, dt, nsteps, tol, maxit, mixed, check_every,
+                  chrono):
+        self._real_field(sigma, "sigma")
+        self._real_field(pi, "pi")
+        if pi.device != sigma.device:
+            raise TypeError("sigma and pi must be on one device")
+        n = self._vec(vec, name, self._solve_dtype(mixed))
+        if vec.device != sigma.device:
+            raise TypeError(f"{name} must be on {sigma.device}")
+        s = sigma.detach().clone()
+        p = pi.detach().clone()
+        o = L.ufg_hmc_opts(float(dt), int(nsteps), float(tol), int(maxit), int(bool(mixed)),
+                           int(check_every), int(bool(chrono)))
+        return n, s, p, o
+
+    def hmc_leapfrog(self, sigma, pi, phi, dt, nsteps, precond: Precond | None = None,
+                     tol=1e-11, maxit=10000, mixed=False, check_every=10, chrono=True):
+        """Leapfrog MD of the phi-algorithm from (sigma, pi) with phi fixed
+        (C ABI hmc_leapfrog). Returns new (sigma, pi) tensors, the action at
+        every force evaluation and the result record."""
+        n, s, p, o = self._hmc_args(sigma, pi, phi, "phi", dt, nsteps, tol, maxit, mixed,
+                                    check_every, chrono)
+        acts = (C.c_double * (int(nsteps) + 1))()
+        res = L.ufg_hmc_result()
+        pc = precond.to_c() if precond else None
+        code = self._lib.hmc_leapfrog(self._h, C.byref(pc) if pc else None,
+                                      C.c_void_p(s.data_ptr()), C.c_void_p(p.data_ptr()),
+                                      C.c_void_p(phi.data_ptr()), n, C.byref(o), acts,
+                                      C.byref(res))
+        L.check(code, "hmc_leapfrog")
+        self._sigma = s
+        return s, p, list(acts), res.as_dict()
+
+    def hmc_trajectory(self, sigma, pi, eta, u, dt, nsteps, precond: Precond | None = None,
+                       tol=1e-11, maxit=10000, mixed=False, check_every=10, chrono=True,
+                       want_phi=False):
+        """One phi-algorithm trajectory (C ABI hmc_trajectory): heat bath
+        phi = M^dagger eta at sigma, leapfrog, Metropolis with the draw u.
+        Returns (sigma, pi, info): the chain's next state (MD end point if
+        accepted, else the start) and the result record plus 'actions' (and
+        'phi' when want_phi)."""
+        n, s, p, o = self._hmc_args(sigma, pi, eta, "eta", dt, nsteps, tol, maxit, mixed,
+                                    check_every, chrono)
+        phi = torch.empty_like(eta) if want_phi else None
+        acts = (C.c_double * (int(nsteps) + 1))()
+        res = L.ufg_hmc_result()
+        pc = precond.to_c() if precond else None
+        code = self._lib.hmc_trajectory(self._h, C.byref(pc) if pc else None,
+                                        C.c_void_p(s.data_ptr()), C.c_void_p(p.data_ptr()),
+                                        C.c_void_p(eta.data_ptr()), n, float(u), C.byref(o),
+                                        C.c_void_p(phi.data_ptr()) if phi is not None else None,
+                                        acts, C.byref(res))
+        L.check(code, "hmc_trajectory")
+        self._sigma = s
+        info = res.as_dict()
+        info["actions"] = list(acts)
+        if phi is not None:
+            info["phi"] = phi
+        return s, p, info
+
     def norm2(self, x):
         """||x_r||^2 per right-hand side (host list), FP64 accumulation."""
         n = self._vec(x, "x")
