@@ -57,8 +57,9 @@ def parse():
 
 def mv_only(a):
     """apply_M launches alone (the counter runs), cycling through 6 (x, y) pairs
-    as the bench's HBM figure does, plus a plain copy of known size that
-    calibrates FETCH_SIZE / WRITE_SIZE."""
+    as the bench's HBM figure does, plus the library's streaming copy of one
+    operand vector over the same buffers, which calibrates FETCH_SIZE /
+    WRITE_SIZE and gives the copy ceiling."""
     import torch
     from synthetic import sigma_field, gaussian_rhs, WORKLOADS
     from paper_1008_3647_amd import Lattice
@@ -73,8 +74,6 @@ def mv_only(a):
     ROT = 6
     xs = [x0.clone() for _ in range(ROT)]
     ys = [torch.empty_like(x0) for _ in range(ROT)]
-    src = torch.ones(64 << 20, dtype=torch.float32, device="cuda")  # 256 MiB
-    dst = torch.empty_like(src)
     # warm-up: every buffer pair, then launches for `mv_warmup_ms` of wall time
     # so that the timed launches run at the clocks of a busy device
     for i in range(2 * ROT):
@@ -87,8 +86,7 @@ def mv_only(a):
             L.apply_M(xs[i % ROT], ys[i % ROT])
             i += 1
         torch.cuda.synchronize()
-    dst.copy_(src)
-    torch.cuda.synchronize()
+    from paper_1008_3647_amd.lattice import device_copy
     e0 = torch.cuda.Event(enable_timing=True)
     e1 = torch.cuda.Event(enable_timing=True)
     e0.record()
@@ -98,14 +96,20 @@ def mv_only(a):
     torch.cuda.synchronize()
     ms = e0.elapsed_time(e1) / a.mv_launches
     alg = N * (x0.shape[0] * 16 + 4)
+    # copy ceiling: the library's streaming copy of one operand vector (read +
+    # write, the same bytes as x and y of one launch) over the same buffers
+    for i in range(2 * ROT):
+        device_copy(xs[i % ROT], ys[i % ROT])
     e0.record()
-    dst.copy_(src)
+    for i in range(a.mv_launches):
+        device_copy(xs[i % ROT], ys[i % ROT])
     e1.record()
     torch.cuda.synchronize()
-    cms = e0.elapsed_time(e1)
+    cms = e0.elapsed_time(e1) / a.mv_launches
+    cbytes = 2 * xs[0].nbytes
     print(json.dumps(dict(mode="mv-only", apply_M_us=ms * 1e3, apply_M_GBs=alg / ms / 1e6,
-                          alg_bytes=alg, copy_bytes=2 * src.numel() * 4,
-                          copy_GBs=2 * src.numel() * 4 / cms / 1e6,
+                          alg_bytes=alg, copy_bytes=cbytes, copy_us=cms * 1e3,
+                          copy_GBs=cbytes / cms / 1e6,
                           hop_source_sha256_16=hop_source_hash())), flush=True)
     return 0
 
@@ -395,7 +399,7 @@ def report_force(a):
     import torch
     from synthetic import sigma_field, gaussian_rhs, gaussian_momenta, WORKLOADS
     from paper_1008_3647_amd import Lattice, Precond
-    from paper_1008_3647_amd.action import force, heat_bath_phi, leapfrog, hamiltonian
+    from paper_1008_3647_amd.action import force, heat_bath_phi
     w = WORKLOADS["lattice_12x200"]
     nx, ntau = w["nx"], w["ntau"]
     sigma = torch.from_numpy(sigma_field(nx, ntau, w["sigma_seed"])).cuda()
@@ -418,10 +422,9 @@ def report_force(a):
     pi0 = torch.from_numpy(gaussian_momenta(nx, ntau, w["momentum_seed"])).cuda()
     pcl = Precond("wce", wce_order=2, euler=True)
     dt = 0.0025
-    (traj, secs) = _timed(lambda: leapfrog(sigma, pi0, phi, L, dt, 20, pcl, tol=1e-13))
-    s1, p1, S1 = traj
-    dH = hamiltonian(p1, S1[-1]) - hamiltonian(pi0, S1[0])
-    s2, p2, S2 = leapfrog(s1, -p1, phi, L, dt, 20, pcl, tol=1e-13)
+    (traj, secs) = _timed(lambda: L.hmc_leapfrog(sigma, pi0, phi, dt, 20, pcl, tol=1e-13))
+    s1, p1, S1, res1 = traj
+    s2, p2, S2, _ = L.hmc_leapfrog(s1, -p1, phi, dt, 20, pcl, tol=1e-13)
     rev = float((s2 - sigma).abs().max().item())
     print(f"12^3 x 200 lattice, one pseudofermion, WCE2-preconditioned BiCGStab, tol 1e-12.\n")
     print("| force (two solves + contraction) | time per force | error vs oracle gradient (64 sites) |")
@@ -429,8 +432,38 @@ def report_force(a):
     for mixed, t, err, S in rows:
         print(f"| {'complex64-refined' if mixed else 'complex128'} | {t * 1e3:.1f} ms | {err:.1e} |")
     print(f"\n20 leapfrog steps, dt = {dt} (WCE2 + Euler, tol 1e-13): {secs:.2f} s, "
-          f"dH = {dH:.3e}, reversibility max|sigma - sigma0| = {rev:.1e}")
+          f"dH = {res1['dH']:.3e}, reversibility max|sigma - sigma0| = {rev:.1e}")
+    report_hmc_chain(L, w, sigma, pcl)
     return 0
+
+
+def report_hmc_chain(L, w, sigma, pc, ntraj=6, dt=0.0025, nsteps=20):
+    """A Markov chain of phi-algorithm trajectories (hmc_trajectory: heat bath,
+    leapfrog, Metropolis) on the workload lattice; every random number is a
+    seeded input (momenta and eta seeds offset by 100 k per trajectory)."""
+    import torch
+    from synthetic import gaussian_rhs, gaussian_momenta, uniform_draws
+    nx, ntau = w["nx"], w["ntau"]
+    us = uniform_draws(w["metropolis_seed"], ntraj)
+    print(f"\nHMC chain, {ntraj} trajectories of {nsteps} leapfrog steps, dt = {dt} "
+          "(hmc_trajectory, WCE2 + Euler BiCGStab, tol 1e-12, chronological starting vectors):\n")
+    print("| trajectory | dH | u | exp(-dH) | accept | solves | iterations | seconds |")
+    print("|---|---|---|---|---|---|---|---|")
+    s = sigma
+    acc, total = 0, 0.0
+    for k in range(ntraj):
+        pi = torch.from_numpy(gaussian_momenta(nx, ntau, w["momentum_seed"] + 100 * k)).cuda()
+        eta = torch.from_numpy(gaussian_rhs(nx, ntau, [w["eta_seed"] + 100 * k])).cuda()
+        s, _, info = L.hmc_trajectory(s, pi, eta, float(us[k]), dt, nsteps, pc, tol=1e-12)
+        if info["status"] != 0:
+            print(f"| {k} | solve status {info['status']} | | | | | | |")
+            continue
+        acc += info["accept"]
+        total += info["seconds"]
+        print(f"| {k} | {info['dH']:+.4e} | {us[k]:.4f} | {np.exp(-info['dH']):.4f} | "
+              f"{'yes' if info['accept'] else 'no'} | {info['solves']} | {info['iters']} | "
+              f"{info['seconds']:.3f} |")
+    print(f"\nacceptance {acc}/{ntraj}, {total / ntraj:.3f} s per trajectory")
 
 
 def report_mv_sweep(a):
