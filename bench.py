@@ -46,7 +46,8 @@ def parse():
     ap.add_argument("--no-tune", action="store_true",
                     help="skip the launch-shape autotuner (run before the timed region)")
     ap.add_argument("--report",
-                    choices=["config2", "batched", "batched_solve", "force", "mv_sweep"],
+                    choices=["config2", "batched", "batched_solve", "force", "mv_sweep",
+                             "tables"],
                     help="print the measurement table of another workload (markdown) "
                          "instead of the JSON line")
     ap.add_argument("--mv-only", action="store_true",
@@ -466,6 +467,146 @@ def report_hmc_chain(L, w, sigma, pc, ntraj=6, dt=0.0025, nsteps=20):
     print(f"\nacceptance {acc}/{ntraj}, {total / ntraj:.3f} s per trajectory")
 
 
+def _read_paper_csv(name):
+    rows = []
+    with open(os.path.join(GOLDEN, name)) as f:
+        lines = [ln.strip() for ln in f if ln.strip() and not ln.startswith("#")]
+    head = lines[0].split(",")
+    for ln in lines[1:]:
+        rows.append(dict(zip(head, ln.split(","))))
+    return rows
+
+
+def report_tables(a):
+    """The paper's sweeps (Sec. 5, Tables 1 and 3) on this library: mean
+    iterations (Table 1) and paper-model MV counts (Table 3) over 10 random
+    sigma per lattice, one random right-hand side each, tol 1e-12, complex128,
+    next to the printed values (tests/golden/paper_table*.csv). The Chebyshev
+    spectrum floor eps and the SCA alpha are not given in the paper; the values
+    used here are named in the column heads."""
+    import torch
+    from synthetic import sigma_field, gaussian_rhs, sweep_seeds, WORKLOADS
+    from paper_1008_3647_amd import Lattice, Precond
+    w = WORKLOADS["paper_sweeps"]
+    tol, maxit = 1e-12, 10000
+    t1 = {(int(r["nx"]), int(r["ntau"])): r for r in _read_paper_csv("paper_table1_iterations.csv")}
+    t3 = {(int(r["nx"]), int(r["ntau"]), float(r["g"])): r
+          for r in _read_paper_csv("paper_table3_mv.csv")}
+
+    def problems(nx, ntau, n=w["nsigma"], const_rhs=False):
+        out = []
+        for k in range(n):
+            ss, rs = sweep_seeds(w, nx, ntau, k)
+            sig = torch.from_numpy(sigma_field(nx, ntau, ss)).cuda()
+            if const_rhs:
+                b = torch.ones((1, ntau, nx, nx, nx), dtype=torch.complex128, device="cuda")
+            else:
+                b = torch.from_numpy(gaussian_rhs(nx, ntau, [rs])).cuda()
+            out.append((sig, b))
+        return out
+
+    def run(L, solver, pc, b):
+        if solver == "CG":
+            x, st = L.solve_cg_normal(b, pc, tol=tol, maxit=maxit)
+            return st["status"] == 0, st["iters"][0], st["paper_mv"]
+        x, st = L.solve_bicgstab(b, "two_step", pc, tol=tol, maxit=maxit)
+        return st["status"] == 0, st["iters"][0] + st["iters"][1], st["paper_mv"]
+
+    def cell(L, probs, solver, pc, what):
+        vals, fails = [], 0
+        for sig, b in probs:
+            L.set_aux_field(sig)
+            ok, its, mv = run(L, solver, pc, b)
+            if ok:
+                vals.append(its if what == "iters" else mv)
+            else:
+                fails += 1
+        return vals, fails
+
+    def fmt(vals, fails, paper):
+        if not vals:
+            txt = "-"
+        else:
+            m = float(np.mean(vals))
+            sd = float(np.std(vals, ddof=1)) if len(vals) > 1 else 0.0
+            txt = f"{m:.0f} ± {sd:.0f}"
+            if paper not in (None, "-"):
+                txt += f" ({m / float(paper):.2f})"
+        if fails:
+            txt += f" [{fails} not converged]"
+        return txt + f" / {paper if paper is not None else ''}"
+
+    cols = [("CG", "cheb8", Precond("cheb", degree=8, eps=1e-2, lam_max=-1.0)),
+            ("CG", "cheb16", Precond("cheb", degree=16, eps=3e-3, lam_max=-1.0)),
+            ("CG", "cheb32", Precond("cheb", degree=32, eps=1e-3, lam_max=-1.0)),
+            ("CG", "sca", Precond("sca", alpha=2.0)),
+            ("BiCGStab", "wce0", Precond("wce", wce_order=0)),
+            ("BiCGStab", "wce1", Precond("wce", wce_order=1)),
+            ("BiCGStab", "wce2", Precond("wce", wce_order=2))]
+    print("## Table 1: iterations to tol 1e-12, g = 5.0 (mean ± std over 10 random sigma "
+          "(ratio to the paper) / the paper's value)\n")
+    print("CG on M^T M: Chebyshev degree 8 / 16 / 32 with eps = 1e-2 / 3e-3 / 1e-3, "
+          "lambda_max by power iteration; SCA with alpha = 2. BiCGStab: two-step, "
+          "iterations of both steps summed; weak-coupling order 0 / 1 / 2. "
+          "'not converged': 10,000 iterations reached.\n")
+    print("| lattice | " + " | ".join(f"{s} {n}" for s, n, _ in cols) + " |")
+    print("|---|" + "---|" * len(cols))
+    for nx, ntau in w["shapes"]:
+        L = Lattice(nx, ntau, 0.05, 5.0, torch.complex128)
+        probs = problems(nx, ntau)
+        row = []
+        for solver, name, pc in cols:
+            vals, fails = cell(L, probs, solver, pc, "iters")
+            row.append(fmt(vals, fails, t1[(nx, ntau)][name]))
+        print(f"| {nx}^3 x {ntau} | " + " | ".join(row) + " |", flush=True)
+        progress(f"table 1 row {nx}^3 x {ntau} done")
+        L.close()
+
+    print("\n## Table 3: MV operations (the paper's cost model) of two-step BiCGStab with "
+          "WCE2 and WCE4, 10^3 x Ntau (mean ± std (ratio) / the paper's value)\n")
+    print("| lattice | g | A | WCE2 | WCE4 | WCE4 + Euler |")
+    print("|---|---|---|---|---|---|")
+    for ntau in (50, 100, 200):
+        probs = problems(10, ntau)
+        for g in (2.5, 5.0, 7.5):
+            L = Lattice(10, ntau, 0.05, g, torch.complex128)
+            ref = t3[(10, ntau, g)]
+            row = []
+            for pc, key in ((Precond("wce", wce_order=2), "wce2"),
+                            (Precond("wce", wce_order=4), "wce4"),
+                            (Precond("wce", wce_order=4, euler=True), None)):
+                vals, fails = cell(L, probs, "BiCGStab", pc, "mv")
+                row.append(fmt(vals, fails, ref[key] if key else None))
+            A = float(np.sqrt(2.0) * np.sqrt(np.exp(0.05 * g) - 1.0))
+            print(f"| 10^3 x {ntau} | {g} | {A:.2f} | " + " | ".join(row) + " |", flush=True)
+            L.close()
+        progress(f"table 3 rows 10^3 x {ntau} done")
+
+    print("\n## g = 10 (A = 1.14): convergence within 15,000 MV (paper model)\n")
+    print("| lattice | preconditioner | converged within 15,000 MV | MV of the converged |")
+    print("|---|---|---|---|")
+    for ntau in (50, 100):
+        probs = problems(10, ntau)
+        L = Lattice(10, ntau, 0.05, 10.0, torch.complex128)
+        for pc, name in ((Precond("wce", wce_order=2), "WCE2"), (Precond("wce", wce_order=4), "WCE4")):
+            vals, fails = cell(L, probs, "BiCGStab", pc, "mv")
+            within = [v for v in vals if v <= 15000]
+            mvs = f"{np.mean(within):.0f}" if within else "-"
+            print(f"| 10^3 x {ntau} | {name} | {len(within)} of {len(probs)} | {mvs} |", flush=True)
+        L.close()
+    progress("g = 10 rows done")
+
+    print("\n## Constant against random right-hand side (WCE2, g = 5, 8^3 x 100)\n")
+    L = Lattice(8, 100, 0.05, 5.0, torch.complex128)
+    for const in (False, True):
+        vals, fails = cell(L, problems(8, 100, const_rhs=const), "BiCGStab",
+                           Precond("wce", wce_order=2), "iters")
+        print(f"* {'constant' if const else 'random'} b: {np.mean(vals):.1f} ± "
+              f"{np.std(vals, ddof=1):.1f} iterations ({fails} not converged)")
+    L.close()
+    return 0
+
+
 def report_mv_sweep(a):
     """apply_M / apply_Mdag bandwidth across lattice sizes and right-hand-side
     counts (library-default launch shapes). Each timed loop cycles through
@@ -522,12 +663,17 @@ def report_mv_sweep(a):
     return 0
 
 
+def progress(msg):
+    """One line per finished stage of the run (stderr; stdout keeps the JSON line)."""
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
 def main():
     a = parse()
     if a.report:
         return {"config2": report_config2, "batched": report_batched,
                 "batched_solve": report_batched_solve, "force": report_force,
-                "mv_sweep": report_mv_sweep}[a.report](a)
+                "mv_sweep": report_mv_sweep, "tables": report_tables}[a.report](a)
     if a.mv_only:
         return mv_only(a)
     if a.gpus != 1:
@@ -537,6 +683,8 @@ def main():
     # the oracle leg's timing runs first, in forked worker processes, before
     # anything touches the GPU
     orate = None if a.no_cpu_baseline else cpu_oracle_rate(8, a.cpu_seconds)
+    if orate is not None:
+        progress("oracle leg timed")
     import torch
     from synthetic import sigma_field, gaussian_rhs, WORKLOADS
     from paper_1008_3647_amd import Lattice, Precond
@@ -563,6 +711,7 @@ def main():
         tuned64 = {k: t[k] for k in SHAPE}
         t = tune(L, b, mixed=True, op="M", cache=None, precond=pc)
         tuned = {k: t[k] for k in SHAPE}
+        progress(f"launch shapes tuned: complex64-refined {tuned}, complex128 {tuned64}")
 
     def shape(tn):
         if tn is not None:
@@ -590,6 +739,7 @@ def main():
     torch.cuda.synchronize()
     t_mixed = (time.perf_counter() - t0) / a.steps
     ok = st["status"] == 0 and max(st["relres"]) <= tol
+    progress(f"FP32-refined solve: {t_mixed:.4f} s per step, iterations {st['iters']}")
 
     # all-FP64 comparison on the same GPU, in its own tuned launch shape
     shape(tuned64)
@@ -600,6 +750,7 @@ def main():
         x64, st64 = solve(False)
     torch.cuda.synchronize()
     t_fp64 = (time.perf_counter() - t0) / a.fp64_steps
+    progress(f"all-FP64 solve: {t_fp64:.4f} s, iterations {st64['iters']}")
 
     diff_fp64 = float((x - x64).abs().max().item() / x64.abs().max().item())
 
@@ -637,6 +788,7 @@ def main():
         xw64, stw64 = solve_w(False)
         torch.cuda.synchronize()
         tw64 = time.perf_counter() - t0
+        progress(f"WCE2 solves: {tw:.4f} s (refined), {tw64:.4f} s (FP64)")
         secondary = dict(precond="wce2", seconds=round(tw, 4), iters=list(stw["iters"]),
                          relres_steps=list(stw["relres"]), fp64_seconds=round(tw64, 4),
                          fp64_iters=list(stw64["iters"]),
@@ -711,6 +863,7 @@ def main():
                             copy="ufg_device_copy of one 105 MB vector (read + write), same buffers")
         del xs, ys
         Lm.close()
+        progress(f"apply_M / apply_Mdag bandwidth loops done ({'c64' if dt == torch.complex64 else 'c128'})")
 
     out = {
         "metric": "time-to-solution at rel resid 1e-10 (FP32-refined vs FP64), Nx=16 Ntau=400; MV GB/s",

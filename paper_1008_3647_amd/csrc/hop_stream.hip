@@ -274,6 +274,32 @@ __device__ __forceinline__ bool stream_item(int nslab, int nrhs, int xg, int ri,
   return true;
 }
 
+// Where the transform reads the blocks of T (or U) from. The Nx = 16 blocks
+// are 66 numbers. In FP64 (132 SGPRs) they exceed the scalar register file and
+// the compiler spills them to VGPR lanes (a v_readlane before each use); with
+// IN_LDS the workgroup copies them into LDS once and the transform reads them
+// from there (broadcast reads). Measured per kernel: the fused FP64 M-type
+// operator (t = A s: 227 -> 206 us), the FP64 basis changes and both
+// precisions of basis_pair_kernel (two sets) gain; the plain FP64 operator (103
+// -> 122 us), the M^T-type fused ones and every complex64 operator keep the
+// kernel-argument copy.
+template <bool IN_LDS, typename R, int NX>
+using CoefSlot = typename std::conditional<IN_LDS, SplitCoef<R, NX>, char>::type;
+
+template <bool IN_LDS, typename R, int NX>
+__device__ __forceinline__ const SplitCoef<R, NX>* coef_copy(const SplitCoef<R, NX>& c,
+                                                            CoefSlot<IN_LDS, R, NX>* lds_slot) {
+  if constexpr (IN_LDS) {
+    constexpr int NC = sizeof(SplitCoef<R, NX>) / sizeof(R);
+    for (int i = threadIdx.x; i < NC; i += blockDim.x)
+      reinterpret_cast<R*>(lds_slot)[i] = reinterpret_cast<const R*>(&c)[i];
+    __syncthreads();
+    return lds_slot;
+  } else {
+    return &c;
+  }
+}
+
 __device__ __forceinline__ double wsum(double v) {
 #pragma unroll
   for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
@@ -309,6 +335,9 @@ __global__ void __launch_bounds__(NX * NX)
   // decreasing order, so a slab's halo (the next slab) was loaded first
   if (DIR > 0 && xg > 0) sb = nslab - 1 - sb;
   if (a.gate && a.gate[r] == 0) return;
+  constexpr bool kCoefLds = sizeof(R) == 8 && DIR < 0 && (SRC != 0 || RED != 0);
+  __shared__ CoefSlot<kCoefLds, R, NX> coef_lds[1];
+  const SplitCoef<R, NX>& cc = *coef_copy<kCoefLds, R, NX>(c, coef_lds);
 
   const int l = threadIdx.x;
   const int t0 = (int)((long long)sb * ntau / nslab);
@@ -416,7 +445,7 @@ __global__ void __launch_bounds__(NX * NX)
     }
   }
   if (DIR < 0) scale_field<R, NX>(b.pre, th * V * FS, fo, X);
-  slice_T3<R, NX, 0, true>(c, lds, l, X);
+  slice_T3<R, NX, 0, true>(cc, lds, l, X);
   for (int k = 0; k < count; ++k) {
     const int t = tfirst + k * step;
     const int so = t * V * ES;  // slice byte offset (uniform)
@@ -538,7 +567,7 @@ __global__ void __launch_bounds__(NX * NX)
     if (k + 1 < count) {
       // transform source slice t for the next output slice
       if (DIR < 0) scale_field<R, NX>(b.pre, t * V * FS, fo, X);
-      slice_T3<R, NX, 0, true>(c, lds, l, X);
+      slice_T3<R, NX, 0, true>(cc, lds, l, X);
     }
   }
   if (RED != 0) {
@@ -644,6 +673,9 @@ __global__ void __launch_bounds__(NX * NX)
   int r, sb;
   if (!stream_item(nslab, a.nrhs, xg, ri, r, sb)) return;
   if (a.gate && a.gate[r] == 0) return;
+  constexpr bool kCoefLds = sizeof(R) == 8;
+  __shared__ CoefSlot<kCoefLds, R, NX> coef_lds[1];
+  const SplitCoef<R, NX>& cc = *coef_copy<kCoefLds, R, NX>(c, coef_lds);
   const int l = threadIdx.x;
   const int t0 = (int)((long long)sb * ntau / nslab);
   const int t1 = (int)((long long)(sb + 1) * ntau / nslab);
@@ -688,7 +720,7 @@ __global__ void __launch_bounds__(NX * NX)
 #pragma unroll
       for (int z = 0; z < NX; ++z) U[GENERAL ? z : 0] = a.aux[o + z * P];
     }
-    slice_T3<R, NX, FWD ? 1 : 2>(c, lds, l, X);
+    slice_T3<R, NX, FWD ? 1 : 2>(cc, lds, l, X);
 #pragma unroll
     for (int z = 0; z < NX; ++z) {
       C2<R> out;
@@ -741,6 +773,9 @@ __global__ void __launch_bounds__(NX * NX)
   int r, sb;
   if (!stream_item(nslab, a.nrhs, xg, ri, r, sb)) return;
   if (a.gate && a.gate[r] == 0) return;
+  __shared__ SplitCoef<R, NX> coef_lds[2];
+  const SplitCoef<R, NX>& ccb = *coef_copy<true, R, NX>(cb, coef_lds);
+  const SplitCoef<R, NX>& ccf = *coef_copy<true, R, NX>(cf, coef_lds + 1);
   const int l = threadIdx.x;
   const int t0 = (int)((long long)sb * ntau / nslab);
   const int t1 = (int)((long long)(sb + 1) * ntau / nslab);
@@ -763,7 +798,7 @@ __global__ void __launch_bounds__(NX * NX)
 #pragma unroll
       for (int z = 0; z < NX; ++z) Au[z] = a.aux[o + z * P];
     }
-    slice_T3<R, NX, 2>(cb, lds, l, X);  // U^3
+    slice_T3<R, NX, 2>(ccb, lds, l, X);  // U^3
 #pragma unroll
     for (int z = 0; z < NX; ++z) {
       const C2<R> b = C2<R>{F[z] * X[z].x, F[z] * X[z].y};
@@ -778,7 +813,7 @@ __global__ void __launch_bounds__(NX * NX)
       }
       X[z] = C2<R>{G[z] * w.x, G[z] * w.y};
     }
-    slice_T3<R, NX, 1>(cf, lds, l, X);  // U^3T
+    slice_T3<R, NX, 1>(ccf, lds, l, X);  // U^3T
 #pragma unroll
     for (int z = 0; z < NX; ++z) {
       a.dst[o + z * P] = X[z];

@@ -22,6 +22,7 @@ __all__ = [
     "gaussian_rhs",
     "gaussian_momenta",
     "uniform_draws",
+    "sweep_seeds",
     "batched_problem_shapes",
     "sample_sites",
     "WORKLOADS",
@@ -62,6 +63,12 @@ def uniform_draws(seed: int, count: int) -> np.ndarray:
     return rng.random(count)
 
 
+def sweep_seeds(w, nx: int, ntau: int, k: int):
+    """(sigma seed, rhs seed) of configuration k of the paper-sweep workload."""
+    off = 10000 * k + 100 * nx + ntau // 10
+    return w["sigma_seed0"] + off, w["rhs_seed0"] + off
+
+
 def batched_problem_shapes(count: int = 64, seed: int = 4000):
     """Uneven lattice shapes for the batched workload.
 
@@ -96,6 +103,12 @@ WORKLOADS = {
     # force / molecular dynamics at Nx=12, Ntau=200
     "lattice_12x200": dict(nx=12, ntau=200, sigma_seed=5001, eta_seed=5002,
                            site_seed=5003, momentum_seed=5004, metropolis_seed=5005),
+    # the paper's sweeps (Tables 1 and 3): 10 random sigma per lattice and
+    # coupling, one random right-hand side each; sigma seed
+    # sigma_seed0 + 10000 k + 100 nx + ntau / 10 for configuration k (rhs: rhs_seed0 + same)
+    "paper_sweeps": dict(sigma_seed0=600000, rhs_seed0=700000, nsigma=10,
+                         shapes=[(6, 50), (8, 50), (10, 50), (6, 100), (8, 100), (10, 100),
+                                 (6, 200), (8, 200), (10, 200)]),
 }
 TAU = 0.05
 G_COUPLING = 5.0
