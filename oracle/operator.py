@@ -8,6 +8,9 @@ Definition (paper, Sec. 1, Eq. MatrixM and the text after it):
     field on slice j, A = sqrt(2) sqrt(exp(tau g) - 1).
   * K is diagonal in momentum space with E(k) = k^2 / 2 (hbar = m = 1, lattice
     spacing 1), k_i = 2 pi n_i / Nx, n_i = -Nx/2 .. Nx/2-1.
+  * disp="hubbard" (the other dispersion the concluding section names, that of
+    the Hubbard model): E(k) = sum_i (1 - cos k_i), nearest-neighbour hopping of
+    amplitude 1/2, equal to k^2 / 2 up to O(k^4). Everything else is unchanged.
   * M is real, so M^dagger = M^T.
 
 0-based restatement used everywhere: with b_t = 1 + A sin sigma(., t),
@@ -39,25 +42,34 @@ def _fft_momenta(nx: int) -> np.ndarray:
     return 2.0 * np.pi * np.fft.fftfreq(nx)
 
 
-def dispersion(k):
-    """E(k) = hbar^2 k^2 / 2m with hbar = m = 1 (paper, Sec. 1)."""
-    return 0.5 * np.asarray(k) ** 2
+DISPERSIONS = ("free", "hubbard")
 
 
-def kinetic_symbol(nx: int, tau: float) -> np.ndarray:
+def dispersion(k, disp: str = "free"):
+    """Per-axis kinetic energy: k^2 / 2 (hbar = m = 1, paper Sec. 1), or
+    1 - cos k for the Hubbard-model dispersion."""
+    k = np.asarray(k)
+    if disp == "free":
+        return 0.5 * k ** 2
+    if disp == "hubbard":
+        return 1.0 - np.cos(k)
+    raise ValueError(f"unknown dispersion {disp!r}")
+
+
+def kinetic_symbol(nx: int, tau: float, disp: str = "free") -> np.ndarray:
     """exp(-tau E(k)) on the 3D momentum grid, numpy FFT order, axes (z, y, x)."""
     k = _fft_momenta(nx)
     kz, ky, kx = np.meshgrid(k, k, k, indexing="ij")
-    return np.exp(-tau * (dispersion(kx) + dispersion(ky) + dispersion(kz)))
+    return np.exp(-tau * (dispersion(kx, disp) + dispersion(ky, disp) + dispersion(kz, disp)))
 
 
-def apply_expK(v: np.ndarray, tau: float) -> np.ndarray:
+def apply_expK(v: np.ndarray, tau: float, disp: str = "free") -> np.ndarray:
     """exp(-tau K) applied to every slice of v (last three axes z, y, x).
 
     K is diagonal in momentum space, so: FFT, multiply, inverse FFT.
     """
     nx = v.shape[-1]
-    sym = kinetic_symbol(nx, tau)
+    sym = kinetic_symbol(nx, tau, disp)
     return np.fft.ifftn(np.fft.fftn(v, axes=(-3, -2, -1)) * sym, axes=(-3, -2, -1))
 
 
@@ -71,25 +83,27 @@ def _sign(t: int, ntau: int) -> float:
     return 1.0 if t == ntau - 1 else -1.0
 
 
-def apply_M(x: np.ndarray, sigma: np.ndarray, tau: float, g: float) -> np.ndarray:
+def apply_M(x: np.ndarray, sigma: np.ndarray, tau: float, g: float,
+            disp: str = "free") -> np.ndarray:
     """y = M[sigma] x for one vector x shaped [Ntau][Nx][Nx][Nx]."""
     A = coupling_A(tau, g)
     b = field_b(sigma, A)
     ntau = x.shape[0]
     y = np.array(x, dtype=np.complex128, copy=True)
     for t in range(ntau):
-        y[(t + 1) % ntau] += _sign(t, ntau) * apply_expK(b[t] * x[t], tau)
+        y[(t + 1) % ntau] += _sign(t, ntau) * apply_expK(b[t] * x[t], tau, disp)
     return y
 
 
-def apply_Mdag(x: np.ndarray, sigma: np.ndarray, tau: float, g: float) -> np.ndarray:
+def apply_Mdag(x: np.ndarray, sigma: np.ndarray, tau: float, g: float,
+               disp: str = "free") -> np.ndarray:
     """y = M^T x (M is real, paper Sec. 1)."""
     A = coupling_A(tau, g)
     b = field_b(sigma, A)
     ntau = x.shape[0]
     y = np.array(x, dtype=np.complex128, copy=True)
     for t in range(ntau):
-        y[t] += _sign(t, ntau) * b[t] * apply_expK(x[(t + 1) % ntau], tau)
+        y[t] += _sign(t, ntau) * b[t] * apply_expK(x[(t + 1) % ntau], tau, disp)
     return y
 
 
@@ -114,9 +128,9 @@ def apply_M1dag(x: np.ndarray, sigma: np.ndarray, tau: float) -> np.ndarray:
     return y
 
 
-def apply_Q(x, sigma, tau, g):
+def apply_Q(x, sigma, tau, g, disp="free"):
     """Q x = M^T M x (paper, Sec. 1, Eq. 1)."""
-    return apply_Mdag(apply_M(x, sigma, tau, g), sigma, tau, g)
+    return apply_Mdag(apply_M(x, sigma, tau, g, disp), sigma, tau, g, disp)
 
 
 # ---------------------------------------------------------------------------
@@ -125,8 +139,8 @@ def apply_Q(x, sigma, tau, g):
 # Kronecker product of three Nx x Nx matrices built from the cosine sum.
 
 
-def transfer_matrix_1d(nx: int, tau: float) -> np.ndarray:
-    """T_{xy} = (1/Nx) sum_m exp(-tau k_m^2 / 2) exp(i k_m (x - y)), real.
+def transfer_matrix_1d(nx: int, tau: float, disp: str = "free") -> np.ndarray:
+    """T_{xy} = (1/Nx) sum_m exp(-tau E(k_m)) exp(i k_m (x - y)), real.
 
     One-dimensional factor of exp(-tau K); K separates over the three axes.
     """
@@ -135,19 +149,19 @@ def transfer_matrix_1d(nx: int, tau: float) -> np.ndarray:
     d = x[:, None] - x[None, :]
     T = np.zeros((nx, nx))
     for km in k:
-        T += np.exp(-tau * dispersion(km)) * np.cos(km * d)
+        T += np.exp(-tau * dispersion(km, disp)) * np.cos(km * d)
     return T / nx
 
 
-def dense_expK(nx: int, tau: float) -> np.ndarray:
-    T = transfer_matrix_1d(nx, tau)
+def dense_expK(nx: int, tau: float, disp: str = "free") -> np.ndarray:
+    T = transfer_matrix_1d(nx, tau, disp)
     return np.kron(T, np.kron(T, T))  # site index (z*Nx + y)*Nx + x
 
 
-def _dense_blocks(diag_fields, nx, tau, identity=True):
+def _dense_blocks(diag_fields, nx, tau, identity=True, disp="free"):
     ntau = diag_fields.shape[0]
     V = nx ** 3
-    T3 = dense_expK(nx, tau)
+    T3 = dense_expK(nx, tau, disp)
     Mx = np.eye(ntau * V) if identity else np.zeros((ntau * V, ntau * V))
     for t in range(ntau):
         r = (t + 1) % ntau
@@ -156,10 +170,10 @@ def _dense_blocks(diag_fields, nx, tau, identity=True):
     return Mx
 
 
-def dense_M(sigma, tau, g):
+def dense_M(sigma, tau, g, disp="free"):
     """Dense real M[sigma], index (t*V + n); tiny lattices only."""
     nx = sigma.shape[-1]
-    return _dense_blocks(field_b(sigma, coupling_A(tau, g)), nx, tau, True)
+    return _dense_blocks(field_b(sigma, coupling_A(tau, g)), nx, tau, True, disp)
 
 
 def dense_M1(sigma, tau):

@@ -122,3 +122,40 @@ def test_real_operator_does_not_mix_components():
     y = oracle.apply_M(x, sigma, TAU, G)
     yr = oracle.apply_M(x.real.astype(complex), sigma, TAU, G)
     assert np.allclose(y.real, yr.real, atol=1e-14) and np.allclose(yr.imag, 0, atol=1e-14)
+
+
+def test_hubbard_transfer_is_matrix_exponential_of_hopping():
+    """Hubbard-model dispersion (the extension the concluding section names):
+    E(k) = 1 - cos k per axis is the symbol of H = 1 - (S+ + S-)/2 (S+- the
+    periodic shifts), so the cosine-sum factor must equal expm(-tau H), computed
+    here by scipy's Pade route; and E agrees with k^2/2 to O(k^4)."""
+    from scipy.linalg import expm
+    for nx in (2, 4, 6, 8, 12, 16):
+        H = np.eye(nx)
+        for i in range(nx):
+            H[i, (i + 1) % nx] -= 0.5
+            H[i, (i - 1) % nx] -= 0.5
+        T = op.transfer_matrix_1d(nx, TAU, "hubbard")
+        assert np.allclose(T, expm(-TAU * H), rtol=0, atol=1e-14), nx
+        assert not np.allclose(T, op.transfer_matrix_1d(nx, TAU, "free"), atol=1e-6)
+    k = np.linspace(-0.3, 0.3, 61)
+    assert np.all(np.abs(op.dispersion(k, "hubbard") - k ** 2 / 2) <= k ** 4 / 24 + 1e-16)
+
+
+@pytest.mark.parametrize("nx,ntau", [(2, 3), (4, 5)])
+def test_hubbard_matrix_free_equals_dense(nx, ntau):
+    """FFT route (symbol) against the Kronecker route (cosine sums) for the
+    Hubbard dispersion, M and M^T, and the block-cyclic determinant identity."""
+    sigma = sigma_field(nx, ntau, 15)
+    x = gaussian_rhs(nx, ntau, [16])[0]
+    Md = op.dense_M(sigma, TAU, G, "hubbard")
+    assert np.allclose(oracle.apply_M(x, sigma, TAU, G, "hubbard").ravel(), Md @ x.ravel(),
+                       atol=1e-13)
+    assert np.allclose(oracle.apply_Mdag(x, sigma, TAU, G, "hubbard").ravel(),
+                       Md.T @ x.ravel(), atol=1e-13)
+    b = op.field_b(sigma, oracle.coupling_A(TAU, G))
+    T3 = op.dense_expK(nx, TAU, "hubbard")
+    prod = np.eye(nx ** 3)
+    for t in range(ntau):
+        prod = (T3 * b[t].reshape(-1)[None, :]) @ prod
+    assert np.linalg.det(Md) == pytest.approx(np.linalg.det(np.eye(nx ** 3) + prod), rel=1e-10)
