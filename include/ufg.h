@@ -35,6 +35,12 @@ typedef struct ufg_lattice_s* ufg_lattice; /* opaque, owned by the library */
 
 enum { UFG_C64 = 0, UFG_C128 = 1 };
 
+/* Kinetic energy per axis (create_lattice_ex): UFG_DISP_FREE, E = k^2 / 2 (Sec. 1);
+   UFG_DISP_HUBBARD, E = 1 - cos k, the Hubbard-model dispersion the concluding
+   section names as an extension (nearest-neighbour hopping of amplitude 1/2,
+   equal to k^2 / 2 up to O(k^4)). */
+enum { UFG_DISP_FREE = 0, UFG_DISP_HUBBARD = 1 };
+
 enum {
   UFG_OK = 0,
   UFG_EINVAL = -1,
@@ -144,6 +150,18 @@ typedef struct {
  */
 int create_lattice(int nx, int ntau, double tau, double g, int dtype,
                    void* hip_stream, ufg_lattice* out);
+
+/*
+ * create_lattice_ex -- create_lattice with the dispersion of K chosen:
+ *   UFG_DISP_FREE (what create_lattice makes) or UFG_DISP_HUBBARD. exp(-tau K)
+ *   stays the product of one symmetric circulant factor T per axis, so every
+ *   operator, preconditioner, solver and the force apply unchanged; T, its
+ *   eigenbasis (M0^{-1}) and the block form of T follow the dispersion. The
+ *   strong-coupling blocks do not involve K. Errors as create_lattice, and
+ *   UFG_EINVAL for another dispersion value.
+ */
+int create_lattice_ex(int nx, int ntau, double tau, double g, int dtype, int dispersion,
+                      void* hip_stream, ufg_lattice* out);
 
 /* destroy_lattice -- free the handle and all library-owned device memory. */
 int destroy_lattice(ufg_lattice L);

@@ -29,15 +29,16 @@ def action(phi, sigma, tau, g, solve_Mdag):
     return float(np.vdot(y, y).real), y
 
 
-def gradient(X, sigma, tau, g):
-    """dS/dsigma for X = Q^{-1} phi (formula in the module docstring)."""
+def gradient(X, sigma, tau, g, disp="free"):
+    """dS/dsigma for X = Q^{-1} phi (formula in the module docstring); disp as
+    in oracle.operator."""
     A = coupling_A(tau, g)
     ntau = sigma.shape[0]
-    MX = apply_M(X, sigma, tau, g)
+    MX = apply_M(X, sigma, tau, g, disp)
     out = np.empty_like(sigma)
     for t in range(ntau):
         s = 1.0 if t == ntau - 1 else -1.0
-        Ty = apply_expK(MX[(t + 1) % ntau], tau)
+        Ty = apply_expK(MX[(t + 1) % ntau], tau, disp)
         out[t] = -2.0 * A * np.cos(sigma[t]) * s * np.real(X[t] * np.conj(Ty))
     return out
 

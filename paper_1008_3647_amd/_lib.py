@@ -15,6 +15,8 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libufg.so")
 
 UFG_C64, UFG_C128 = 0, 1
+UFG_DISP_FREE, UFG_DISP_HUBBARD = 0, 1
+DISPERSIONS = {"free": UFG_DISP_FREE, "hubbard": UFG_DISP_HUBBARD}
 UFG_OP_M, UFG_OP_MDAG, UFG_OP_TWO_STEP, UFG_OP_Q = 0, 1, 2, 3
 UFG_PC_NONE, UFG_PC_CHEB, UFG_PC_SCA, UFG_PC_WCE, UFG_PC_SCA_CHEB = 0, 1, 2, 3, 4
 UFG_OK, UFG_EINVAL, UFG_ENOMEM, UFG_EHIP = 0, -1, -2, -3
@@ -67,6 +69,8 @@ class ufg_hmc_result(C.Structure):
 
 _P = C.c_void_p
 _SIGNATURES = {
+    "create_lattice_ex": (C.c_int, [C.c_int, C.c_int, C.c_double, C.c_double, C.c_int, C.c_int,
+                                    _P, C.POINTER(_P)]),
     "create_lattice": (C.c_int, [C.c_int, C.c_int, C.c_double, C.c_double, C.c_int, _P,
                                  C.POINTER(_P)]),
     "destroy_lattice": (C.c_int, [_P]),

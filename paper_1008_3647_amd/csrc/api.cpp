@@ -81,26 +81,33 @@ int batched_tune(int hop_blocks_per_cu, int vec_blocks_per_cu, long long chunk, 
                  int sync_iters);
 int euler_weights(int order, double p, double* w);
 
-// T_{xy} = (1/Nx) sum_m exp(-tau k_m^2 / 2) cos(k_m (x - y)), k_m = 2 pi m / Nx,
+// Kinetic energy of one axis at momentum k: k^2 / 2 (Sec. 1) or, for the
+// Hubbard-model dispersion, 1 - cos k (nearest-neighbour hopping of amplitude
+// 1/2, equal to k^2 / 2 up to O(k^4)).
+static double axis_energy(int dispersion, double k) {
+  return dispersion == UFG_DISP_HUBBARD ? 1.0 - std::cos(k) : 0.5 * k * k;
+}
+
+// T_{xy} = (1/Nx) sum_m exp(-tau E(k_m)) cos(k_m (x - y)), k_m = 2 pi m / Nx,
 // m = -Nx/2 .. Nx/2-1: the one-axis factor of exp(-tau K) in position space.
-static void transfer_matrix(int nx, double tau, double* T) {
+static void transfer_matrix(int nx, double tau, int dispersion, double* T) {
   for (int x = 0; x < nx; ++x)
     for (int y = 0; y < nx; ++y) {
       double s = 0.0;
       for (int m = -nx / 2; m < nx / 2; ++m) {
         const double k = 2.0 * M_PI * m / nx;
-        s += std::exp(-0.5 * tau * k * k) * std::cos(k * (x - y));
+        s += std::exp(-tau * axis_energy(dispersion, k)) * std::cos(k * (x - y));
       }
       T[x * nx + y] = s / nx;
     }
 }
 
 // Real orthonormal eigenvectors of the circulant T (columns of U) and their
-// eigenvalues exp(-tau k^2 / 2): constant mode, cos/sin pairs, alternating mode.
-static void transfer_eigenbasis(int nx, double tau, double* U, double* lam) {
+// eigenvalues exp(-tau E(k)): constant mode, cos/sin pairs, alternating mode.
+static void transfer_eigenbasis(int nx, double tau, int dispersion, double* U, double* lam) {
   auto e = [&](int m) {
     const double k = 2.0 * M_PI * m / nx;
-    return std::exp(-0.5 * tau * k * k);
+    return std::exp(-tau * axis_energy(dispersion, k));
   };
   int col = 0;
   for (int x = 0; x < nx; ++x) U[x * nx + col] = 1.0 / std::sqrt((double)nx);
@@ -199,7 +206,14 @@ const char* last_error(void) { return g_err.c_str(); }
 
 int create_lattice(int nx, int ntau, double tau, double g, int dtype, void* hip_stream,
                    ufg_lattice* out) {
+  return create_lattice_ex(nx, ntau, tau, g, dtype, UFG_DISP_FREE, hip_stream, out);
+}
+
+int create_lattice_ex(int nx, int ntau, double tau, double g, int dtype, int dispersion,
+                      void* hip_stream, ufg_lattice* out) {
   UFG_CHECK(out != nullptr, "create_lattice: out is NULL");
+  UFG_CHECK(dispersion == UFG_DISP_FREE || dispersion == UFG_DISP_HUBBARD,
+            "create_lattice: dispersion must be UFG_DISP_FREE or UFG_DISP_HUBBARD");
   *out = nullptr;
   UFG_CHECK(nx >= 2 && nx <= kMaxNx && nx % 2 == 0, "create_lattice: nx must be even, 2..16");
   UFG_CHECK(ntau >= 2, "create_lattice: ntau must be >= 2");
@@ -216,6 +230,7 @@ int create_lattice(int nx, int ntau, double tau, double g, int dtype, void* hip_
   L->g = g;
   L->A = std::sqrt(2.0) * std::sqrt(std::exp(tau * g) - 1.0);
   L->dtype = dtype;
+  L->dispersion = dispersion;
   L->stream = reinterpret_cast<hipStream_t>(hip_stream);
   if (hipGetDevice(&L->device) != hipSuccess) {
     delete L;
@@ -231,8 +246,8 @@ int create_lattice(int nx, int ntau, double tau, double g, int dtype, void* hip_
   L->T_host.assign(nx * nx, 0.0);
   L->U_host.assign(nx * nx, 0.0);
   L->lam1_host.assign(nx, 0.0);
-  transfer_matrix(nx, tau, L->T_host.data());
-  transfer_eigenbasis(nx, tau, L->U_host.data(), L->lam1_host.data());
+  transfer_matrix(nx, tau, dispersion, L->T_host.data());
+  transfer_eigenbasis(nx, tau, dispersion, L->U_host.data(), L->lam1_host.data());
   // check T = U diag(lam) U^T before trusting the eigenbasis
   double err = 0.0;
   for (int i = 0; i < nx; ++i)
@@ -471,7 +486,7 @@ int ufg_transfer_matrix(int nx, double tau, double* out) {
   UFG_CHECK(out != nullptr, "ufg_transfer_matrix: NULL output");
   UFG_CHECK(nx >= 2 && nx <= kMaxNx && nx % 2 == 0, "ufg_transfer_matrix: nx must be even, 2..16");
   UFG_CHECK(tau > 0, "ufg_transfer_matrix: tau must be > 0");
-  transfer_matrix(nx, tau, out);
+  transfer_matrix(nx, tau, UFG_DISP_FREE, out);
   return UFG_OK;
 }
 

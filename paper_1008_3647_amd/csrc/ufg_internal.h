@@ -84,6 +84,7 @@ struct FlagMirror {
 
 struct Lattice {
   int nx = 0, ntau = 0, dtype = UFG_C128;
+  int dispersion = UFG_DISP_FREE;
   int V = 0;        // nx^3
   long long N = 0;  // V * ntau
   double tau = 0, g = 0, A = 0;

@@ -28,18 +28,25 @@ class Lattice:
 
     dtype: torch.complex64 or torch.complex128 (the vector type of apply_* and
     of plain solves; mixed-precision solves need complex128).
+    dispersion: "free" (E = k^2/2, the paper's) or "hubbard" (E = 1 - cos k per
+    axis; C ABI create_lattice_ex).
     """
 
-    def __init__(self, nx, ntau, tau=0.05, g=5.0, dtype=torch.complex128, stream=None):
+    def __init__(self, nx, ntau, tau=0.05, g=5.0, dtype=torch.complex128, stream=None,
+                 dispersion="free"):
         self._lib = L.load()
         if dtype not in (torch.complex64, torch.complex128):
             raise ValueError("dtype must be torch.complex64 or torch.complex128")
+        if dispersion not in L.DISPERSIONS:
+            raise ValueError(f"dispersion must be one of {sorted(L.DISPERSIONS)}")
         self.nx, self.ntau, self.tau, self.g, self.dtype = nx, ntau, tau, g, dtype
+        self.dispersion = dispersion
         self.device = torch.device("cuda", torch.cuda.current_device())
         h = C.c_void_p()
-        code = self._lib.create_lattice(nx, ntau, tau, g,
-                                        L.UFG_C128 if dtype == torch.complex128 else L.UFG_C64,
-                                        _stream_ptr(stream), C.byref(h))
+        code = self._lib.create_lattice_ex(nx, ntau, tau, g,
+                                           L.UFG_C128 if dtype == torch.complex128 else L.UFG_C64,
+                                           L.DISPERSIONS[dispersion], _stream_ptr(stream),
+                                           C.byref(h))
         L.check(code, "create_lattice")
         self._h = h
         A = C.c_double()
