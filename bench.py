@@ -637,7 +637,7 @@ def report_mv_sweep(a):
             alg = N * (nrhs * 2 * c + f)
             pair = 2 * N * nrhs * c
             rot = max(1, min(16, -(-1_250_000_000 // pair)))
-            xs = [b.to(dt) for _ in range(rot)]
+            xs = [b.to(dt).clone() for _ in range(rot)]  # distinct buffers in both precisions
             ys = [torch.empty_like(xs[0]) for _ in range(rot)]
             res = []
             for fn in (L.apply_M, L.apply_Mdag):
@@ -813,7 +813,7 @@ def main():
     for dt, c, f in ((torch.complex64, 8, 4), (torch.complex128, 16, 8)):
         Lm = Lattice(nx, ntau, 0.05, 5.0, dt)  # library-default launch shape
         Lm.set_aux_field(sigma)
-        xs = [b.to(dt) for _ in range(ROT)]
+        xs = [b.to(dt).clone() for _ in range(ROT)]  # distinct buffers in both precisions
         ys = [torch.empty_like(xs[0]) for _ in range(ROT)]
         # warm-up: every buffer pair with both operators, then launches for
         # `mv_warmup_ms` of wall time so that the timed launches run at the

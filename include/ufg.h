@@ -414,8 +414,9 @@ int lattice_tune_slabs(ufg_lattice L, int nslab);
  *   side of a group in turn (rhs_inner = 1). group = 0: contiguous runs of
  *   (slab, rhs) pairs per XCD, rhs fastest (rhs_inner ignored); group = -1:
  *   the library default (complex64 lattices: groups of 10, rhs_inner 0;
- *   complex128 lattices: 0). group: -1..Ntau. Same result guarantee as
- *   lattice_tune (the numbering changes no arithmetic).
+ *   complex128 lattices of 2^20 sites and more: groups of 10, rhs_inner 1;
+ *   smaller complex128 lattices: 0). group: -1..Ntau. Same result guarantee
+ *   as lattice_tune (the numbering changes no arithmetic).
  */
 int lattice_tune_order(ufg_lattice L, int group, int rhs_inner);
 

@@ -47,6 +47,8 @@ int stream_nslab(const Lattice& L);
 // runs per XCD with the rhs fastest), and the grid of a launch over nrhs.
 int stream_group(const Lattice& L);
 int stream_grid(const Lattice& L, int nrhs);
+// 1: an XCD takes every rhs of a slab group in turn (default or lattice_tune_order)
+int stream_inner(const Lattice& L);
 bool stream_supported(const Lattice& L);
 template <typename R>
 int launch_hop_stream(const Lattice& L, const HopArgs<R>& a);

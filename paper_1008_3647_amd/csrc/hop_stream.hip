@@ -610,7 +610,7 @@ int launch_one(const Lattice& L, const HopArgs<R>& a, const SplitCoef<R, NX>& c,
     attr = true;
   }
   hipLaunchKernelGGL((hop_stream_kernel<R, NX, DIR, GENERAL, SRC, RED>), grid, dim3(NX * NX),
-                     lds, L.stream, a, c, L.ntau, nslab, stream_group(L), L.xcd_rhs_inner);
+                     lds, L.stream, a, c, L.ntau, nslab, stream_group(L), stream_inner(L));
   UFG_HIP(hipGetLastError());
   return UFG_OK;
 }
@@ -844,7 +844,7 @@ int launch_basis_pair_nx(const Lattice& L, const PairArgs<R>& a) {
   }
   hipLaunchKernelGGL((basis_pair_kernel<R, NX>), dim3(stream_grid(L, a.nrhs)), dim3(NX * NX),
                      lds, L.stream, a, cb, cf, L.ntau, nslab, stream_group(L),
-                     L.xcd_rhs_inner);
+                     stream_inner(L));
   UFG_HIP(hipGetLastError());
   return UFG_OK;
 }
@@ -859,7 +859,7 @@ int launch_basis_one(const Lattice& L, const HopArgs<R>& a, const SplitCoef<R, N
     attr = true;
   }
   hipLaunchKernelGGL((basis_kernel<R, NX, FWD, GENERAL, SRC>), grid, dim3(NX * NX), lds,
-                     L.stream, a, c, L.ntau, nslab, stream_group(L), L.xcd_rhs_inner);
+                     L.stream, a, c, L.ntau, nslab, stream_group(L), stream_inner(L));
   UFG_HIP(hipGetLastError());
   return UFG_OK;
 }
@@ -896,12 +896,13 @@ int launch_basis_nx(const Lattice& L, const HopArgs<R>& a, bool forward) {
 
 int stream_slab(const Lattice& L) {
   if (L.slab > 0) return std::min(L.slab, L.ntau);
-  // complex128 lattices: two slices per workgroup measured best at
-  // 16^3 x 400 (the FP64 solve); lattices below 2^20 sites take one, which
-  // doubles the workgroups of their short launches. complex64 lattices: one,
-  // with slab groups (stream_group), measured best for apply_M.
-  if (L.dtype == UFG_C64 || (long long)L.V * L.ntau < (1ll << 20)) return 1;
-  return std::min(2, L.ntau);
+  // One slice per workgroup throughout (with the slab groups of stream_group):
+  // complex64 apply_M at 16^3 x 400, 8 rhs: 48.8 us at two slices per
+  // workgroup in the contiguous numbering, 43.1 us at one in groups of 10;
+  // complex128: 102.9 / 95.3 us (M / M^T) at two slices, 95.4 / 95.8 us at
+  // one in groups of 10 taken rhs-inner (16^3 x 800: 200.1 / 177.9 against
+  // 178.7 / 178.9 us), the FP64 solve within 0.5 %.
+  return 1;
 }
 
 int stream_nslab(const Lattice& L) {
@@ -912,19 +913,25 @@ int stream_nslab(const Lattice& L) {
 
 int stream_group(const Lattice& L) {
   if (L.xcd_group >= 0) return std::min(L.xcd_group, stream_nslab(L));
-  // complex64 lattices: groups of ten slabs (apply_M at 16^3 x 400, 8 rhs:
-  // 48.8 us at two slices per workgroup in the contiguous numbering, 43.1 us
-  // at one slice per workgroup in groups of 5 or 10). complex128 lattices keep
-  // the contiguous numbering (their field slab, 32 KB, is then shared by the
-  // eight right-hand sides at once; in groups it was re-read per rhs).
+  // Groups of ten slabs per XCD. complex64 walks a group's slabs for one rhs
+  // after the other; complex128 lattices of 2^20 sites and more take every rhs
+  // of a group in turn (stream_inner), so a field slice is read while the same
+  // XCD still holds it. Smaller complex128 lattices (short launches,
+  // few slabs) keep the contiguous numbering.
   if (L.dtype == UFG_C64) return std::min(10, stream_nslab(L));
+  if ((long long)L.V * L.ntau >= (1ll << 20)) return std::min(10, stream_nslab(L));
   return 0;
+}
+
+int stream_inner(const Lattice& L) {
+  if (L.xcd_group >= 0) return L.xcd_rhs_inner;
+  return (L.dtype == UFG_C128 && (long long)L.V * L.ntau >= (1ll << 20)) ? 1 : 0;
 }
 
 int stream_grid(const Lattice& L, int nrhs) {
   const int nslab = stream_nslab(L), xg = stream_group(L);
   if (xg <= 0) return nslab * nrhs;
-  if (L.xcd_rhs_inner) {
+  if (stream_inner(L)) {
     const int groups = (nslab + xg - 1) / xg;
     return 8 * ((groups + 7) / 8) * nrhs * xg;
   }
