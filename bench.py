@@ -47,7 +47,7 @@ def parse():
                     help="skip the launch-shape autotuner (run before the timed region)")
     ap.add_argument("--report",
                     choices=["config2", "batched", "batched_solve", "force", "mv_sweep",
-                             "tables"],
+                             "tables", "thermalize"],
                     help="print the measurement table of another workload (markdown) "
                          "instead of the JSON line")
     ap.add_argument("--mv-only", action="store_true",
@@ -612,6 +612,91 @@ def report_tables(a):
     return 0
 
 
+def report_thermalize(a):
+    """phi-algorithm HMC (hmc_trajectory) from a random sigma on 6^3 x 50 at
+    g = 5 until the action settles, then the solver iterations on the
+    thermalized configurations against random ones (Sec. 5: thermalized sigma
+    cluster around +-pi/2 and need about twice the CG iterations). Every
+    random number is seeded (momenta, eta and u per trajectory); the step size
+    is adapted during thermalization only and frozen for the measured part."""
+    import torch
+    from synthetic import (sigma_field, gaussian_rhs, gaussian_momenta, uniform_draws,
+                           sweep_seeds, WORKLOADS)
+    from paper_1008_3647_amd import Lattice, Precond
+    nx, ntau, g = 6, 50, 5.0
+    w = WORKLOADS["paper_sweeps"]
+    L = Lattice(nx, ntau, 0.05, g, torch.complex128)
+    pc = Precond("wce", wce_order=2, euler=True)
+    nsteps, dt = 20, 0.01
+    ntherm, nmeas, every = 500, 10, 10
+    us = uniform_draws(880000, ntherm + nmeas * every)
+    sigma = torch.from_numpy(sigma_field(nx, ntau, 880001)).cuda()
+    hist, acc_window, kept = [], [], []
+    t0 = time.perf_counter()
+    for k in range(ntherm + nmeas * every):
+        pi = torch.from_numpy(gaussian_momenta(nx, ntau, 881000 + k)).cuda()
+        eta = torch.from_numpy(gaussian_rhs(nx, ntau, [891000 + k])).cuda()
+        sigma, _, info = L.hmc_trajectory(sigma, pi, eta, float(us[k]), dt, nsteps, pc,
+                                          tol=1e-10)
+        if info["status"] != 0:
+            raise RuntimeError(f"trajectory {k}: solve status {info['status']}")
+        acc_window.append(info["accept"])
+        hist.append((k, dt, info["dH"], info["accept"], info["S0"]))
+        if k < ntherm and len(acc_window) == 10:
+            rate = sum(acc_window) / 10.0
+            dt = dt * (0.7 if rate < 0.6 else (1.25 if rate > 0.9 else 1.0))
+            acc_window = []
+        if k >= ntherm and (k - ntherm) % every == every - 1:
+            kept.append(sigma.clone())
+        if k % 100 == 99:
+            progress(f"trajectory {k + 1}: dt {dt:.4g}, S0 {info['S0']:.1f}")
+    secs = time.perf_counter() - t0
+    meas = hist[ntherm:]
+    print(f"6^3 x 50, g = {g}, one pseudofermion, WCE2 + Euler BiCGStab (tol 1e-10), "
+          f"{nsteps} leapfrog steps per trajectory; {ntherm} thermalization trajectories "
+          f"(step size adapted to 60-90 % acceptance), then {nmeas * every} at dt = {dt:.4g} "
+          f"keeping every {every}th: {secs:.1f} s in all.\n")
+    print("| trajectories | dt | acceptance | mean dH | mean exp(-dH) | mean S0 |")
+    print("|---|---|---|---|---|---|")
+    for lo, hi in ((0, 100), (100, 200), (200, 300), (300, ntherm), (ntherm, len(hist))):
+        part = hist[lo:hi]
+        print(f"| {lo}-{hi - 1} | {part[0][1]:.4g}-{part[-1][1]:.4g} | "
+              f"{np.mean([h[3] for h in part]):.2f} | {np.mean([h[2] for h in part]):+.3f} | "
+              f"{np.mean([np.exp(-h[2]) for h in part]):.3f} | {np.mean([h[4] for h in part]):.1f} |")
+    del meas
+
+    def near_half_pi(s):
+        return float((torch.sin(s).abs() > 0.7).double().mean().item())
+
+    rand = []
+    for k in range(nmeas):
+        ss, _ = sweep_seeds(w, nx, ntau, k)
+        rand.append(torch.from_numpy(sigma_field(nx, ntau, ss)).cuda())
+    b = torch.from_numpy(gaussian_rhs(nx, ntau, [899999])).cuda()
+    rows = []
+    for name, confs in (("random", rand), ("thermalized", kept)):
+        cg, bi, fr = [], [], []
+        for s in confs:
+            L.set_aux_field(s)
+            _, st = L.solve_cg_normal(b, None, tol=1e-10, maxit=20000)
+            cg.append(st["iters"][0])
+            _, st = L.solve_bicgstab(b, "two_step", Precond("wce", wce_order=2), tol=1e-10)
+            bi.append(st["iters"][0] + st["iters"][1])
+            fr.append(near_half_pi(s))
+        rows.append((name, cg, bi, fr))
+    print("\n| configurations | CG iterations (no preconditioner) | BiCGStab WCE2 iterations | "
+          "fraction of sites with abs(sin sigma) > 0.7 |")
+    print("|---|---|---|---|")
+    for name, cg, bi, fr in rows:
+        print(f"| {name} (10) | {np.mean(cg):.0f} ± {np.std(cg, ddof=1):.0f} | "
+              f"{np.mean(bi):.1f} ± {np.std(bi, ddof=1):.1f} | {np.mean(fr):.3f} |")
+    r = rows[1][1], rows[0][1]
+    print(f"\nthermalized / random: CG {np.mean(r[0]) / np.mean(r[1]):.2f}x, BiCGStab WCE2 "
+          f"{np.mean(rows[1][2]) / np.mean(rows[0][2]):.2f}x (uniform sigma: 0.506 of the sites "
+          "have abs(sin sigma) > 0.7)")
+    return 0
+
+
 def report_mv_sweep(a):
     """apply_M / apply_Mdag bandwidth across lattice sizes and right-hand-side
     counts (library-default launch shapes). Each timed loop cycles through
@@ -678,7 +763,8 @@ def main():
     if a.report:
         return {"config2": report_config2, "batched": report_batched,
                 "batched_solve": report_batched_solve, "force": report_force,
-                "mv_sweep": report_mv_sweep, "tables": report_tables}[a.report](a)
+                "mv_sweep": report_mv_sweep, "tables": report_tables,
+                "thermalize": report_thermalize}[a.report](a)
     if a.mv_only:
         return mv_only(a)
     if a.gpus != 1:
