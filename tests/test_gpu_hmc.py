@@ -152,3 +152,34 @@ def test_trajectory_12x200():
     if not i1["accept"]:
         assert np.array_equal(s1, sigma)
     assert i1["iters"] < i0["iters"]  # chronological starting vectors save iterations
+
+
+def test_chain_checkpoint_resume_is_bitwise(tmp_path):
+    """HMCChain: a chain checkpointed after two trajectories and resumed in a
+    fresh object (new lattice handle) continues bit for bit like the chain
+    that ran straight through; the JSON-lines log holds one record per
+    trajectory; every recorded decision equals u < exp(-dH)."""
+    require_gpu()
+    import json
+    from paper_1008_3647_amd import Lattice
+    from paper_1008_3647_amd.hmc import HMCChain
+    sigma = to_dev(sigma_field(NX, NT, 9450))
+    log = tmp_path / "chain.jsonl"
+    L = Lattice(NX, NT, TAU, G, torch.complex128)
+    a = HMCChain(L, sigma, seed=9451, dt=DT, nsteps=NSTEPS, tol=1e-12, log_path=str(log))
+    ra = a.run(4)
+    b = HMCChain(Lattice(NX, NT, TAU, G, torch.complex128), sigma, seed=9451, dt=DT,
+                 nsteps=NSTEPS, tol=1e-12)
+    b.run(2)
+    ck = tmp_path / "chain.npz"
+    b.save(str(ck))
+    c = HMCChain(Lattice(NX, NT, TAU, G, torch.complex128), sigma, seed=1, dt=0.5, nsteps=1,
+                 tol=1e-12).load(str(ck))
+    rc = c.run(2)
+    assert c.trajectory == 4 and c.accepted == a.accepted
+    assert torch.equal(c.sigma, a.sigma)
+    assert [r["dH"] for r in rc] == [r["dH"] for r in ra[2:]]
+    lines = [json.loads(x) for x in log.read_text().splitlines()]
+    assert [r["trajectory"] for r in lines] == [1, 2, 3, 4]
+    for r in lines:
+        assert r["accept"] == int(r["u"] < np.exp(-r["dH"]))
