@@ -39,6 +39,8 @@ def parse():
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--precond", default="none", choices=["none", "wce2"])
     ap.add_argument("--slab", type=int, default=0, help="--mv-only: slab size (0 = default)")
+    ap.add_argument("--transform", type=int, default=0, choices=[0, 1],
+                    help="--mv-only: T^3 route of apply_M (0 VALU block form, 1 MFMA y/x stages)")
     ap.add_argument("--mv-warmup-ms", type=float, default=500.0,
                     help="wall time of apply_M warm-up launches before the timed ones")
     ap.add_argument("--no-secondary", action="store_true",
@@ -69,8 +71,8 @@ def mv_only(a):
     N = nx ** 3 * ntau
     L = Lattice(nx, ntau, 0.05, 5.0, torch.complex64)
     L.set_aux_field(torch.from_numpy(sigma_field(nx, ntau, w["sigma_seed"])).cuda())
-    if a.slab:
-        L.tune(a.slab, 0)
+    if a.slab or a.transform:
+        L.tune(a.slab, 0, transform=a.transform)
     x0 = torch.from_numpy(gaussian_rhs(nx, ntau, w["rhs_seeds"])).cuda().to(torch.complex64)
     ROT = 6
     xs = [x0.clone() for _ in range(ROT)]
@@ -108,7 +110,8 @@ def mv_only(a):
     torch.cuda.synchronize()
     cms = e0.elapsed_time(e1) / a.mv_launches
     cbytes = 2 * xs[0].nbytes
-    print(json.dumps(dict(mode="mv-only", apply_M_us=ms * 1e3, apply_M_GBs=alg / ms / 1e6,
+    print(json.dumps(dict(mode="mv-only", transform=a.transform, apply_M_us=ms * 1e3,
+                          apply_M_GBs=alg / ms / 1e6,
                           alg_bytes=alg, copy_bytes=cbytes, copy_us=cms * 1e3,
                           copy_GBs=cbytes / cms / 1e6,
                           hop_source_sha256_16=hop_source_hash())), flush=True)
@@ -928,6 +931,21 @@ def main():
                 torch.cuda.synchronize()
                 ms = e0.elapsed_time(e1) / a.mv_launches
                 res[f"{name}_{mode}"] = dict(us=round(ms * 1e3, 2), GBs=round(alg / ms / 1e6, 1))
+        if dt == torch.complex64:
+            # the same launches with the transform's y and x stages on MFMA
+            # (lattice_tune_transform route 1), for the choice of T^3 route
+            Lm.tune(transform=1)
+            for i in range(2 * ROT):
+                Lm.apply_M(xs[i % ROT], ys[i % ROT])
+            e0.record()
+            for i in range(a.mv_launches):
+                Lm.apply_M(xs[i % ROT], ys[i % ROT])
+            e1.record()
+            torch.cuda.synchronize()
+            ms = e0.elapsed_time(e1) / a.mv_launches
+            res["apply_M_hbm_mfma_transform"] = dict(us=round(ms * 1e3, 2),
+                                                     GBs=round(alg / ms / 1e6, 1))
+            Lm.tune(transform=0)
         res["alg_bytes"] = alg
         mv["c64" if dt == torch.complex64 else "c128"] = res
         if dt == torch.complex64:

@@ -420,6 +420,18 @@ int lattice_tune_slabs(ufg_lattice L, int nslab);
  */
 int lattice_tune_order(ufg_lattice L, int group, int rhs_inner);
 
+/*
+ * lattice_tune_transform -- how the complex64 Nx = 16 streaming M / M^T
+ *   operator applies exp(-tau K) = T (x) T (x) T (Sec. 1) to a slice: route 0
+ *   (default) runs all three axes in the reflection-symmetry block form of T on
+ *   the vector ALUs; route 1 keeps the z axis there and runs the y and x axes
+ *   as 16x16x4 FP32 matrix-core (MFMA) contractions with T. Same operator;
+ *   results agree to FP32 rounding, not bit for bit. Other dtypes, sizes and
+ *   the fused solver variants always use route 0. Errors: UFG_EINVAL for a
+ *   route other than 0 or 1.
+ */
+int lattice_tune_transform(ufg_lattice L, int route);
+
 /* lattice_info -- nx, ntau, dtype, A of a handle (host pointers, any may be NULL). */
 int lattice_info(ufg_lattice L, int* nx, int* ntau, int* dtype, double* A);
 

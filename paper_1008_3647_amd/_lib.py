@@ -93,6 +93,7 @@ _SIGNATURES = {
     "lattice_tune": (C.c_int, [_P, C.c_int, C.c_int]),
     "lattice_tune_slabs": (C.c_int, [_P, C.c_int]),
     "lattice_tune_order": (C.c_int, [_P, C.c_int, C.c_int]),
+    "lattice_tune_transform": (C.c_int, [_P, C.c_int]),
     "precond_lam_max": (C.c_int, [_P, C.POINTER(ufg_precond), C.POINTER(C.c_double)]),
     "hmc_leapfrog": (C.c_int, [_P, C.POINTER(ufg_precond), _P, _P, _P, C.c_int,
                                C.POINTER(ufg_hmc_opts), C.POINTER(C.c_double),

@@ -445,6 +445,15 @@ int lattice_tune_order(ufg_lattice h, int group, int rhs_inner) {
   return UFG_OK;
 }
 
+int lattice_tune_transform(ufg_lattice h, int route) {
+  Lattice* L = check_handle(h);
+  UFG_CHECK(L != nullptr, "lattice_tune_transform: NULL handle");
+  UFG_CHECK(route == 0 || route == 1, "lattice_tune_transform: route must be 0 or 1");
+  UFG_HIP(hipStreamSynchronize(L->stream));
+  L->t3_route = route;
+  return UFG_OK;
+}
+
 int lattice_info(ufg_lattice h, int* nx, int* ntau, int* dtype, double* A) {
   Lattice* L = check_handle(h);
   UFG_CHECK(L != nullptr, "lattice_info: NULL handle");

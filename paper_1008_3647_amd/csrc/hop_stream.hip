@@ -119,6 +119,62 @@ __device__ __forceinline__ void slice_T3(const SplitCoef<R, NX>& c, C2<R>* lds, 
   for (int z = 0; z < NX; ++z) v[z] = lds[lds_at<NX>(z * NX + y, x)];
 }
 
+// The y and x stages of T^3 as 16x16x4 FP32 MFMA contractions (Nx = 16,
+// complex64; lattice_tune_transform route 1). A wave owns z-planes 4w..4w+3,
+// as in the VALU stages. For one plane and axis, the lines of the plane form
+// the 16 columns of B and T the 16x16 A operand: lane holds
+// ta[s] = T[lane % 16][4 s + lane / 16] for k-block s, and B[k][c] = the
+// plane's element k of line c (real and imaginary parts separately); the
+// product lands as D[4 (lane / 16) + j][lane % 16], element 4 (lane / 16) + j
+// of line lane % 16. AX = 1: lines along y (c = x); AX = 0: along x (c = y).
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+template <int AX>
+__device__ __forceinline__ void stage_mfma16(const float (&ta)[4], float2* lds, int l) {
+  constexpr int NX = 16;
+  const int w = l >> 6, lane = l & 63, g = lane >> 4, cc = lane & 15;
+#pragma unroll
+  for (int zz = 0; zz < 4; ++zz) {
+    const int z = 4 * w + zz;
+    f32x4 dre = {0.f, 0.f, 0.f, 0.f}, dim = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int s = 0; s < 4; ++s) {
+      const int k = 4 * s + g;
+      const float2 v = AX == 0 ? lds[lds_at<NX>(z * NX + cc, k)] : lds[lds_at<NX>(z * NX + k, cc)];
+      dre = __builtin_amdgcn_mfma_f32_16x16x4f32(ta[s], v.x, dre, 0, 0, 0);
+      dim = __builtin_amdgcn_mfma_f32_16x16x4f32(ta[s], v.y, dim, 0, 0, 0);
+    }
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const int o = 4 * g + j;
+      const float2 r = make_float2(dre[j], dim[j]);
+      if (AX == 0)
+        lds[lds_at<NX>(z * NX + cc, o)] = r;
+      else
+        lds[lds_at<NX>(z * NX + o, cc)] = r;
+    }
+  }
+}
+
+// slice_T3 with the y and x stages on MFMA (z stays on the VALU, in registers);
+// the result stays in LDS as for slice_T3<..., KEEP = true>.
+__device__ __forceinline__ void slice_T3_mfma16(const SplitCoef<float, 16>& c,
+                                                const float (&ta)[4], float2* lds, int l,
+                                                float2 (&v)[16]) {
+  constexpr int NX = 16;
+  const int y = l / NX, x = l - (l / NX) * NX;
+  split_line<float, NX>(c, v);  // along z
+#pragma unroll
+  for (int z = 0; z < NX; ++z) lds[lds_at<NX>(z * NX + y, x)] = v[z];
+  __syncthreads();
+  stage_mfma16<1>(ta, lds, l);  // along y: planes of this wave only
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+  stage_mfma16<0>(ta, lds, l);  // along x
+  __syncthreads();
+}
+
 // Per-rhs scalars of the fused BiCGStab sources.
 template <typename R>
 struct SrcScal {
@@ -312,9 +368,13 @@ __device__ __forceinline__ double wsum(double v) {
 // of the next output: each thread holds one z-line X (current source) in
 // registers, and the transform of the previous source stays in the LDS slice,
 // from which the output phase reads the thread's own z-line.
-template <typename R, int NX, int DIR, bool GENERAL, int SRC, int RED>
+// TR = 1: the transform's y and x stages on MFMA (complex64, Nx = 16, plain
+// operator only; see slice_T3_mfma16).
+template <typename R, int NX, int DIR, bool GENERAL, int SRC, int RED, int TR = 0>
 __global__ void __launch_bounds__(NX * NX)
     hop_stream_kernel(HopArgs<R> a, SplitCoef<R, NX> c, int ntau, int nslab, int xg, int ri) {
+  static_assert(TR == 0 || (sizeof(R) == 4 && NX == 16 && SRC == 0 && RED == 0 && !GENERAL),
+                "the MFMA transform route exists for the plain complex64 Nx = 16 operator");
   constexpr int P = NX * NX, V = NX * NX * NX;
   constexpr int ES = sizeof(C2<R>), FS = sizeof(R);
   // Single-use operand slices are loaded non-temporal (measured: faster for
@@ -340,6 +400,12 @@ __global__ void __launch_bounds__(NX * NX)
   const SplitCoef<R, NX>& cc = *coef_copy<kCoefLds, R, NX>(c, coef_lds);
 
   const int l = threadIdx.x;
+  float ta[TR ? 4 : 1];
+  if constexpr (TR != 0) {
+    const int lane = l & 63;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) ta[j] = float(a.mat[(lane & 15) * NX + 4 * j + (lane >> 4)]);
+  }
   const int t0 = (int)((long long)sb * ntau / nslab);
   const int t1 = (int)((long long)(sb + 1) * ntau / nslab);  // exclusive
   const long long rbase = (long long)r * ntau * V;
@@ -445,7 +511,10 @@ __global__ void __launch_bounds__(NX * NX)
     }
   }
   if (DIR < 0) scale_field<R, NX>(b.pre, th * V * FS, fo, X);
-  slice_T3<R, NX, 0, true>(cc, lds, l, X);
+  if constexpr (TR != 0)
+    slice_T3_mfma16(cc, ta, lds, l, X);
+  else
+    slice_T3<R, NX, 0, true>(cc, lds, l, X);
   for (int k = 0; k < count; ++k) {
     const int t = tfirst + k * step;
     const int so = t * V * ES;  // slice byte offset (uniform)
@@ -567,7 +636,10 @@ __global__ void __launch_bounds__(NX * NX)
     if (k + 1 < count) {
       // transform source slice t for the next output slice
       if (DIR < 0) scale_field<R, NX>(b.pre, t * V * FS, fo, X);
-      slice_T3<R, NX, 0, true>(cc, lds, l, X);
+      if constexpr (TR != 0)
+        slice_T3_mfma16(cc, ta, lds, l, X);
+      else
+        slice_T3<R, NX, 0, true>(cc, lds, l, X);
     }
   }
   if (RED != 0) {
@@ -600,16 +672,16 @@ __global__ void __launch_bounds__(NX * NX)
   }
 }
 
-template <typename R, int NX, int DIR, bool GENERAL, int SRC, int RED>
+template <typename R, int NX, int DIR, bool GENERAL, int SRC, int RED, int TR = 0>
 int launch_one(const Lattice& L, const HopArgs<R>& a, const SplitCoef<R, NX>& c, dim3 grid,
                size_t lds, int nslab) {
   static bool attr = false;
   if (!attr) {
-    UFG_HIP(hipFuncSetAttribute((const void*)hop_stream_kernel<R, NX, DIR, GENERAL, SRC, RED>,
+    UFG_HIP(hipFuncSetAttribute((const void*)hop_stream_kernel<R, NX, DIR, GENERAL, SRC, RED, TR>,
                                 hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
     attr = true;
   }
-  hipLaunchKernelGGL((hop_stream_kernel<R, NX, DIR, GENERAL, SRC, RED>), grid, dim3(NX * NX),
+  hipLaunchKernelGGL((hop_stream_kernel<R, NX, DIR, GENERAL, SRC, RED, TR>), grid, dim3(NX * NX),
                      lds, L.stream, a, c, L.ntau, nslab, stream_group(L), stream_inner(L));
   UFG_HIP(hipGetLastError());
   return UFG_OK;
@@ -633,7 +705,12 @@ int launch_dir(const Lattice& L, const HopArgs<R>& a, const SplitCoef<R, NX>& c)
     return launch_one<R, NX, DIR, true, 0, 0>(L, a, c, grid, lds, nslab);
   if (a.src_mode == 0 && !general) {
     switch (a.red_mode) {
-      case 0: return launch_one<R, NX, DIR, false, 0, 0>(L, a, c, grid, lds, nslab);
+      case 0:
+        if constexpr (sizeof(R) == 4 && NX == 16) {
+          if (L.t3_route == 1)
+            return launch_one<R, NX, DIR, false, 0, 0, 1>(L, a, c, grid, lds, nslab);
+        }
+        return launch_one<R, NX, DIR, false, 0, 0>(L, a, c, grid, lds, nslab);
       case 1: return launch_one<R, NX, DIR, false, 0, 1>(L, a, c, grid, lds, nslab);
       case 2: return launch_one<R, NX, DIR, false, 0, 2>(L, a, c, grid, lds, nslab);
       case 3: return launch_one<R, NX, DIR, false, 0, 3>(L, a, c, grid, lds, nslab);

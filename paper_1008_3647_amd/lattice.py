@@ -198,14 +198,16 @@ class Lattice:
         L.check(code, "solve_bicgstab")
         return x, st.as_dict()
 
-    def tune(self, slab=0, vec_blocks=0, nslab=0, xcd_group=-1, rhs_inner=False):
+    def tune(self, slab=0, vec_blocks=0, nslab=0, xcd_group=-1, rhs_inner=False, transform=0):
         """Launch parameters (0 = library default, xcd_group -1 = default); see
-        lattice_tune, lattice_tune_slabs and lattice_tune_order in ufg.h (nslab,
-        when given, overrides slab)."""
+        lattice_tune, lattice_tune_slabs, lattice_tune_order and
+        lattice_tune_transform in ufg.h (nslab, when given, overrides slab)."""
         L.check(self._lib.lattice_tune(self._h, int(slab), int(vec_blocks)), "lattice_tune")
         L.check(self._lib.lattice_tune_slabs(self._h, int(nslab)), "lattice_tune_slabs")
         L.check(self._lib.lattice_tune_order(self._h, int(xcd_group), int(bool(rhs_inner))),
                 "lattice_tune_order")
+        L.check(self._lib.lattice_tune_transform(self._h, int(transform)),
+                "lattice_tune_transform")
 
     def _real_field(self, t, name):
         if not isinstance(t, torch.Tensor) or t.device.type != "cuda":

@@ -277,3 +277,38 @@ def test_largest_rhs_blocks(ntau):
     del y, yd, xd
     L.close()
     torch.cuda.empty_cache()
+
+
+@pytest.mark.parametrize("ntau,nrhs,slab", [(6, 2, 0), (23, 3, 2), (400, 8, 0)])
+def test_mfma_transform_route(ntau, nrhs, slab):
+    """lattice_tune_transform(1): the y and x stages of T^3 on 16x16x4 MFMA
+    (complex64, Nx = 16). The oracle's operator within the complex64
+    tolerance, and the VALU route's output within 2e-6 relative (FP32 sums in a
+    different order); the full 16^3 x 400 launch on sampled slices; route 0 is
+    restored bit for bit afterwards."""
+    require_gpu()
+    from paper_1008_3647_amd import Lattice
+    nx = 16
+    sigma = sigma_field(nx, ntau, 470 + ntau)
+    x = gaussian_rhs(nx, ntau, range(480, 480 + nrhs))
+    L = Lattice(nx, ntau, TAU, G, torch.complex64)
+    L.set_aux_field(to_dev(sigma))
+    xd = to_dev(x, torch.complex64)
+    L.tune(slab, 0, transform=0)
+    y0, yd0 = to_host(L.apply_M(xd)), to_host(L.apply_Mdag(xd))
+    L.tune(slab, 0, transform=1)
+    y1, yd1 = to_host(L.apply_M(xd)), to_host(L.apply_Mdag(xd))
+    say(f"MFMA route ntau={ntau}: |M diff| {rel_err(y1, y0):.1e}, |M^T diff| {rel_err(yd1, yd0):.1e}")
+    assert rel_err(y1, y0) < 2e-6 and rel_err(yd1, yd0) < 2e-6
+    xin = x.astype(np.complex64).astype(np.complex128)
+    ts = range(ntau) if ntau <= 23 else (0, 1, 199, 200, ntau - 1)
+    for k in (range(nrhs) if ntau <= 23 else (0, nrhs - 1)):
+        Mx = oracle.apply_M(xin[k], sigma, TAU, G)
+        Mdx = oracle.apply_Mdag(xin[k], sigma, TAU, G)
+        for t in ts:
+            assert rel_err(y1[k, t], Mx[t]) < TOL[torch.complex64], (k, t)
+            assert rel_err(yd1[k, t], Mdx[t]) < TOL[torch.complex64], (k, t)
+    L.tune(slab, 0, transform=0)
+    assert np.array_equal(to_host(L.apply_M(xd)), y0)
+    with pytest.raises(Exception):
+        L.tune(slab, 0, transform=2)
