@@ -946,6 +946,23 @@ def main():
             res["apply_M_hbm_mfma_transform"] = dict(us=round(ms * 1e3, 2),
                                                      GBs=round(alg / ms / 1e6, 1))
             Lm.tune(transform=0)
+        if not a.no_tune:
+            # the plain operator's own tuned shape (slab, numbering, T^3 route),
+            # next to the library default that the roofline line reports
+            from paper_1008_3647_amd.autotune import tune_apply
+            tn = tune_apply(Lm, xs, launches=2 * ROT, reps=2)
+            for i in range(2 * ROT):
+                Lm.apply_M(xs[i % ROT], ys[i % ROT])
+            e0.record()
+            for i in range(a.mv_launches):
+                Lm.apply_M(xs[i % ROT], ys[i % ROT])
+            e1.record()
+            torch.cuda.synchronize()
+            ms = e0.elapsed_time(e1) / a.mv_launches
+            res["apply_M_hbm_tuned"] = dict(
+                us=round(ms * 1e3, 2), GBs=round(alg / ms / 1e6, 1),
+                shape={k: tn[k] for k in ("slab", "xcd_group", "rhs_inner", "transform")},
+                candidates=len(tn["candidates"]))
         res["alg_bytes"] = alg
         mv["c64" if dt == torch.complex64 else "c128"] = res
         if dt == torch.complex64:

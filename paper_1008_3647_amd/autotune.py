@@ -2,8 +2,14 @@
 
 tune(): per lattice, the slab size and workgroup numbering of the streaming
 M / M^T kernels and the workgroups per right-hand side of the Krylov vector
-kernels. tune_batched():
+kernels. tune_apply(): the launch shape of the plain operator (apply_M or
+apply_Mdag) including the route of the T^3 transform. tune_batched():
 the persistent launch shape of solve_batched for a set of problems.
+
+The workgroup size of the streaming kernels is not a knob: one thread owns one
+z-line of an Nx^3 slice (Nx^2 threads), which the transform's three stages are
+built on. Right-hand sides per workgroup follow from the numbering: with
+rhs_inner an XCD takes every rhs of a slab group in turn.
 
 Each candidate is timed on the real workload: a BiCGStab run of a fixed number
 of iterations (tolerance unreachable, so every candidate does identical work)
@@ -120,6 +126,51 @@ def tune(L: Lattice, b: torch.Tensor, mixed=False, op="M", iters=16, reps=2,
         data[key] = choice
         _store(cache, data)
     return dict(choice, cached=False, candidates=results)
+
+
+def tune_apply(L: Lattice, x, dagger=False, launches=20, reps=3, orders=ORDERS,
+               transforms=None, verbose=False):
+    """Pick the launch shape of the plain operator (apply_M, or apply_Mdag with
+    dagger=True) on `x` (a tensor, or a list of tensors that the timed
+    launches cycle through, e.g. to keep the operands out of the Infinity
+    Cache): slices per slab, workgroup numbering and, for complex64 on
+    Nx = 16, the transform route (0: VALU block form, 1: y and x stages on
+    MFMA; see lattice_tune_transform). Each candidate is timed over `launches`
+    back-to-back applications between two synchronisations (best of `reps`);
+    the best is applied with Lattice.tune and returned with the timings of
+    every candidate."""
+    fn = L.apply_Mdag if dagger else L.apply_M
+    xs = list(x) if isinstance(x, (list, tuple)) else [x]
+    ys = [torch.empty_like(v) for v in xs]
+    x = xs[0]
+    if transforms is None:
+        transforms = (0, 1) if (x.dtype == torch.complex64 and L.nx == 16) else (0,)
+    streaming = L.nx in (8, 12, 16)
+    results = []
+    for slab in candidate_slabs(L):
+        for grp, ri in (orders if streaming else ((0, False),)):
+            for tr in transforms:
+                L.tune(slab, 0, xcd_group=grp, rhs_inner=ri, transform=tr)
+                for i in range(len(xs)):  # warm-up
+                    fn(xs[i], ys[i])
+                best_t = float("inf")
+                for _ in range(reps):
+                    torch.cuda.synchronize()
+                    t0 = time.perf_counter()
+                    for i in range(launches):
+                        fn(xs[i % len(xs)], ys[i % len(xs)])
+                    torch.cuda.synchronize()
+                    best_t = min(best_t, (time.perf_counter() - t0) / launches)
+                results.append(dict(slab=slab, xcd_group=grp, rhs_inner=ri, transform=tr,
+                                    seconds=best_t))
+                if verbose:
+                    print(f"tune_apply slab={slab} group={grp} rhs_inner={ri} transform={tr}: "
+                          f"{best_t * 1e6:.1f} us", flush=True)
+    best = min(results, key=lambda d: d["seconds"])
+    L.tune(best["slab"], 0, xcd_group=best["xcd_group"], rhs_inner=best["rhs_inner"],
+           transform=best["transform"])
+    choice = {k: best[k] for k in ("slab", "xcd_group", "rhs_inner", "transform", "seconds")}
+    return dict(choice, candidates=results)
 
 
 def tune_batched(lattices, bs, mixed=True, iters=10, reps=2, hop_blocks=(2, 4, 8),

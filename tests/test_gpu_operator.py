@@ -312,3 +312,32 @@ def test_mfma_transform_route(ntau, nrhs, slab):
     assert np.array_equal(to_host(L.apply_M(xd)), y0)
     with pytest.raises(Exception):
         L.tune(slab, 0, transform=2)
+
+
+@pytest.mark.parametrize("dtype", [torch.complex64, torch.complex128])
+def test_tune_apply(dtype):
+    """autotune.tune_apply: every (slab, numbering[, T^3 route]) candidate is
+    timed on the plain operator, the best is applied, and apply_M / apply_Mdag
+    under the chosen shape match the oracle on every slice."""
+    require_gpu()
+    from paper_1008_3647_amd import Lattice
+    from paper_1008_3647_amd.autotune import tune_apply, candidate_slabs, ORDERS
+    nx, ntau, nrhs = 16, 12, 2
+    sigma = sigma_field(nx, ntau, 490)
+    x = gaussian_rhs(nx, ntau, [491, 492])
+    L = Lattice(nx, ntau, TAU, G, dtype)
+    L.set_aux_field(to_dev(sigma))
+    xd = to_dev(x, dtype)
+    xs = [xd, xd.clone()]
+    for dagger in (False, True):
+        t = tune_apply(L, xs, dagger=dagger, launches=4, reps=1)
+        nt = 2 if dtype == torch.complex64 else 1
+        assert len(t["candidates"]) == len(candidate_slabs(L)) * len(ORDERS) * nt
+        assert (t["xcd_group"], t["rhs_inner"]) in ORDERS and t["transform"] in range(nt)
+        say(f"tune_apply {dtype} dagger={dagger}: "
+            f"{ {k: t[k] for k in ('slab', 'xcd_group', 'rhs_inner', 'transform')} }")
+        y = to_host(L.apply_Mdag(xd) if dagger else L.apply_M(xd))
+        xin = x.astype(np.complex64).astype(np.complex128) if dtype == torch.complex64 else x
+        for k in range(nrhs):
+            ref = (oracle.apply_Mdag if dagger else oracle.apply_M)(xin[k], sigma, TAU, G)
+            assert rel_err(y[k], ref) < TOL[dtype], (dagger, k)
