@@ -38,7 +38,7 @@ def gradient(X, sigma, tau, g, disp="free"):
     out = np.empty_like(sigma)
     for t in range(ntau):
         s = 1.0 if t == ntau - 1 else -1.0
-        Ty = apply_expK(MX[(t + 1) % ntau], tau, disp)
+        Ty = apply_expK(MX[(t + 1) % ntau], tau, disp, sigma.ndim - 1)
         out[t] = -2.0 * A * np.cos(sigma[t]) * s * np.real(X[t] * np.conj(Ty))
     return out
 
@@ -54,15 +54,15 @@ def exact_difference(phi_y, sigma, tau, g, site, h, solve_MdagT_unit):
     ``solve_MdagT_unit(site)`` returns z (real). ``phi_y`` is y.
     """
     A = coupling_A(tau, g)
-    ntau, nx = sigma.shape[0], sigma.shape[-1]
+    ntau, nx, d = sigma.shape[0], sigma.shape[-1], sigma.ndim - 1
     t, n = site
     s = 1.0 if t == ntau - 1 else -1.0
     flat = sigma[t].reshape(-1)
     db = A * (np.sin(flat[n] + h) - np.sin(flat[n]))
-    e_n = np.zeros(nx ** 3)
+    e_n = np.zeros(nx ** d)
     e_n[n] = 1.0
-    col = apply_expK(e_n.reshape(nx, nx, nx), tau).real.reshape(-1)
-    a = np.zeros((ntau, nx ** 3))
+    col = apply_expK(e_n.reshape((nx,) * d), tau, "free", d).real.reshape(-1)
+    a = np.zeros((ntau, nx ** d))
     a[(t + 1) % ntau] = s * db * col
     a = a.reshape(sigma.shape)
     z = solve_MdagT_unit(site)

@@ -23,30 +23,32 @@ def _frequencies(ntau: int) -> np.ndarray:
     return 2.0 * np.pi * np.fft.fftfreq(ntau) + np.pi / ntau
 
 
-def free_spectrum(nx: int, ntau: int, tau: float) -> np.ndarray:
-    """Eigenvalues of M0: 1 - exp(-i omega) exp(-tau E(k)) on the 4D grid."""
-    lam = kinetic_symbol(nx, tau)
+def free_spectrum(nx: int, ntau: int, tau: float, dim: int = 3) -> np.ndarray:
+    """Eigenvalues of M0: 1 - exp(-i omega) exp(-tau E(k)) on the (1 + dim)D grid."""
+    lam = kinetic_symbol(nx, tau, "free", dim)
     w = _frequencies(ntau)
-    return 1.0 - np.exp(-1j * w)[:, None, None, None] * lam[None]
+    return 1.0 - np.exp(-1j * w).reshape((ntau,) + (1,) * dim) * lam[None]
 
 
 def _apply_symbol(v, tau, adjoint):
-    ntau, nx = v.shape[0], v.shape[-1]
+    ntau, nx, dim = v.shape[0], v.shape[-1], v.ndim - 1
     t = np.arange(ntau)
-    twist = np.exp(-1j * np.pi * t / ntau)[:, None, None, None]
-    sym = free_spectrum(nx, ntau, tau)
+    twist = np.exp(-1j * np.pi * t / ntau).reshape((ntau,) + (1,) * dim)
+    sym = free_spectrum(nx, ntau, tau, dim)
     if adjoint:
         # M0^T shifts the other way in time, u_t - e^{-tau K} u_{t+1}; under
         # the same twist its symbol is 1 - exp(+i omega) exp(-tau E(k)),
         # the complex conjugate of M0's symbol.
         sym = np.conj(sym)
-    vt = np.fft.fftn(v * twist, axes=(0, 1, 2, 3))
-    ut = np.fft.ifftn(vt / sym, axes=(0, 1, 2, 3))
+    axes = tuple(range(dim + 1))
+    vt = np.fft.fftn(v * twist, axes=axes)
+    ut = np.fft.ifftn(vt / sym, axes=axes)
     return ut / twist
 
 
 def apply_M0inv(v: np.ndarray, tau: float) -> np.ndarray:
-    """u = M0^{-1} v via the antiperiodic 4D Fourier transform (paper, Sec. 3)."""
+    """u = M0^{-1} v via the antiperiodic (1 + d)-dimensional Fourier transform
+    (paper, Sec. 3; 4D for d = 3); v is one vector [Ntau][Nx]^d."""
     return _apply_symbol(np.asarray(v, dtype=np.complex128), tau, adjoint=False)
 
 

@@ -9,9 +9,10 @@ iid uniform on [-pi, pi] per space-time site; right-hand sides are complex
 Gaussian vectors (Re and Im iid N(0, 1/2), the heat-bath law exp(-eta^H eta)).
 All generators use numpy's PCG64 (``numpy.random.default_rng``).
 
-Array layouts (C order):
-  sigma : float64 [ntau][nx][nx][nx]
-  rhs   : complex128 [nrhs][ntau][nx][nx][nx]
+Array layouts (C order), spatial dimension dim = 3 by default (1 and 2 for
+the lower-dimensional lattices):
+  sigma : float64 [ntau][nx]^dim
+  rhs   : complex128 [nrhs][ntau][nx]^dim
 """
 from __future__ import annotations
 
@@ -29,32 +30,33 @@ __all__ = [
 ]
 
 
-def sigma_field(nx: int, ntau: int, seed: int) -> np.ndarray:
+def sigma_field(nx: int, ntau: int, seed: int, dim: int = 3) -> np.ndarray:
     """Auxiliary field, iid uniform on [-pi, pi] per site (paper, Sec. 5)."""
     rng = np.random.default_rng(seed)
-    return rng.uniform(-np.pi, np.pi, size=(ntau, nx, nx, nx))
+    return rng.uniform(-np.pi, np.pi, size=(ntau,) + (nx,) * dim)
 
 
-def gaussian_rhs(nx: int, ntau: int, seeds) -> np.ndarray:
+def gaussian_rhs(nx: int, ntau: int, seeds, dim: int = 3) -> np.ndarray:
     """Complex Gaussian right-hand sides, one seed per RHS.
 
     Re and Im are iid N(0, 1/2) so that the density is proportional to
     exp(-|eta|^2), the pseudofermion heat-bath law (paper, Sec. 1).
     """
     seeds = list(seeds)
-    out = np.empty((len(seeds), ntau, nx, nx, nx), dtype=np.complex128)
+    shape = (ntau,) + (nx,) * dim
+    out = np.empty((len(seeds),) + shape, dtype=np.complex128)
     for i, s in enumerate(seeds):
         rng = np.random.default_rng(s)
-        re = rng.standard_normal((ntau, nx, nx, nx))
-        im = rng.standard_normal((ntau, nx, nx, nx))
+        re = rng.standard_normal(shape)
+        im = rng.standard_normal(shape)
         out[i] = (re + 1j * im) / np.sqrt(2.0)
     return out
 
 
-def gaussian_momenta(nx: int, ntau: int, seed: int) -> np.ndarray:
+def gaussian_momenta(nx: int, ntau: int, seed: int, dim: int = 3) -> np.ndarray:
     """MD momenta pi ~ N(0, 1) per site (paper, Sec. 1, MD Hamiltonian)."""
     rng = np.random.default_rng(seed)
-    return rng.standard_normal((ntau, nx, nx, nx))
+    return rng.standard_normal((ntau,) + (nx,) * dim)
 
 
 def uniform_draws(seed: int, count: int) -> np.ndarray:
