@@ -11,7 +11,8 @@
  *
  * Conventions shared by every entry point
  *   - Vectors are complex, interleaved (re, im), C order [nrhs][Ntau][Nx][Nx][Nx]
- *     (x fastest). Element type is complex64 (float2) or complex128 (double2)
+ *     (x fastest; [nrhs][Ntau][Nx]^dim and fields [Ntau][Nx]^dim on lattices
+ *     made by create_lattice_dim). Element type is complex64 (float2) or complex128 (double2)
  *     as fixed by the lattice's dtype; "mixed" solves take complex128.
  *   - Every vector and field pointer is a DEVICE pointer owned by the caller;
  *     it must stay valid until the call's work has completed on the stream.
@@ -162,6 +163,21 @@ int create_lattice(int nx, int ntau, double tau, double g, int dtype,
  */
 int create_lattice_ex(int nx, int ntau, double tau, double g, int dtype, int dispersion,
                       void* hip_stream, ufg_lattice* out);
+
+/*
+ * create_lattice_dim -- create_lattice_ex for a lattice of spatial dimension
+ *   dim = 1, 2 or 3 (the lower dimensions the paper's concluding section
+ *   names as an extension): slices of Nx^dim sites, exp(-tau K) the product
+ *   of dim factors T, E(k) summed over dim axes (Sec. 1 otherwise unchanged).
+ *   Vectors are [nrhs][Ntau][Nx]^dim and sigma [Ntau][Nx]^dim, C order.
+ *   dim = 3 is create_lattice_ex. On dim < 3 every operator, preconditioner,
+ *   solver, the force and the HMC calls apply (through the general slice
+ *   kernels; the streaming kernels and fused BiCGStab forms are for dim = 3);
+ *   solve_batched takes dim = 3 only. Errors as create_lattice_ex, and
+ *   UFG_EINVAL for another dim.
+ */
+int create_lattice_dim(int nx, int ntau, int dim, double tau, double g, int dtype,
+                       int dispersion, void* hip_stream, ufg_lattice* out);
 
 /* destroy_lattice -- free the handle and all library-owned device memory. */
 int destroy_lattice(ufg_lattice L);

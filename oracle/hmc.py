@@ -28,7 +28,7 @@ from .force import gradient
 
 
 def heat_bath(eta, sigma, tau, g):
-    """phi_r = M^dagger eta_r for every pseudofermion r (eta: [nphi][Ntau][Nx]^3)."""
+    """phi_r = M^dagger eta_r for every pseudofermion r (eta: [nphi][Ntau][Nx]^d)."""
     return np.stack([apply_Mdag(e, sigma, tau, g) for e in eta])
 
 

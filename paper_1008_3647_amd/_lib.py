@@ -71,6 +71,8 @@ _P = C.c_void_p
 _SIGNATURES = {
     "create_lattice_ex": (C.c_int, [C.c_int, C.c_int, C.c_double, C.c_double, C.c_int, C.c_int,
                                     _P, C.POINTER(_P)]),
+    "create_lattice_dim": (C.c_int, [C.c_int, C.c_int, C.c_int, C.c_double, C.c_double,
+                                     C.c_int, C.c_int, _P, C.POINTER(_P)]),
     "create_lattice": (C.c_int, [C.c_int, C.c_int, C.c_double, C.c_double, C.c_int, _P,
                                  C.POINTER(_P)]),
     "destroy_lattice": (C.c_int, [_P]),

@@ -17,7 +17,7 @@ BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libufg.so")
 SOURCES = ["api.cpp", "ops.cpp", "solvers.cpp", "split.cpp", "batched.hip", "hop.hip",
            "hop_stream.hip", "temporal.hip", "krylov.hip", "noalloc.hip",
-           "hmc.hip"]
+           "hmc.hip", "lowd.hip"]
 ARCH = "gfx950"
 
 

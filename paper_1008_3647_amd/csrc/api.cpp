@@ -211,7 +211,13 @@ int create_lattice(int nx, int ntau, double tau, double g, int dtype, void* hip_
 
 int create_lattice_ex(int nx, int ntau, double tau, double g, int dtype, int dispersion,
                       void* hip_stream, ufg_lattice* out) {
+  return create_lattice_dim(nx, ntau, 3, tau, g, dtype, dispersion, hip_stream, out);
+}
+
+int create_lattice_dim(int nx, int ntau, int dim, double tau, double g, int dtype,
+                       int dispersion, void* hip_stream, ufg_lattice* out) {
   UFG_CHECK(out != nullptr, "create_lattice: out is NULL");
+  UFG_CHECK(dim >= 1 && dim <= 3, "create_lattice: dim must be 1, 2 or 3");
   UFG_CHECK(dispersion == UFG_DISP_FREE || dispersion == UFG_DISP_HUBBARD,
             "create_lattice: dispersion must be UFG_DISP_FREE or UFG_DISP_HUBBARD");
   *out = nullptr;
@@ -224,7 +230,8 @@ int create_lattice_ex(int nx, int ntau, double tau, double g, int dtype, int dis
   if (!L) return UFG_ENOMEM;
   L->nx = nx;
   L->ntau = ntau;
-  L->V = nx * nx * nx;
+  L->dim = dim;
+  L->V = dim == 1 ? nx : dim == 2 ? nx * nx : nx * nx * nx;
   L->N = (long long)L->V * ntau;
   L->tau = tau;
   L->g = g;
@@ -262,14 +269,16 @@ int create_lattice_ex(int nx, int ntau, double tau, double g, int dtype, int dis
     set_error("create_lattice: eigenbasis check failed");
     return UFG_EHIP;
   }
-  if (split_coefficients(nx, L->T_host, &L->split_host) > 1e-13) {
+  // block forms of T and U serve the streaming kernels (three-dimensional
+  // slices); lower dimensions use the general slice kernels with T and U
+  if (dim == 3 && split_coefficients(nx, L->T_host, &L->split_host) > 1e-13) {
     free_fields(*L);
     delete L;
     set_error("create_lattice: block form of T failed its check");
     return UFG_EHIP;
   }
-  if (mode_split_coefficients(nx, L->U_host, &L->mode_fwd_host, &L->mode_bwd_host,
-                              &L->mode_perm) > 1e-12) {
+  if (dim == 3 && mode_split_coefficients(nx, L->U_host, &L->mode_fwd_host,
+                                          &L->mode_bwd_host, &L->mode_perm) > 1e-12) {
     free_fields(*L);
     delete L;
     set_error("create_lattice: block form of the eigenbasis failed its check");
@@ -283,10 +292,13 @@ int create_lattice_ex(int nx, int ntau, double tau, double g, int dtype, int dis
   std::vector<double> Ut(nx * nx), lam3(L->V);
   for (int i = 0; i < nx; ++i)
     for (int j = 0; j < nx; ++j) Ut[i * nx + j] = L->U_host[j * nx + i];
-  for (int z = 0; z < nx; ++z)
-    for (int y = 0; y < nx; ++y)
-      for (int x = 0; x < nx; ++x)
-        lam3[(z * nx + y) * nx + x] = lam1m[z] * lam1m[y] * lam1m[x];
+  // eigenvalue of the mode product: one factor per axis (site index
+  // (z nx + y) nx + x; the leading axes are absent in lower dimensions)
+  for (int i = 0; i < L->V; ++i) {
+    double v = 1.0;
+    for (int k = 0, rest = i; k < dim; ++k, rest /= nx) v *= lam1m[rest % nx];
+    lam3[i] = v;
+  }
   int rc = UFG_OK;
   if (!rc) rc = upload<double>(L->stream, L->f64.T, L->T_host);
   if (!rc) rc = upload<float>(L->stream, L->f32.T, L->T_host);

@@ -1079,6 +1079,7 @@ int solve_batched_impl(const ufg_lattice* Ls, int nprob, const void* const* b, v
     L[i] = reinterpret_cast<Lattice*>(Ls[i]);
     UFG_CHECK(L[i] != nullptr, "solve_batched: NULL lattice");
     UFG_CHECK(L[i]->dtype == UFG_C128, "solve_batched: lattices must be complex128");
+    UFG_CHECK(L[i]->dim == 3, "solve_batched: lattices must be three-dimensional");
     UFG_CHECK(nrhs[i] >= 1, "solve_batched: nrhs must be >= 1");
     UFG_CHECK(b[i] && x[i] && b[i] != x[i], "solve_batched: bad vectors");
     UFG_CHECK(L[i]->device == L[0]->device, "solve_batched: lattices on different devices");

@@ -233,6 +233,7 @@ int launch_force_nx(const Lattice& L, const C2<R>* X, const C2<R>* y, int nrhs, 
 
 template <typename R>
 int launch_hop(const Lattice& L, const HopArgs<R>& a) {
+  if (L.dim < 3) return launch_hop_lowd<R>(L, a);
   // M and M^T with the kinetic factor T go through the streaming kernel
   if (a.shift != 0 && a.mat == fields<R>(L).T && (a.id == nullptr || a.id == a.src) &&
       stream_supported(L))
@@ -248,6 +249,7 @@ int launch_hop(const Lattice& L, const HopArgs<R>& a) {
 }
 
 int hop_blocks_per_rhs(const Lattice& L) {
+  if (L.dim < 3) return lowd_blocks_per_rhs(L);
   if (stream_supported(L)) return stream_nslab(L);
   int spw = 256 / (L.nx * L.nx);
   if (spw < 1) spw = 1;
@@ -256,6 +258,7 @@ int hop_blocks_per_rhs(const Lattice& L) {
 
 template <typename R>
 int launch_force(const Lattice& L, const C2<R>* X, const C2<R>* y, int nrhs, double* grad) {
+  if (L.dim < 3) return launch_force_lowd<R>(L, X, y, nrhs, grad);
 #define CALL_F(NX) launch_force_nx<R, NX>(L, X, y, nrhs, grad)
   UFG_NX_SWITCH(L.nx, CALL_F)
 #undef CALL_F

@@ -85,7 +85,8 @@ struct FlagMirror {
 struct Lattice {
   int nx = 0, ntau = 0, dtype = UFG_C128;
   int dispersion = UFG_DISP_FREE;
-  int V = 0;        // nx^3
+  int dim = 3;      // spatial dimension (1, 2 or 3)
+  int V = 0;        // nx^dim
   long long N = 0;  // V * ntau
   double tau = 0, g = 0, A = 0;
   hipStream_t stream = nullptr;
@@ -198,6 +199,14 @@ struct HopArgs {
 template <typename R>
 int launch_hop(const Lattice& L, const HopArgs<R>& a);
 int hop_blocks_per_rhs(const Lattice& L);
+
+// Slice operator and force of lattices of spatial dimension 1 and 2
+// (lowd.hip); launch_hop, hop_blocks_per_rhs and launch_force route there.
+template <typename R>
+int launch_hop_lowd(const Lattice& L, const HopArgs<R>& a);
+int lowd_blocks_per_rhs(const Lattice& L);
+template <typename R>
+int launch_force_lowd(const Lattice& L, const C2<R>* X, const C2<R>* y, int nrhs, double* grad);
 
 // Force contraction: grad(n,t) = c(n,t) s_t sum_r Re[X_t conj((T^3 y_{t+1}))],
 // c = -2 A cos sigma.

@@ -24,29 +24,35 @@ def _stream_ptr(stream=None):
 
 
 class Lattice:
-    """Nx^3 x Ntau lattice with field sigma (paper, Sec. 1).
+    """Nx^3 x Ntau lattice with field sigma (paper, Sec. 1); Nx^dim x Ntau for
+    dim = 1 or 2 (the lower dimensions of the paper's conclusions).
 
     dtype: torch.complex64 or torch.complex128 (the vector type of apply_* and
     of plain solves; mixed-precision solves need complex128).
     dispersion: "free" (E = k^2/2, the paper's) or "hubbard" (E = 1 - cos k per
     axis; C ABI create_lattice_ex).
+    dim: spatial dimension (C ABI create_lattice_dim); vectors are
+    [nrhs][Ntau][Nx]^dim.
     """
 
     def __init__(self, nx, ntau, tau=0.05, g=5.0, dtype=torch.complex128, stream=None,
-                 dispersion="free"):
+                 dispersion="free", dim=3):
         self._lib = L.load()
         if dtype not in (torch.complex64, torch.complex128):
             raise ValueError("dtype must be torch.complex64 or torch.complex128")
         if dispersion not in L.DISPERSIONS:
             raise ValueError(f"dispersion must be one of {sorted(L.DISPERSIONS)}")
+        if dim not in (1, 2, 3):
+            raise ValueError("dim must be 1, 2 or 3")
         self.nx, self.ntau, self.tau, self.g, self.dtype = nx, ntau, tau, g, dtype
         self.dispersion = dispersion
+        self.dim = int(dim)
         self.device = torch.device("cuda", torch.cuda.current_device())
         h = C.c_void_p()
-        code = self._lib.create_lattice_ex(nx, ntau, tau, g,
-                                           L.UFG_C128 if dtype == torch.complex128 else L.UFG_C64,
-                                           L.DISPERSIONS[dispersion], _stream_ptr(stream),
-                                           C.byref(h))
+        code = self._lib.create_lattice_dim(nx, ntau, self.dim, tau, g,
+                                            L.UFG_C128 if dtype == torch.complex128 else L.UFG_C64,
+                                            L.DISPERSIONS[dispersion], _stream_ptr(stream),
+                                            C.byref(h))
         L.check(code, "create_lattice")
         self._h = h
         A = C.c_double()
@@ -57,7 +63,7 @@ class Lattice:
     # ------------------------------------------------------------------ utils
     @property
     def shape(self):
-        return (self.ntau, self.nx, self.nx, self.nx)
+        return (self.ntau,) + (self.nx,) * self.dim
 
     def _vec(self, x, name, dtype=None):
         dtype = dtype or self.dtype
@@ -67,9 +73,9 @@ class Lattice:
             raise TypeError(f"{name} must have dtype {dtype}, got {x.dtype}")
         if not x.is_contiguous():
             raise ValueError(f"{name} must be contiguous")
-        if tuple(x.shape[-4:]) != self.shape:
+        if x.dim() < len(self.shape) or tuple(x.shape[-len(self.shape):]) != self.shape:
             raise ValueError(f"{name} must end in shape {self.shape}, got {tuple(x.shape)}")
-        return x.numel() // (self.ntau * self.nx ** 3)
+        return x.numel() // (self.ntau * self.nx ** self.dim)
 
     def _like(self, t, ref, name):
         """`t` must be a contiguous CUDA tensor of ref's dtype, shape and device
