@@ -49,7 +49,7 @@ def parse():
                     help="skip the launch-shape autotuner (run before the timed region)")
     ap.add_argument("--report",
                     choices=["config2", "batched", "batched_solve", "force", "mv_sweep",
-                             "tables", "thermalize"],
+                             "tables", "thermalize", "lowdim"],
                     help="print the measurement table of another workload (markdown) "
                          "instead of the JSON line")
     ap.add_argument("--mv-only", action="store_true",
@@ -756,6 +756,85 @@ def report_mv_sweep(a):
     return 0
 
 
+def report_lowdim(a):
+    """Lattices of spatial dimension 1 and 2: apply_M / apply_Mdag bandwidth
+    (rotating distinct buffers, library-default launch shape), and the
+    FP32-refined two-step BiCGStab and WCE2-preconditioned solves with the
+    oracle's residual of M^T M x = b for the first rhs."""
+    import numpy as np
+    import torch
+    import oracle
+    from synthetic import sigma_field, gaussian_rhs
+    from paper_1008_3647_amd import Lattice, Precond
+    print("| dim | lattice | rhs | dtype | MB per launch | apply_M us | GB/s | of 8 TB/s "
+          "| apply_Mdag us | GB/s |")
+    print("|---|---|---|---|---|---|---|---|---|---|")
+    for dim, nx, ntau, nrhs in ((1, 16, 4000, 64), (1, 16, 16000, 64), (2, 16, 1000, 8),
+                                (2, 16, 4000, 16), (2, 8, 8000, 16), (3, 16, 400, 8)):
+        N = nx ** dim * ntau
+        sigma = torch.from_numpy(sigma_field(nx, ntau, 7101, dim)).cuda()
+        b = torch.from_numpy(gaussian_rhs(nx, ntau, list(range(7102, 7102 + nrhs)), dim)).cuda()
+        for dt, c, f in ((torch.complex64, 8, 4), (torch.complex128, 16, 8)):
+            L = Lattice(nx, ntau, 0.05, 5.0, dt, dim=dim)
+            L.set_aux_field(sigma)
+            alg = N * (nrhs * 2 * c + f)
+            pair = 2 * N * nrhs * c
+            rot = max(1, min(16, -(-1_250_000_000 // pair)))
+            xs = [b.to(dt).clone() for _ in range(rot)]
+            ys = [torch.empty_like(xs[0]) for _ in range(rot)]
+            res = []
+            for fn in (L.apply_M, L.apply_Mdag):
+                t_end = time.perf_counter() + 0.2
+                i = 0
+                while time.perf_counter() < t_end:
+                    for _ in range(10):
+                        fn(xs[i % rot], ys[i % rot])
+                        i += 1
+                    torch.cuda.synchronize()
+                e0 = torch.cuda.Event(enable_timing=True)
+                e1 = torch.cuda.Event(enable_timing=True)
+                e0.record()
+                for i in range(100):
+                    fn(xs[i % rot], ys[i % rot])
+                e1.record()
+                torch.cuda.synchronize()
+                us = e0.elapsed_time(e1) / 100 * 1e3
+                res.append((us, alg / us / 1e3))
+            name = "c64" if dt == torch.complex64 else "c128"
+            shape = " x ".join([f"{nx}"] * dim) + f" x {ntau}"
+            print(f"| {dim} | {shape} | {nrhs} | {name} | {alg / 1e6:.1f} | {res[0][0]:.1f} | "
+                  f"{res[0][1]:.0f} | {res[0][1] / 8000:.2f} | {res[1][0]:.1f} | "
+                  f"{res[1][1]:.0f} |", flush=True)
+            del xs, ys, L
+            torch.cuda.empty_cache()
+    print()
+    print("| dim | lattice | rhs | solve | status | iterations (step 1 + 2) | seconds "
+          "| relres per step | oracle relres of M^T M x = b (rhs 0) |")
+    print("|---|---|---|---|---|---|---|---|---|")
+    for dim, nx, ntau in ((1, 16, 400), (2, 16, 400), (2, 8, 160)):
+        sig_h = sigma_field(nx, ntau, 7201, dim)
+        b_h = gaussian_rhs(nx, ntau, list(range(7202, 7210)), dim)
+        L = Lattice(nx, ntau, 0.05, 5.0, torch.complex128, dim=dim)
+        L.set_aux_field(torch.from_numpy(sig_h).cuda())
+        bd = torch.from_numpy(b_h).cuda()
+        for name, pc, mixed in (("FP32-refined", None, True), ("FP64", None, False),
+                                ("WCE2, FP32-refined", Precond("wce", wce_order=2), True)):
+            # WCE2 does not converge on the lower-dimensional lattices at g = 5
+            # (its expansion grows, see the design notes): capped at 2000
+            maxit = 2000 if pc is not None else 20000
+            L.solve_bicgstab(bd, "two_step", pc, tol=1e-10, mixed=mixed, maxit=maxit)  # warm-up
+            x, st = L.solve_bicgstab(bd, "two_step", pc, tol=1e-10, mixed=mixed, maxit=maxit)
+            xh = x[0].cpu().numpy()
+            r = b_h[0] - oracle.apply_Q(xh, sig_h, 0.05, 5.0)
+            rel = float(np.linalg.norm(r) / np.linalg.norm(b_h[0]))
+            shape = " x ".join([f"{nx}"] * dim) + f" x {ntau}"
+            print(f"| {dim} | {shape} | 8 | {name} | {st['status']} | {st['iters'][0]} + "
+                  f"{st['iters'][1]} | {st['seconds']:.4f} | {max(st['relres']):.1e} | "
+                  f"{rel:.1e} |", flush=True)
+        L.close()
+    return 0
+
+
 def progress(msg):
     """One line per finished stage of the run (stderr; stdout keeps the JSON line)."""
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
@@ -767,7 +846,7 @@ def main():
         return {"config2": report_config2, "batched": report_batched,
                 "batched_solve": report_batched_solve, "force": report_force,
                 "mv_sweep": report_mv_sweep, "tables": report_tables,
-                "thermalize": report_thermalize}[a.report](a)
+                "thermalize": report_thermalize, "lowdim": report_lowdim}[a.report](a)
     if a.mv_only:
         return mv_only(a)
     if a.gpus != 1:

@@ -3,14 +3,15 @@
 //
 // A slice has Nx (dimension 1) or Nx^2 (dimension 2) sites and exp(-tau K)
 // is T or T (x) T with the same symmetric circulant T as in three dimensions.
-// One thread per site; a 256-thread workgroup takes SPW = 256 / Nx^d slices of
-// one right-hand side. The scaled source slice goes to LDS, each thread forms
-// its output along x as a row of T times the slice row, and in dimension 2 the
-// result goes through LDS once more for the y axis. The epilogue (identity,
-// auxiliary term, complex scaling, fused dot products) is that of the general
-// three-dimensional slice kernel, with the same operand conventions
-// (HopArgs): shift -1 / +1 / 0 for M-type / M^T-type / basis changes, mat the
-// Nx x Nx matrix applied along every axis.
+// One thread per site of SPW = 256 / Nx^d slices of one right-hand side, and
+// four such groups of slices per workgroup, whose loads each thread issues
+// together. The scaled source slices go to LDS, each thread forms its output
+// along x as a row of T (held in registers) times the slice row, and in
+// dimension 2 the result goes through LDS once more for the y axis. The
+// epilogue (identity, auxiliary term, complex scaling, fused dot products) is
+// that of the general three-dimensional slice kernel, with the same operand
+// conventions (HopArgs): shift -1 / +1 / 0 for M-type / M^T-type / basis
+// changes, mat the Nx x Nx matrix applied along every axis.
 #include "hop_common.h"
 
 namespace ufg {
@@ -18,6 +19,8 @@ namespace {
 using namespace hopc;
 
 constexpr int kLowdThreads = 256;
+// slices per thread of the operator kernel (its loads are issued together)
+constexpr int kLowdSlices = 4;
 
 template <int NX, int D>
 struct LowdShape {
@@ -63,50 +66,103 @@ __device__ __forceinline__ C2<R> lowd_transform(const R* __restrict__ mat, C2<R>
 template <typename R, int NX, int D, bool GENERAL>
 __global__ void __launch_bounds__(kLowdThreads) hop_lowd_kernel(HopArgs<R> a, int ntau) {
   using S = LowdShape<NX, D>;
-  constexpr int V = S::V, SPW = S::SPW;
-  __shared__ C2<R> src_lds[SPW * V];
-  __shared__ C2<R> tmp_lds[D == 2 ? SPW * V : 1];
+  constexpr int V = S::V, SPW = S::SPW, KS = kLowdSlices, W = SPW * V;
+  __shared__ C2<R> src_lds[KS][W];
+  __shared__ C2<R> tmp_lds[D == 2 ? KS : 1][D == 2 ? W : 1];
   __shared__ double red_lds[4 * (kLowdThreads / 64)];
-  const int tgroups = (ntau + SPW - 1) / SPW;
+  const int tgroups = (ntau + SPW * KS - 1) / (SPW * KS);
   const int r = blockIdx.x / tgroups;
   const int tg = blockIdx.x - r * tgroups;
   if (a.gate && a.gate[r] == 0) return;  // uniform over the block
 
   const int sub = threadIdx.x / V;
   const int l = threadIdx.x - sub * V;
-  const int t = tg * SPW + sub;
   const bool active = sub < SPW;
-  const bool valid = active && t < ntau;
-  int ts = t + a.shift;
-  if (ts < 0) ts += ntau;
-  if (ts >= ntau) ts -= ntau;
+  const int x = l % NX, y = l / NX, row = l - x;
   const long long rbase = (long long)r * ntau * V;
-
-  C2<R> v = mk<R>(R(0), R(0));
-  if (valid) {
-    v = a.src[rbase + (long long)ts * V + l];
-    if (a.pre) {
-      const R f = a.pre[(long long)ts * V + l];
-      v.x *= f;
-      v.y *= f;
+  // slice k of this workgroup: t = (tg KS + k) SPW + sub, so that for every k
+  // the workgroup reads SPW consecutive slices (one contiguous block)
+  C2<R> v[KS];
+  int ts[KS];
+#pragma unroll
+  for (int k = 0; k < KS; ++k) {
+    const int t = (tg * KS + k) * SPW + sub;
+    int q = t + a.shift;
+    if (q < 0) q += ntau;
+    if (q >= ntau) q -= ntau;
+    ts[k] = q;
+    v[k] = mk<R>(R(0), R(0));
+    if (active && t < ntau) v[k] = a.src[rbase + (long long)q * V + l];
+  }
+  if (a.pre) {
+#pragma unroll
+    for (int k = 0; k < KS; ++k) {
+      const int t = (tg * KS + k) * SPW + sub;
+      if (active && t < ntau) {
+        const R f = a.pre[(long long)ts[k] * V + l];
+        v[k].x *= f;
+        v[k].y *= f;
+      }
     }
   }
-  C2<R>* s = src_lds + (active ? sub : 0) * V;
-  C2<R>* tmp = tmp_lds + (D == 2 && active ? sub * V : 0);
-  if (active) s[l] = v;
+  R mrow[NX], mcol[D == 2 ? NX : 1];
+#pragma unroll
+  for (int j = 0; j < NX; ++j) mrow[j] = a.mat[x * NX + j];
+  if constexpr (D == 2) {
+#pragma unroll
+    for (int j = 0; j < NX; ++j) mcol[j] = a.mat[y * NX + j];
+  }
+  if (active) {
+#pragma unroll
+    for (int k = 0; k < KS; ++k) src_lds[k][sub * V + l] = v[k];
+  }
   __syncthreads();
-  const C2<R> w = lowd_transform<R, NX, D>(a.mat, s, tmp, l, active);
-
-  R sgn = R(1);
-  if (a.shift < 0) sgn = (ts == ntau - 1) ? R(1) : R(-1);
-  if (a.shift > 0) sgn = (t == ntau - 1) ? R(1) : R(-1);
+  // along x: a row of T times the slice row
+  C2<R> w[KS];
+#pragma unroll
+  for (int k = 0; k < KS; ++k) {
+    w[k] = mk<R>(R(0), R(0));
+    if (active) {
+      const C2<R>* sl = &src_lds[k][sub * V + row];
+#pragma unroll
+      for (int j = 0; j < NX; ++j) {
+        w[k].x = fma(mrow[j], sl[j].x, w[k].x);
+        w[k].y = fma(mrow[j], sl[j].y, w[k].y);
+      }
+    }
+  }
+  if constexpr (D == 2) {  // along y
+    if (active) {
+#pragma unroll
+      for (int k = 0; k < KS; ++k) tmp_lds[k][sub * V + l] = w[k];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < KS; ++k) {
+      w[k] = mk<R>(R(0), R(0));
+      if (active) {
+        const C2<R>* sl = &tmp_lds[k][sub * V + x];
+#pragma unroll
+        for (int j = 0; j < NX; ++j) {
+          w[k].x = fma(mcol[j], sl[j * NX].x, w[k].x);
+          w[k].y = fma(mcol[j], sl[j * NX].y, w[k].y);
+        }
+      }
+    }
+  }
 
   double acc0 = 0, acc1 = 0, acc2 = 0, acc3 = 0;
-  if (valid) {
+#pragma unroll
+  for (int k = 0; k < KS; ++k) {
+    const int t = (tg * KS + k) * SPW + sub;
+    if (!(active && t < ntau)) continue;
+    R sgn = R(1);
+    if (a.shift < 0) sgn = (ts[k] == ntau - 1) ? R(1) : R(-1);
+    if (a.shift > 0) sgn = (t == ntau - 1) ? R(1) : R(-1);
     const long long idx = rbase + (long long)t * V + l;
     R f = sgn;
     if (a.post) f *= a.post[(long long)t * V + l];
-    C2<R> base = mk<R>(f * w.x, f * w.y);
+    C2<R> base = mk<R>(f * w[k].x, f * w[k].y);
     if (a.id) {
       const C2<R> i0 = a.id[idx];
       base.x += i0.x;
@@ -183,7 +239,7 @@ int launch_lowd(const Lattice& L, const HopArgs<R>& args) {
   using S = LowdShape<NX, D>;
   HopArgs<R> a = args;
   if (a.beta.x == 0.0 && a.beta.y == 0.0) a.aux = nullptr;  // never read an unused operand
-  const int tgroups = (L.ntau + S::SPW - 1) / S::SPW;
+  const int tgroups = (L.ntau + S::SPW * kLowdSlices - 1) / (S::SPW * kLowdSlices);
   const bool general = (a.alpha.x != 1.0 || a.alpha.y != 0.0 || a.aux != nullptr);
   const dim3 grid(tgroups * a.nrhs), block(kLowdThreads);
   if (general)
@@ -234,8 +290,8 @@ int launch_hop_lowd(const Lattice& L, const HopArgs<R>& a) {
 
 int lowd_blocks_per_rhs(const Lattice& L) {
   const int v = L.dim == 1 ? L.nx : L.nx * L.nx;
-  const int spw = kLowdThreads / v;
-  return (L.ntau + spw - 1) / spw;
+  const int per = (kLowdThreads / v) * kLowdSlices;  // slices per workgroup
+  return (L.ntau + per - 1) / per;
 }
 
 template <typename R>
