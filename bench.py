@@ -49,7 +49,7 @@ def parse():
                     help="skip the launch-shape autotuner (run before the timed region)")
     ap.add_argument("--report",
                     choices=["config2", "batched", "batched_solve", "force", "mv_sweep",
-                             "tables", "thermalize", "lowdim"],
+                             "tables", "thermalize", "lowdim", "fig1"],
                     help="print the measurement table of another workload (markdown) "
                          "instead of the JSON line")
     ap.add_argument("--mv-only", action="store_true",
@@ -756,6 +756,52 @@ def report_mv_sweep(a):
     return 0
 
 
+def report_fig1(a):
+    """The experiment of the paper's Fig. 1 (Sec. 5): BiCGStab iterations of the
+    two-step solve (M^T y = b, then M x = y) with the second-order
+    weak-coupling preconditioner (WCE2) as a function of Ntau and Nx, tol 1e-7,
+    g = 5, mean over 20 random sigma (one random right-hand side each). The
+    figure's data are not in the paper's text, so this is the measurement
+    alone; both precisions of the solve are reported."""
+    import numpy as np
+    import torch
+    from synthetic import sigma_field, gaussian_rhs, sweep_seeds, WORKLOADS
+    from paper_1008_3647_amd import Lattice, Precond
+    w = WORKLOADS["paper_sweeps"]
+    nsig = 20
+    pc = Precond("wce", wce_order=2)
+    nxs, ntaus = (4, 6, 8, 10, 12, 16), (25, 50, 100, 200, 400)
+    print("Mean BiCGStab iterations (step 1 + step 2) over 20 random sigma, WCE2, tol 1e-7, "
+          "g = 5, complex128 (in brackets: the standard deviation; FP32-refined in the second "
+          "table)")
+    print()
+    for mixed in (False, True):
+        print("| Ntau \\ Nx | " + " | ".join(str(n) for n in nxs) + " |")
+        print("|---|" + "---|" * len(nxs))
+        for ntau in ntaus:
+            cells = []
+            for nx in nxs:
+                L = Lattice(nx, ntau, 0.05, 5.0, torch.complex128)
+                its, fails = [], 0
+                for k in range(nsig):
+                    ss, rs = sweep_seeds(w, nx, ntau, k)
+                    L.set_aux_field(torch.from_numpy(sigma_field(nx, ntau, ss)).cuda())
+                    b = torch.from_numpy(gaussian_rhs(nx, ntau, [rs])).cuda()
+                    x, st = L.solve_bicgstab(b, "two_step", pc, tol=1e-7, maxit=5000, mixed=mixed)
+                    if st["status"] == 0:
+                        its.append(st["iters"][0] + st["iters"][1])
+                    else:
+                        fails += 1
+                L.close()
+                cell = f"{np.mean(its):.1f} ({np.std(its, ddof=1):.1f})" if its else "---"
+                if fails:
+                    cell += f" [{fails} not converged]"
+                cells.append(cell)
+            print(f"| {ntau} | " + " | ".join(cells) + " |", flush=True)
+        print()
+    return 0
+
+
 def report_lowdim(a):
     """Lattices of spatial dimension 1 and 2: apply_M / apply_Mdag bandwidth
     (rotating distinct buffers, library-default launch shape), and the
@@ -846,7 +892,8 @@ def main():
         return {"config2": report_config2, "batched": report_batched,
                 "batched_solve": report_batched_solve, "force": report_force,
                 "mv_sweep": report_mv_sweep, "tables": report_tables,
-                "thermalize": report_thermalize, "lowdim": report_lowdim}[a.report](a)
+                "thermalize": report_thermalize, "lowdim": report_lowdim,
+                "fig1": report_fig1}[a.report](a)
     if a.mv_only:
         return mv_only(a)
     if a.gpus != 1:
