@@ -70,3 +70,17 @@ def test_host_transfer_matrix_matches_oracle():
     from paper_1008_3647_amd.lattice import transfer_matrix
     for nx in (2, 4, 6, 8, 10, 12, 14, 16):
         assert np.allclose(transfer_matrix(nx, 0.05), op.transfer_matrix_1d(nx, 0.05), atol=1e-15)
+
+
+def test_create_lattice_dim_rejects_bad_arguments_on_the_host():
+    """create_lattice_dim validates dim (1, 2, 3) and the sizes before any
+    device call, so the rejections need no GPU."""
+    from paper_1008_3647_amd import _lib
+    lib = _lib.load()
+    h = ctypes.c_void_p()
+    for nx, ntau, dim in ((4, 4, 0), (4, 4, 4), (3, 4, 2), (4, 1, 1), (18, 4, 1)):
+        code = lib.create_lattice_dim(nx, ntau, dim, 0.05, 5.0, _lib.UFG_C128, _lib.UFG_DISP_FREE,
+                                      None, ctypes.byref(h))
+        assert code == _lib.UFG_EINVAL, (nx, ntau, dim, code)
+    msg = lib.ufg_last_error().decode()
+    assert "nx" in msg
