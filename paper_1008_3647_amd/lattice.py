@@ -9,6 +9,8 @@ library call, since the C ABI receives bare pointers and cannot.
 from __future__ import annotations
 
 import ctypes as C
+import json
+import time
 
 import torch
 
@@ -33,10 +35,12 @@ class Lattice:
     axis; C ABI create_lattice_ex).
     dim: spatial dimension (C ABI create_lattice_dim); vectors are
     [nrhs][Ntau][Nx]^dim.
+    log_path: when set, every solve appends one JSON line (call, parameters,
+    solve statistics) to this file.
     """
 
     def __init__(self, nx, ntau, tau=0.05, g=5.0, dtype=torch.complex128, stream=None,
-                 dispersion="free", dim=3):
+                 dispersion="free", dim=3, log_path=None):
         self._lib = L.load()
         if dtype not in (torch.complex64, torch.complex128):
             raise ValueError("dtype must be torch.complex64 or torch.complex128")
@@ -59,6 +63,7 @@ class Lattice:
         L.check(self._lib.lattice_info(h, None, None, None, C.byref(A)), "lattice_info")
         self.A = A.value
         self._sigma = None
+        self.log_path = log_path
 
     # ------------------------------------------------------------------ utils
     @property
@@ -97,6 +102,19 @@ class Lattice:
         if out.data_ptr() == x.data_ptr():
             raise ValueError(f"{name} must not alias the input")
         return out
+
+    def _log(self, call, stats, nrhs, **params):
+        """Append one JSON line per solve to log_path (when set): the call, its
+        parameters and the solve statistics (ufg_solve_stats)."""
+        if not self.log_path:
+            return
+        rec = dict(call=call, lattice=dict(nx=self.nx, ntau=self.ntau, dim=self.dim,
+                                           dtype=str(self.dtype).replace("torch.", ""),
+                                           dispersion=self.dispersion, tau=self.tau, g=self.g),
+                   nrhs=nrhs, time=time.time(), **params)
+        rec.update({k: v for k, v in stats.items() if isinstance(v, (int, float, list, tuple))})
+        with open(self.log_path, "a") as f:
+            f.write(json.dumps(rec) + "\n")
 
     def new_vectors(self, nrhs, dtype=None):
         return torch.empty((nrhs,) + self.shape, dtype=dtype or self.dtype, device=self.device)
@@ -171,7 +189,10 @@ class Lattice:
                                          C.c_void_p(b.data_ptr()), C.c_void_p(x.data_ptr()), n,
                                          C.byref(o), C.byref(st))
         L.check(code, "solve_cg_normal")
-        return x, st.as_dict()
+        stats = st.as_dict()
+        self._log("solve_cg_normal", stats, n, precond=repr(precond), tol=tol, maxit=maxit,
+                  mixed=bool(mixed))
+        return x, stats
 
     def solve_cg_split(self, b, precond: Precond, tol=1e-10, maxit=10000, check_every=10,
                        graph=True):
@@ -185,7 +206,9 @@ class Lattice:
         code = self._lib.solve_cg_split(self._h, C.byref(p), C.c_void_p(b.data_ptr()),
                                         C.c_void_p(x.data_ptr()), n, C.byref(o), C.byref(st))
         L.check(code, "solve_cg_split")
-        return x, st.as_dict()
+        stats = st.as_dict()
+        self._log("solve_cg_split", stats, n, precond=repr(precond), tol=tol, maxit=maxit)
+        return x, stats
 
     def solve_bicgstab(self, b, op="two_step", precond: Precond | None = None, tol=1e-10,
                        maxit=10000, mixed=False, delta=0.1, check_every=10, x0=None,
@@ -202,7 +225,10 @@ class Lattice:
                                         C.c_void_p(b.data_ptr()), C.c_void_p(x.data_ptr()), n,
                                         C.byref(o), C.byref(st))
         L.check(code, "solve_bicgstab")
-        return x, st.as_dict()
+        stats = st.as_dict()
+        self._log("solve_bicgstab", stats, n, op=op, precond=repr(precond), tol=tol,
+                  maxit=maxit, mixed=bool(mixed))
+        return x, stats
 
     def tune(self, slab=0, vec_blocks=0, nslab=0, xcd_group=-1, rhs_inner=False, transform=0):
         """Launch parameters (0 = library default, xcd_group -1 = default); see

@@ -328,3 +328,26 @@ def test_split_cg_against_dense_lu(dtype, order):
         say(f"rhs {k}: forward error {err:.2e}, oracle residual {rq:.2e}, cond(Q) {condQ:.0f}")
         assert err <= 2 * condQ * rq, (k, err)
         assert rq < (1e-10 if dtype == torch.complex128 else 1e-3), (k, rq)
+
+
+def test_solve_log_json_lines(tmp_path):
+    """Lattice(log_path=...): one JSON line per solve with the call, its
+    parameters and the statistics the call returned."""
+    require_gpu()
+    import json
+    from paper_1008_3647_amd import Lattice, Precond
+    nx, ntau = 4, 8
+    sigma = sigma_field(nx, ntau, 495)
+    b = to_dev(gaussian_rhs(nx, ntau, [496, 497]))
+    log = tmp_path / "solves.jsonl"
+    L = Lattice(nx, ntau, TAU, G, torch.complex128, log_path=str(log))
+    L.set_aux_field(to_dev(sigma))
+    _, s1 = L.solve_bicgstab(b, "two_step", tol=1e-10, mixed=True)
+    _, s2 = L.solve_cg_normal(b, Precond("sca", alpha=2.0), tol=1e-9)
+    recs = [json.loads(x) for x in log.read_text().splitlines()]
+    assert [r["call"] for r in recs] == ["solve_bicgstab", "solve_cg_normal"]
+    assert recs[0]["op"] == "two_step" and recs[0]["mixed"] is True and recs[0]["nrhs"] == 2
+    assert tuple(recs[0]["iters"]) == s1["iters"] and recs[0]["status"] == s1["status"]
+    assert recs[1]["relres"][0] == s2["relres"][0] and "sca" in recs[1]["precond"]
+    assert recs[0]["lattice"] == dict(nx=nx, ntau=ntau, dim=3, dtype="complex128",
+                                      dispersion="free", tau=TAU, g=G)
