@@ -39,8 +39,9 @@ def parse():
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--precond", default="none", choices=["none", "wce2"])
     ap.add_argument("--slab", type=int, default=0, help="--mv-only: slab size (0 = default)")
-    ap.add_argument("--transform", type=int, default=0, choices=[0, 1],
-                    help="--mv-only: T^3 route of apply_M (0 VALU block form, 1 MFMA y/x stages)")
+    ap.add_argument("--transform", type=int, default=0, choices=[0, 1, 2],
+                    help="--mv-only: T^3 route of apply_M (0 VALU block form, 1 MFMA y/x "
+                         "stages, 2 16-point DFTs)")
     ap.add_argument("--mv-warmup-ms", type=float, default=500.0,
                     help="wall time of apply_M warm-up launches before the timed ones")
     ap.add_argument("--no-secondary", action="store_true",
@@ -1059,18 +1060,20 @@ def main():
                 res[f"{name}_{mode}"] = dict(us=round(ms * 1e3, 2), GBs=round(alg / ms / 1e6, 1))
         if dt == torch.complex64:
             # the same launches with the transform's y and x stages on MFMA
-            # (lattice_tune_transform route 1), for the choice of T^3 route
-            Lm.tune(transform=1)
-            for i in range(2 * ROT):
-                Lm.apply_M(xs[i % ROT], ys[i % ROT])
-            e0.record()
-            for i in range(a.mv_launches):
-                Lm.apply_M(xs[i % ROT], ys[i % ROT])
-            e1.record()
-            torch.cuda.synchronize()
-            ms = e0.elapsed_time(e1) / a.mv_launches
-            res["apply_M_hbm_mfma_transform"] = dict(us=round(ms * 1e3, 2),
-                                                     GBs=round(alg / ms / 1e6, 1))
+            # (lattice_tune_transform route 1) and with every stage through
+            # 16-point DFTs (route 2), for the choice of T^3 route
+            for route, key in ((1, "apply_M_hbm_mfma_transform"),
+                               (2, "apply_M_hbm_dft_transform")):
+                Lm.tune(transform=route)
+                for i in range(2 * ROT):
+                    Lm.apply_M(xs[i % ROT], ys[i % ROT])
+                e0.record()
+                for i in range(a.mv_launches):
+                    Lm.apply_M(xs[i % ROT], ys[i % ROT])
+                e1.record()
+                torch.cuda.synchronize()
+                ms = e0.elapsed_time(e1) / a.mv_launches
+                res[key] = dict(us=round(ms * 1e3, 2), GBs=round(alg / ms / 1e6, 1))
             Lm.tune(transform=0)
         if not a.no_tune:
             # the plain operator's own tuned shape (slab, numbering, T^3 route),

@@ -441,10 +441,11 @@ int lattice_tune_order(ufg_lattice L, int group, int rhs_inner);
  *   operator applies exp(-tau K) = T (x) T (x) T (Sec. 1) to a slice: route 0
  *   (default) runs all three axes in the reflection-symmetry block form of T on
  *   the vector ALUs; route 1 keeps the z axis there and runs the y and x axes
- *   as 16x16x4 FP32 matrix-core (MFMA) contractions with T. Same operator;
- *   results agree to FP32 rounding, not bit for bit. Other dtypes, sizes and
- *   the fused solver variants always use route 0. Errors: UFG_EINVAL for a
- *   route other than 0 or 1.
+ *   as 16x16x4 FP32 matrix-core (MFMA) contractions with T; route 2 applies T
+ *   along every axis as a 16-point DFT, the eigenvalues of T and the inverse
+ *   DFT (T is circulant). Same operator; results agree to FP32 rounding, not
+ *   bit for bit. Other dtypes, sizes and the fused solver variants always use
+ *   route 0. Errors: UFG_EINVAL for a route other than 0, 1 or 2.
  */
 int lattice_tune_transform(ufg_lattice L, int route);
 

@@ -135,16 +135,16 @@ def tune_apply(L: Lattice, x, dagger=False, launches=20, reps=3, orders=ORDERS,
     launches cycle through, e.g. to keep the operands out of the Infinity
     Cache): slices per slab, workgroup numbering and, for complex64 on
     Nx = 16, the transform route (0: VALU block form, 1: y and x stages on
-    MFMA; see lattice_tune_transform). Each candidate is timed over `launches`
-    back-to-back applications between two synchronisations (best of `reps`);
-    the best is applied with Lattice.tune and returned with the timings of
-    every candidate."""
+    MFMA, 2: 16-point DFTs; see lattice_tune_transform). Each candidate is
+    timed over `launches` back-to-back applications between two
+    synchronisations (best of `reps`); the best is applied with Lattice.tune
+    and returned with the timings of every candidate."""
     fn = L.apply_Mdag if dagger else L.apply_M
     xs = list(x) if isinstance(x, (list, tuple)) else [x]
     ys = [torch.empty_like(v) for v in xs]
     x = xs[0]
     if transforms is None:
-        transforms = (0, 1) if (x.dtype == torch.complex64 and L.nx == 16) else (0,)
+        transforms = (0, 1, 2) if (x.dtype == torch.complex64 and L.nx == 16) else (0,)
     streaming = L.nx in (8, 12, 16)
     results = []
     for slab in candidate_slabs(L):

@@ -460,7 +460,7 @@ int lattice_tune_order(ufg_lattice h, int group, int rhs_inner) {
 int lattice_tune_transform(ufg_lattice h, int route) {
   Lattice* L = check_handle(h);
   UFG_CHECK(L != nullptr, "lattice_tune_transform: NULL handle");
-  UFG_CHECK(route == 0 || route == 1, "lattice_tune_transform: route must be 0 or 1");
+  UFG_CHECK(route >= 0 && route <= 2, "lattice_tune_transform: route must be 0, 1 or 2");
   UFG_HIP(hipStreamSynchronize(L->stream));
   L->t3_route = route;
   return UFG_OK;

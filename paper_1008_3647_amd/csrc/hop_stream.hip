@@ -175,6 +175,135 @@ __device__ __forceinline__ void slice_T3_mfma16(const SplitCoef<float, 16>& c,
   __syncthreads();
 }
 
+// T^3 through Fourier transforms (complex64, Nx = 16; lattice_tune_transform
+// route 2): T is a symmetric circulant, so along each axis T = F^-1 diag(lam) F
+// with F the 16-point DFT and lam_k = sum_j T_0j cos(2 pi j k / 16). Each
+// stage is a forward DFT of the line, the scaling by lam_k / 16 and an
+// inverse DFT, the DFT in radix 4 x 4 (index n = 4 n1 + n2, k = k1 + 4 k2:
+// 4-point DFTs over n1, twiddles W^(n2 k1), 4-point DFTs over n2).
+template <int M, bool INV>
+__device__ __forceinline__ float2 twiddle16(float2 a) {
+  // a * exp(-+2 pi i M / 16) (INV: +)
+  constexpr float c1 = 0.92387953251128674f, s1 = 0.38268343236508978f,
+                  r2 = 0.70710678118654752f;
+  constexpr float cs[10] = {1.f, c1, r2, s1, 0.f, -s1, -r2, -c1, -1.f, -c1};
+  constexpr float sn[10] = {0.f, s1, r2, c1, 1.f, c1, r2, s1, 0.f, -s1};
+  if constexpr (M == 0) {
+    return a;
+  } else if constexpr (M == 4) {  // -i (forward) or +i (inverse)
+    return INV ? make_float2(-a.y, a.x) : make_float2(a.y, -a.x);
+  } else if constexpr (M == 8) {
+    return make_float2(-a.x, -a.y);
+  } else {
+    const float c = cs[M], sg = INV ? sn[M] : -sn[M];
+    return make_float2(a.x * c - a.y * sg, a.x * sg + a.y * c);
+  }
+}
+
+template <bool INV>
+__device__ __forceinline__ void dft4(float2& a0, float2& a1, float2& a2, float2& a3) {
+  const float2 t0 = make_float2(a0.x + a2.x, a0.y + a2.y);
+  const float2 t1 = make_float2(a0.x - a2.x, a0.y - a2.y);
+  const float2 t2 = make_float2(a1.x + a3.x, a1.y + a3.y);
+  const float2 t3 = make_float2(a1.x - a3.x, a1.y - a3.y);
+  a0 = make_float2(t0.x + t2.x, t0.y + t2.y);
+  a2 = make_float2(t0.x - t2.x, t0.y - t2.y);
+  // forward: A1 = t1 - i t3, A3 = t1 + i t3 (inverse: the other way round)
+  const float2 m = make_float2(t1.x + t3.y, t1.y - t3.x);
+  const float2 p = make_float2(t1.x - t3.y, t1.y + t3.x);
+  a1 = INV ? p : m;
+  a3 = INV ? m : p;
+}
+
+template <bool INV>
+__device__ __forceinline__ void dft16(float2 (&v)[16]) {
+  float2 y[16];  // y[4 n2 + k1]
+#pragma unroll
+  for (int n2 = 0; n2 < 4; ++n2) {
+    float2 a0 = v[n2], a1 = v[4 + n2], a2 = v[8 + n2], a3 = v[12 + n2];
+    dft4<INV>(a0, a1, a2, a3);
+    y[4 * n2 + 0] = a0;
+    y[4 * n2 + 1] = a1;
+    y[4 * n2 + 2] = a2;
+    y[4 * n2 + 3] = a3;
+  }
+  y[5] = twiddle16<1, INV>(y[5]);
+  y[6] = twiddle16<2, INV>(y[6]);
+  y[7] = twiddle16<3, INV>(y[7]);
+  y[9] = twiddle16<2, INV>(y[9]);
+  y[10] = twiddle16<4, INV>(y[10]);
+  y[11] = twiddle16<6, INV>(y[11]);
+  y[13] = twiddle16<3, INV>(y[13]);
+  y[14] = twiddle16<6, INV>(y[14]);
+  y[15] = twiddle16<9, INV>(y[15]);
+#pragma unroll
+  for (int k1 = 0; k1 < 4; ++k1) {
+    float2 a0 = y[k1], a1 = y[4 + k1], a2 = y[8 + k1], a3 = y[12 + k1];
+    dft4<INV>(a0, a1, a2, a3);
+    v[k1] = a0;
+    v[k1 + 4] = a1;
+    v[k1 + 8] = a2;
+    v[k1 + 12] = a3;
+  }
+}
+
+__device__ __forceinline__ void fft_line16(const float (&lam)[16], float2 (&v)[16]) {
+  dft16<false>(v);
+#pragma unroll
+  for (int k = 0; k < 16; ++k) {
+    v[k].x *= lam[k];
+    v[k].y *= lam[k];
+  }
+  dft16<true>(v);
+}
+
+// lam_k / 16 from the first row of T (row-major Nx x Nx on the device).
+__device__ __forceinline__ void fft_lambda16(const float* __restrict__ T, float (&lam)[16]) {
+  constexpr float c1 = 0.92387953251128674f, s1 = 0.38268343236508978f,
+                  r2 = 0.70710678118654752f;
+  constexpr float cs[16] = {1.f, c1, r2, s1, 0.f, -s1, -r2, -c1,
+                            -1.f, -c1, -r2, -s1, 0.f, s1, r2, c1};
+#pragma unroll
+  for (int k = 0; k < 16; ++k) {
+    float acc = 0.f;
+#pragma unroll
+    for (int j = 0; j < 16; ++j) acc = fmaf(T[j], cs[(j * k) & 15], acc);
+    lam[k] = acc * (1.f / 16.f);
+  }
+}
+
+// slice_T3<float, 16, 0, true> with each line through fft_line16.
+__device__ __forceinline__ void slice_T3_fft16(const float (&lam)[16], float2* lds, int l,
+                                               float2 (&v)[16]) {
+  constexpr int NX = 16;
+  const int y = l / NX, x = l - (l / NX) * NX;
+  fft_line16(lam, v);  // along z
+#pragma unroll
+  for (int z = 0; z < NX; ++z) lds[lds_at<NX>(z * NX + y, x)] = v[z];
+  __syncthreads();
+  float2 w[NX];
+  {
+    const int z = l / NX, xx = l - (l / NX) * NX;
+#pragma unroll
+    for (int yy = 0; yy < NX; ++yy) w[yy] = lds[lds_at<NX>(z * NX + yy, xx)];
+    fft_line16(lam, w);  // along y
+#pragma unroll
+    for (int yy = 0; yy < NX; ++yy) lds[lds_at<NX>(z * NX + yy, xx)] = w[yy];
+  }
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+  {
+    const int z = l / NX, yy = l - (l / NX) * NX;
+#pragma unroll
+    for (int xx = 0; xx < NX; ++xx) w[xx] = lds[lds_at<NX>(z * NX + yy, xx)];
+    fft_line16(lam, w);  // along x
+#pragma unroll
+    for (int xx = 0; xx < NX; ++xx) lds[lds_at<NX>(z * NX + yy, xx)] = w[xx];
+  }
+  __syncthreads();
+}
+
 // Per-rhs scalars of the fused BiCGStab sources.
 template <typename R>
 struct SrcScal {
@@ -369,12 +498,14 @@ __device__ __forceinline__ double wsum(double v) {
 // registers, and the transform of the previous source stays in the LDS slice,
 // from which the output phase reads the thread's own z-line.
 // TR = 1: the transform's y and x stages on MFMA (complex64, Nx = 16, plain
-// operator only; see slice_T3_mfma16).
+// operator only; see slice_T3_mfma16); TR = 2: every stage through 16-point
+// DFTs (same restriction; see slice_T3_fft16).
 template <typename R, int NX, int DIR, bool GENERAL, int SRC, int RED, int TR = 0>
 __global__ void __launch_bounds__(NX * NX)
     hop_stream_kernel(HopArgs<R> a, SplitCoef<R, NX> c, int ntau, int nslab, int xg, int ri) {
   static_assert(TR == 0 || (sizeof(R) == 4 && NX == 16 && SRC == 0 && RED == 0 && !GENERAL),
-                "the MFMA transform route exists for the plain complex64 Nx = 16 operator");
+                "the MFMA and DFT transform routes exist for the plain complex64 Nx = 16 "
+                "operator");
   constexpr int P = NX * NX, V = NX * NX * NX;
   constexpr int ES = sizeof(C2<R>), FS = sizeof(R);
   // Single-use operand slices are loaded non-temporal (measured: faster for
@@ -400,12 +531,14 @@ __global__ void __launch_bounds__(NX * NX)
   const SplitCoef<R, NX>& cc = *coef_copy<kCoefLds, R, NX>(c, coef_lds);
 
   const int l = threadIdx.x;
-  float ta[TR ? 4 : 1];
-  if constexpr (TR != 0) {
+  float ta[TR == 1 ? 4 : 1];
+  if constexpr (TR == 1) {
     const int lane = l & 63;
 #pragma unroll
     for (int j = 0; j < 4; ++j) ta[j] = float(a.mat[(lane & 15) * NX + 4 * j + (lane >> 4)]);
   }
+  float lam[TR == 2 ? 16 : 1];
+  if constexpr (TR == 2) fft_lambda16(a.mat, lam);
   const int t0 = (int)((long long)sb * ntau / nslab);
   const int t1 = (int)((long long)(sb + 1) * ntau / nslab);  // exclusive
   const long long rbase = (long long)r * ntau * V;
@@ -517,8 +650,10 @@ __global__ void __launch_bounds__(NX * NX)
   // variants ran slower that way)
   if constexpr (EARLY) __builtin_amdgcn_s_setprio(2);
   if (DIR < 0) scale_field<R, NX>(b.pre, th * V * FS, fo, X);
-  if constexpr (TR != 0)
+  if constexpr (TR == 1)
     slice_T3_mfma16(cc, ta, lds, l, X);
+  else if constexpr (TR == 2)
+    slice_T3_fft16(lam, lds, l, X);
   else
     slice_T3<R, NX, 0, true>(cc, lds, l, X);
   for (int k = 0; k < count; ++k) {
@@ -642,8 +777,10 @@ __global__ void __launch_bounds__(NX * NX)
     if (k + 1 < count) {
       // transform source slice t for the next output slice
       if (DIR < 0) scale_field<R, NX>(b.pre, t * V * FS, fo, X);
-      if constexpr (TR != 0)
+      if constexpr (TR == 1)
         slice_T3_mfma16(cc, ta, lds, l, X);
+      else if constexpr (TR == 2)
+        slice_T3_fft16(lam, lds, l, X);
       else
         slice_T3<R, NX, 0, true>(cc, lds, l, X);
     }
@@ -715,6 +852,8 @@ int launch_dir(const Lattice& L, const HopArgs<R>& a, const SplitCoef<R, NX>& c)
         if constexpr (sizeof(R) == 4 && NX == 16) {
           if (L.t3_route == 1)
             return launch_one<R, NX, DIR, false, 0, 0, 1>(L, a, c, grid, lds, nslab);
+          if (L.t3_route == 2)
+            return launch_one<R, NX, DIR, false, 0, 0, 2>(L, a, c, grid, lds, nslab);
         }
         return launch_one<R, NX, DIR, false, 0, 0>(L, a, c, grid, lds, nslab);
       case 1: return launch_one<R, NX, DIR, false, 0, 1>(L, a, c, grid, lds, nslab);

@@ -105,7 +105,7 @@ struct Lattice {
   int vec_blocks = 0;              // workgroups per rhs of the vector kernels (0: default)
   int xcd_group = -1;              // slab groups per XCD of the streaming kernels (-1: default)
   int xcd_rhs_inner = 0;           // 1: an XCD takes every rhs of a slab group in turn
-  int t3_route = 0;                // 1: y and x stages of T^3 on MFMA (complex64, Nx = 16)
+  int t3_route = 0;                // 1: y and x stages of T^3 on MFMA, 2: DFTs (complex64, Nx = 16)
   DevBuf work[26];          // vector workspaces (solver / preconditioner)
   DevBuf hmc[7];            // HMC trajectory: sigma0, pi0, grad, phi, y, X, partials
   DevBuf red;               // reduction partials
