@@ -1017,7 +1017,11 @@ def main():
                          converged=bool(stw["status"] == 0 and max(stw["relres"]) <= tol),
                          tuning=tuned_w, tuning_fp64=tuned_w64,
                          max_rel_diff_vs_unpreconditioned=float(
-                             (xw - x64).abs().max().item() / x64.abs().max().item()))
+                             (xw - x64).abs().max().item() / x64.abs().max().item()),
+                         # the same system as the headline solve, so the same
+                         # stored oracle samples apply
+                         max_rel_err_vs_oracle=oracle_errors(xw.cpu().numpy()),
+                         max_rel_err_vs_oracle_fp64_solve=oracle_errors(xw64.cpu().numpy()))
 
     # apply_M bandwidth (the dominant kernel of the solve), HIP events on the lattice
     # stream. The timed launches cycle through ROT distinct (x, y) pairs (ROT x 216 MB
