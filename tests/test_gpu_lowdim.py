@@ -1,8 +1,9 @@
 """Lattices of spatial dimension 1 and 2 (create_lattice_dim) through the C ABI
 against the oracle: the operator element by element (both dispersions, both
 precisions, odd slice counts per workgroup and a ragged last workgroup), the
-preconditioners, the solvers (dense LU on tiny lattices, the oracle's
-residual elsewhere), the force, and a short HMC chain.
+preconditioners, the solvers (BiCGStab, CG with every preconditioner and
+split-preconditioned CG: dense LU on tiny lattices, the oracle's residual
+elsewhere), the force, and a short HMC chain.
 
 Tolerances as for three dimensions: operators 1e-13 (complex128) / 5e-6
 (complex64), preconditioners 1e-12 / 2e-5, relative to the largest output
@@ -193,3 +194,27 @@ def test_batched_and_bad_dim_rejected():
         Lattice(4, 6, TAU, G, torch.complex128, dim=4)
     with pytest.raises(ValueError):  # a 3D vector on a 2D lattice
         L.apply_M(to_dev(gaussian_rhs(4, 6, [872])))
+
+
+@pytest.mark.parametrize("dim,nx,ntau", [(1, 8, 6), (2, 4, 5)])
+def test_cg_variants_against_dense_lu(dim, nx, ntau):
+    """CG on M^T M with the Chebyshev and SCA + Chebyshev preconditioners, and
+    split-preconditioned CG with the weak-coupling W_1 (at g = 1, where the
+    series converges in these dimensions), against dense LU."""
+    require_gpu()
+    from paper_1008_3647_amd import Precond
+    b, bd = _rhs(dim, nx, ntau, [881, 882], torch.complex128)
+    for g, solver, pcd in ((G, "cg", Precond("cheb", degree=8, eps=1e-2, lam_max=-1.0)),
+                           (G, "cg", Precond("sca_cheb", degree=8, eps=1e-2, lam_max=-1.0)),
+                           (1.0, "split", Precond("wce", wce_order=1))):
+        L, sigma = _lattice(dim, nx, ntau, torch.complex128, g=g, seed=880)
+        if solver == "cg":
+            x, st = L.solve_cg_normal(bd, pcd, tol=1e-11)
+        else:
+            x, st = L.solve_cg_split(bd, pcd, tol=1e-11)
+        say(f"lowdim {solver} {pcd.kind} dim={dim}: iters {st['iters']} status {st['status']}")
+        assert st["status"] == 0, (solver, pcd.kind, st)
+        Md = op.dense_M(sigma, TAU, g)
+        for k in range(2):
+            ref = np.linalg.solve(Md.T @ Md, b[k].ravel())
+            assert rel_err(to_host(x)[k].ravel(), ref) < 1e-7, (solver, pcd.kind, k)
