@@ -1083,7 +1083,10 @@ def main():
             # the plain operator's own tuned shape (slab, numbering, T^3 route),
             # next to the library default that the roofline line reports
             from paper_1008_3647_amd.autotune import tune_apply
-            tn = tune_apply(Lm, xs, launches=2 * ROT, reps=2)
+            # sustained runs per candidate (short bursts ranked the slab groups
+            # differently from the 200-launch measurement); the T^3 routes are
+            # timed above
+            tn = tune_apply(Lm, xs, launches=200, reps=2, transforms=(0,))
             for i in range(2 * ROT):
                 Lm.apply_M(xs[i % ROT], ys[i % ROT])
             e0.record()

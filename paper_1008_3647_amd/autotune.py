@@ -128,7 +128,7 @@ def tune(L: Lattice, b: torch.Tensor, mixed=False, op="M", iters=16, reps=2,
     return dict(choice, cached=False, candidates=results)
 
 
-def tune_apply(L: Lattice, x, dagger=False, launches=20, reps=3, orders=ORDERS,
+def tune_apply(L: Lattice, x, dagger=False, launches=100, reps=3, orders=ORDERS,
                transforms=None, verbose=False):
     """Pick the launch shape of the plain operator (apply_M, or apply_Mdag with
     dagger=True) on `x` (a tensor, or a list of tensors that the timed
@@ -136,8 +136,8 @@ def tune_apply(L: Lattice, x, dagger=False, launches=20, reps=3, orders=ORDERS,
     Cache): slices per slab, workgroup numbering and, for complex64 on
     Nx = 16, the transform route (0: VALU block form, 1: y and x stages on
     MFMA, 2: 16-point DFTs; see lattice_tune_transform). Each candidate is
-    timed over `launches` back-to-back applications between two
-    synchronisations (best of `reps`); the best is applied with Lattice.tune
+    timed over `launches` back-to-back applications with HIP events on the
+    lattice's stream (best of `reps`); the best is applied with Lattice.tune
     and returned with the timings of every candidate."""
     fn = L.apply_Mdag if dagger else L.apply_M
     xs = list(x) if isinstance(x, (list, tuple)) else [x]
@@ -154,13 +154,15 @@ def tune_apply(L: Lattice, x, dagger=False, launches=20, reps=3, orders=ORDERS,
                 for i in range(len(xs)):  # warm-up
                     fn(xs[i], ys[i])
                 best_t = float("inf")
+                e0 = torch.cuda.Event(enable_timing=True)
+                e1 = torch.cuda.Event(enable_timing=True)
                 for _ in range(reps):
-                    torch.cuda.synchronize()
-                    t0 = time.perf_counter()
+                    e0.record(L.stream)  # on the stream the lattice launches on
                     for i in range(launches):
                         fn(xs[i % len(xs)], ys[i % len(xs)])
+                    e1.record(L.stream)
                     torch.cuda.synchronize()
-                    best_t = min(best_t, (time.perf_counter() - t0) / launches)
+                    best_t = min(best_t, e0.elapsed_time(e1) * 1e-3 / launches)
                 results.append(dict(slab=slab, xcd_group=grp, rhs_inner=ri, transform=tr,
                                     seconds=best_t))
                 if verbose:

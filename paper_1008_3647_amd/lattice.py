@@ -52,6 +52,7 @@ class Lattice:
         self.dispersion = dispersion
         self.dim = int(dim)
         self.device = torch.device("cuda", torch.cuda.current_device())
+        self.stream = stream if stream is not None else torch.cuda.current_stream()
         h = C.c_void_p()
         code = self._lib.create_lattice_dim(nx, ntau, self.dim, tau, g,
                                             L.UFG_C128 if dtype == torch.complex128 else L.UFG_C64,
@@ -132,6 +133,7 @@ class Lattice:
 
     def set_stream(self, stream=None):
         L.check(self._lib.set_lattice_stream(self._h, _stream_ptr(stream)), "set_lattice_stream")
+        self.stream = stream if stream is not None else torch.cuda.current_stream()
 
     # ---------------------------------------------------------------- the ABI
     def set_aux_field(self, sigma: torch.Tensor):
