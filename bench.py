@@ -1080,25 +1080,37 @@ def main():
                 res[key] = dict(us=round(ms * 1e3, 2), GBs=round(alg / ms / 1e6, 1))
             Lm.tune(transform=0)
         if not a.no_tune:
-            # the plain operator's own tuned shape (slab, numbering, T^3 route),
-            # next to the library default that the roofline line reports
+            # the plain operator's own tuned shape (slab, slab groups, rhs
+            # order), timed against the library default in alternating runs
+            # right after the tuning (single runs there read up to 5 % slower
+            # than the default figure above, so only same-run figures compare)
             from paper_1008_3647_amd.autotune import tune_apply
             # sustained runs per candidate (short bursts ranked the slab groups
             # differently from the 200-launch measurement); the T^3 routes are
             # timed above
             tn = tune_apply(Lm, xs, launches=200, reps=2, transforms=(0,))
-            for i in range(2 * ROT):
-                Lm.apply_M(xs[i % ROT], ys[i % ROT])
-            e0.record()
-            for i in range(a.mv_launches):
-                Lm.apply_M(xs[i % ROT], ys[i % ROT])
-            e1.record()
-            torch.cuda.synchronize()
-            ms = e0.elapsed_time(e1) / a.mv_launches
+            shape_t = {k: tn[k] for k in ("slab", "xcd_group", "rhs_inner", "transform")}
+
+            def timed():
+                for i in range(2 * ROT):
+                    Lm.apply_M(xs[i % ROT], ys[i % ROT])
+                e0.record()
+                for i in range(a.mv_launches):
+                    Lm.apply_M(xs[i % ROT], ys[i % ROT])
+                e1.record()
+                torch.cuda.synchronize()
+                return e0.elapsed_time(e1) / a.mv_launches
+
+            ms_t = ms_d = float("inf")
+            for _ in range(2):
+                Lm.tune(shape_t["slab"], 0, xcd_group=shape_t["xcd_group"],
+                        rhs_inner=shape_t["rhs_inner"], transform=shape_t["transform"])
+                ms_t = min(ms_t, timed())
+                Lm.tune()  # library default
+                ms_d = min(ms_d, timed())
             res["apply_M_hbm_tuned"] = dict(
-                us=round(ms * 1e3, 2), GBs=round(alg / ms / 1e6, 1),
-                shape={k: tn[k] for k in ("slab", "xcd_group", "rhs_inner", "transform")},
-                candidates=len(tn["candidates"]))
+                us=round(ms_t * 1e3, 2), GBs=round(alg / ms_t / 1e6, 1), shape=shape_t,
+                candidates=len(tn["candidates"]), default_us_same_run=round(ms_d * 1e3, 2))
         res["alg_bytes"] = alg
         mv["c64" if dt == torch.complex64 else "c128"] = res
         if dt == torch.complex64:
