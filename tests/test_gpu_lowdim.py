@@ -218,3 +218,24 @@ def test_cg_variants_against_dense_lu(dim, nx, ntau):
         for k in range(2):
             ref = np.linalg.solve(Md.T @ Md, b[k].ravel())
             assert rel_err(to_host(x)[k].ravel(), ref) < 1e-7, (solver, pcd.kind, k)
+
+
+@pytest.mark.parametrize("dtype", [torch.complex64, torch.complex128])
+@pytest.mark.parametrize("dim,nx,ntau,nrhs", [(1, 16, 4000, 64), (2, 16, 1000, 8),
+                                               (2, 8, 8000, 16)])
+def test_operator_at_full_size(dim, nx, ntau, nrhs, dtype):
+    """The lower-dimensional bandwidth workloads at their full size and right-hand
+    side count, in the launch the bandwidth report times (library default):
+    M and M^T element by element against the oracle for the first, a middle
+    and the last rhs (1D: 64 slices per workgroup, 4000 = 62 x 64 + 32 leaves a
+    ragged last workgroup; 2D, Nx = 8: 16 slices per workgroup)."""
+    require_gpu()
+    say(f"lowdim full-size operator dim={dim} nx={nx} ntau={ntau} nrhs={nrhs} {dtype}")
+    L, sigma = _lattice(dim, nx, ntau, dtype, seed=890)
+    seeds = list(range(891, 891 + nrhs))
+    x, xd = _rhs(dim, nx, ntau, seeds, dtype)
+    y = to_host(L.apply_M(xd))
+    yd = to_host(L.apply_Mdag(xd))
+    for k in (0, nrhs // 2, nrhs - 1):
+        assert rel_err(y[k], oracle.apply_M(x[k], sigma, TAU, G)) < TOL_OP[dtype], k
+        assert rel_err(yd[k], oracle.apply_Mdag(x[k], sigma, TAU, G)) < TOL_OP[dtype], k
