@@ -1,4 +1,5 @@
-"""Build libufg.so for gfx950 with hipcc (in-tree, next to this file).
+"""Build libufg.so for gfx950 with hipcc (in-tree, next to this file), then
+the plain-C example program examples/solve_from_c against it.
 
 Usage: python -m paper_1008_3647_amd.build [--jobs N] [--debug]
 """
@@ -15,6 +16,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libufg.so")
+EXAMPLES = os.path.join(HERE, "examples")
 SOURCES = ["api.cpp", "ops.cpp", "solvers.cpp", "split.cpp", "batched.hip", "hop.hip",
            "hop_stream.hip", "temporal.hip", "krylov.hip", "noalloc.hip",
            "hmc.hip", "lowd.hip"]
@@ -61,7 +63,27 @@ def build(jobs: int = 8, debug: bool = False, verbose: bool = True) -> str:
     os.replace(tmp, LIB)
     if verbose:
         print(f"built {LIB}")
+    build_c_example(verbose)
     return LIB
+
+
+def build_c_example(verbose: bool = True) -> str:
+    """Compile examples/solve_from_c.c with gcc as C11 against include/ufg.h and
+    libufg.so (run path: the package directory, then ROCm's libraries)."""
+    inc = os.path.join(os.path.dirname(HERE), "include")
+    rocm = os.environ.get("ROCM_PATH", "/opt/rocm")
+    out = os.path.join(EXAMPLES, "solve_from_c")
+    cmd = ["gcc", "-std=c11", "-O2", "-Wall", "-Wextra", "-Werror", "-D__HIP_PLATFORM_AMD__",
+           f"-I{inc}", f"-I{rocm}/include", os.path.join(EXAMPLES, "solve_from_c.c"),
+           "-o", out + ".tmp", f"-L{HERE}", "-lufg", f"-L{rocm}/lib", "-lamdhip64",
+           "-Wl,-rpath,$ORIGIN/..", f"-Wl,-rpath,{rocm}/lib"]
+    r = subprocess.run(cmd, capture_output=True, text=True)
+    if r.returncode != 0:
+        raise RuntimeError(f"C example failed to build\n{' '.join(cmd)}\n{r.stdout}\n{r.stderr}")
+    os.replace(out + ".tmp", out)
+    if verbose:
+        print(f"built {out}")
+    return out
 
 
 def main(argv=None):

@@ -81,7 +81,10 @@ class Lattice:
             raise ValueError(f"{name} must be contiguous")
         if x.dim() < len(self.shape) or tuple(x.shape[-len(self.shape):]) != self.shape:
             raise ValueError(f"{name} must end in shape {self.shape}, got {tuple(x.shape)}")
-        return x.numel() // (self.ntau * self.nx ** self.dim)
+        n = x.numel() // (self.ntau * self.nx ** self.dim)
+        if n == 0:
+            raise ValueError(f"{name} holds no right-hand sides (shape {tuple(x.shape)})")
+        return n
 
     def _like(self, t, ref, name):
         """`t` must be a contiguous CUDA tensor of ref's dtype, shape and device

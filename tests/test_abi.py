@@ -84,3 +84,18 @@ def test_create_lattice_dim_rejects_bad_arguments_on_the_host():
         assert code == _lib.UFG_EINVAL, (nx, ntau, dim, code)
     msg = lib.ufg_last_error().decode()
     assert "nx" in msg
+
+
+def test_header_is_plain_c_and_the_c_example_links(tmp_path):
+    """include/ufg.h compiles as C11 with every warning an error, and the
+    example program that uses it links against libufg.so (no device work)."""
+    import subprocess
+    from paper_1008_3647_amd import build as b
+    src = os.path.join(b.EXAMPLES, "solve_from_c.c")
+    out = str(tmp_path / "solve_from_c")
+    cmd = ["gcc", "-std=c11", "-O2", "-Wall", "-Wextra", "-Werror", "-D__HIP_PLATFORM_AMD__",
+           f"-I{os.path.join(ROOT, 'include')}", "-I/opt/rocm/include", src, "-o", out,
+           f"-L{os.path.dirname(LIB)}", "-lufg", "-L/opt/rocm/lib", "-lamdhip64"]
+    r = subprocess.run(cmd, capture_output=True, text=True)
+    assert r.returncode == 0, r.stderr
+    assert os.path.exists(out)

@@ -100,3 +100,21 @@ def test_force_buffers_are_checked():
     ref = sum(oracle.force.gradient(to_host(X)[k], sigma, TAU, G) for k in range(2))
     assert rel_err(got, ref) < 1e-12
     assert np.array_equal(got, to_host(L.force_dS_dsigma(X, y)))
+
+
+def test_empty_batches_are_rejected():
+    """A batch of zero right-hand sides is an error raised in Python (the C
+    ABI takes nrhs >= 1), for the operator, the preconditioners, the solvers,
+    the norm, the force and the HMC calls."""
+    require_gpu()
+    from paper_1008_3647_amd import Precond
+    L = _lattice()
+    e = torch.empty((0,) + L.shape, dtype=L.dtype, device="cuda")
+    s = to_dev(sigma_field(4, 6, 880))
+    pi = torch.zeros(L.shape, dtype=torch.float64, device="cuda")
+    for fn in (lambda: L.apply_M(e), lambda: L.apply_Mdag(e),
+               lambda: L.apply_precond(e, Precond("wce", wce_order=1), "M"),
+               lambda: L.solve_bicgstab(e, "M"), lambda: L.solve_cg_normal(e),
+               lambda: L.norm2(e), lambda: L.force_dS_dsigma(e, e),
+               lambda: L.hmc_trajectory(s, pi, e, 0.5, 0.1, 2)):
+        _rejects(L, ValueError, fn)
