@@ -87,8 +87,9 @@ def test_create_lattice_dim_rejects_bad_arguments_on_the_host():
 
 
 def test_header_is_plain_c_and_the_c_example_links(tmp_path):
-    """include/ufg.h compiles as C11 with every warning an error, and the
-    example program that uses it links against libufg.so (no device work)."""
+    """include/ufg.h compiles as C11 with every warning an error, the example
+    program that uses it links against libufg.so, and it rejects malformed
+    input files before touching the device."""
     import subprocess
     from paper_1008_3647_amd import build as b
     src = os.path.join(b.EXAMPLES, "solve_from_c.c")
@@ -99,3 +100,22 @@ def test_header_is_plain_c_and_the_c_example_links(tmp_path):
     r = subprocess.run(cmd, capture_output=True, text=True)
     assert r.returncode == 0, r.stderr
     assert os.path.exists(out)
+    # its input checks run before any device call: bad files end with exit
+    # status 1 and a message, and no output
+    env = dict(os.environ, LD_LIBRARY_PATH=os.pathsep.join(
+        [os.path.dirname(LIB), "/opt/rocm/lib", os.environ.get("LD_LIBRARY_PATH", "")]))
+    head = np.array([4, 6, 1], np.int32).tobytes() + np.array([0.05, 5.0]).tobytes()
+    cases = {b"": "short header",
+             np.array([20, 6, 1], np.int32).tobytes() + np.array([0.05, 5.0]).tobytes():
+                 "sizes out of range",
+             np.array([4, 6, 0], np.int32).tobytes() + np.array([0.05, 5.0]).tobytes():
+                 "sizes out of range",
+             head + np.zeros(4 * 4 * 4 * 6).tobytes(): "short body"}
+    for i, (data, msg) in enumerate(cases.items()):
+        src, dst = tmp_path / f"in{i}.bin", tmp_path / f"out{i}.bin"
+        src.write_bytes(data)
+        r = subprocess.run([out, str(src), str(dst)], capture_output=True, text=True, env=env,
+                           timeout=60)
+        assert r.returncode == 1 and msg in r.stderr, (i, r.returncode, r.stderr)
+    r = subprocess.run([out], capture_output=True, text=True, env=env, timeout=60)
+    assert r.returncode == 1 and "usage" in r.stderr
