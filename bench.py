@@ -1061,7 +1061,9 @@ def main():
                 e1.record()
                 torch.cuda.synchronize()
                 ms = e0.elapsed_time(e1) / a.mv_launches
-                res[f"{name}_{mode}"] = dict(us=round(ms * 1e3, 2), GBs=round(alg / ms / 1e6, 1))
+                # MV/s: applications of the operator to one vector per second
+                res[f"{name}_{mode}"] = dict(us=round(ms * 1e3, 2), GBs=round(alg / ms / 1e6, 1),
+                                             MV_per_s=round(nrhs / ms * 1e3))
         if dt == torch.complex64:
             # the same launches with the transform's y and x stages on MFMA
             # (lattice_tune_transform route 1) and with every stage through
@@ -1165,6 +1167,11 @@ def main():
         "relres_steps": list(st["relres"]),
         "relres_normal": st["relres_normal"],
         "reliable_updates": st["reliable_updates"],
+        # operator applications to one vector per second over the solve:
+        # operator launches x right-hand sides (an upper bound of the work,
+        # since a converged system skips its share of later launches)
+        "solve_mv_per_s": round(st["mv"] * nrhs / t_mixed),
+        "fp64_solve_mv_per_s": round(st64["mv"] * nrhs / t_fp64),
         "fp64_seconds": round(t_fp64, 4),
         "fp64_iters": list(st64["iters"]),
         "fp64_relres_steps": list(st64["relres"]),
