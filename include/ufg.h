@@ -265,7 +265,7 @@ int solve_bicgstab(ufg_lattice L, const ufg_precond* p, int op, const void* b,
  *   iteration is one persistent launch over a work table covering all
  *   problems; whole check intervals, with their reliable updates and restarts
  *   gated on device flags, are replayed from captured HIP graphs, the host
- *   reading the flags once per ~100 iterations (solve_batched_tune); every
+ *   reading the flags once per ~200 iterations (solve_batched_tune); every
  *   (problem, rhs) keeps its own device state and stops on its own.
  *   Ls[i]: complex128 lattices (fields installed). b[i], x[i]: device
  *   complex128 vectors [nrhs[i]][Ntau][Nx]^3 of lattice i. o->mixed: complex64
@@ -286,7 +286,7 @@ int solve_batched(const ufg_lattice* Ls, int nprob, const void* const* b,
  *   work item (256..4194304; default 4096), time slices per slab of the
  *   batched streaming operator (1..64; default 2) and iterations between host
  *   reads of the convergence flags (1..100000, rounded to whole check
- *   intervals; default 100). Process-wide; not thread safe against concurrent
+ *   intervals; default 200). Process-wide; not thread safe against concurrent
  *   solves. Results do not depend on them beyond floating-point summation
  *   order (and the last point at which an unconverged system may stop).
  */
