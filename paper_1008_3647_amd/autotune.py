@@ -176,30 +176,51 @@ def tune_apply(L: Lattice, x, dagger=False, launches=100, reps=3, orders=ORDERS,
 
 
 def tune_batched(lattices, bs, mixed=True, iters=10, reps=2, hop_blocks=(2, 4, 8),
-                 vec_blocks=(8, 16), chunks=(4096, 16384), slabs=(1, 2, 4), verbose=False):
+                 vec_blocks=(8, 16), chunks=(4096, 16384), slabs=(1, 2, 4), finalists=3,
+                 refine_iters=60, refine_reps=3, verbose=False):
     """Pick the launch shape of solve_batched (workgroups per CU of the
     persistent operator and vector launches, elements per vector work item,
     slices per slab of the batched operator) for
     this set of problems. Each candidate runs the batch for a fixed number of
-    iterations per step (tolerance unreachable, identical work); the best is
-    applied with solve_batched_tune and returned."""
+    iterations per step (tolerance unreachable, identical work); the
+    `finalists` fastest are timed again over `refine_iters` iterations per
+    step, `refine_reps` rounds in turn (short runs cannot separate shapes a
+    few per cent apart); the best is applied with solve_batched_tune and
+    returned."""
     from .lattice import solve_batched, solve_batched_tune
+
+    def run(shape, n):
+        solve_batched_tune(*shape)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        solve_batched(lattices, bs, tol=1e-30, maxit=n, mixed=mixed, check_every=n)
+        torch.cuda.synchronize()
+        return time.perf_counter() - t0
+
     results = []
     for hb, vb, ch, sl in itertools.product(hop_blocks, vec_blocks, chunks, slabs):
         solve_batched_tune(hb, vb, ch, sl)
         solve_batched(lattices, bs, tol=1e-30, maxit=2, mixed=mixed, check_every=2)
-        best_t = float("inf")
-        for _ in range(reps):
-            torch.cuda.synchronize()
-            t0 = time.perf_counter()
-            solve_batched(lattices, bs, tol=1e-30, maxit=iters, mixed=mixed, check_every=iters)
-            torch.cuda.synchronize()
-            best_t = min(best_t, time.perf_counter() - t0)
+        best_t = min(run((hb, vb, ch, sl), iters) for _ in range(reps))
         results.append(dict(hop_blocks_per_cu=hb, vec_blocks_per_cu=vb, chunk=ch, slab=sl,
                             seconds=best_t))
         if verbose:
             print(f"tune_batched {hb} {vb} {ch} {sl}: {best_t * 1e3:.2f} ms", flush=True)
-    best = min(results, key=lambda d: d["seconds"])
+    keys = ("hop_blocks_per_cu", "vec_blocks_per_cu", "chunk", "slab")
+    final = sorted(results, key=lambda d: d["seconds"])[:max(1, finalists)]
+    if len(final) > 1 and refine_reps > 0:
+        for d in final:
+            d["refined"] = float("inf")
+        for _ in range(refine_reps):
+            for d in final:
+                d["refined"] = min(d["refined"], run(tuple(d[k] for k in keys), refine_iters))
+        if verbose:
+            for d in final:
+                print(f"tune_batched refine {[d[k] for k in keys]}: "
+                      f"{d['refined'] * 1e3:.2f} ms", flush=True)
+        best = min(final, key=lambda d: d["refined"])
+    else:
+        best = final[0]
     solve_batched_tune(best["hop_blocks_per_cu"], best["vec_blocks_per_cu"], best["chunk"],
                        best["slab"])
     return {k: best[k] for k in ("hop_blocks_per_cu", "vec_blocks_per_cu", "chunk", "slab")}

@@ -55,6 +55,34 @@ def test_tiny_uneven_batch_against_dense_lu(mixed):
             assert np.linalg.norm(xh[k] - ref) / np.linalg.norm(ref) < 1e-7
 
 
+def test_tune_batched_picks_a_candidate_and_solves():
+    """tune_batched over a small candidate set (two rounds: the short sweep,
+    then the finalists over longer runs) returns one of the candidates, leaves
+    it applied, and the batch then solves to tolerance and to the dense-LU
+    solutions; the library default is restored afterwards."""
+    require_gpu()
+    from paper_1008_3647_amd.lattice import solve_batched, solve_batched_tune
+    from paper_1008_3647_amd.autotune import tune_batched
+    probs = _problems([(4, 6), (6, 10), (8, 5), (4, 13)], 1200, 1250, 2)
+    lats, bs = _lattices(probs)
+    try:
+        choice = tune_batched(lats, bs, hop_blocks=(2, 4), vec_blocks=(8,), chunks=(4096,),
+                              slabs=(1, 2), finalists=2, refine_iters=12, refine_reps=2)
+        say(f"tune_batched choice {choice}")
+        assert choice["hop_blocks_per_cu"] in (2, 4) and choice["slab"] in (1, 2)
+        assert choice["vec_blocks_per_cu"] == 8 and choice["chunk"] == 4096
+        xs, st = solve_batched(lats, bs, tol=1e-10)
+        for (nx, ntau, sigma, b), x, s in zip(probs, xs, st):
+            assert s["status"] == 0 and max(s["relres"]) <= 1e-10
+            Md = op.dense_M(sigma, TAU, G)
+            xh = to_host(x)
+            for k in range(b.shape[0]):
+                ref = osol.dense_two_step(Md, b[k].ravel()).reshape(b[k].shape)
+                assert np.linalg.norm(xh[k] - ref) / np.linalg.norm(ref) < 1e-7
+    finally:
+        solve_batched_tune()
+
+
 def test_batched_64_against_oracle():
     """The 64-lattice batch (Nx in {6,8,10,12}, Ntau in 80..320), 2 rhs each,
     complex64-refined: every system converges to 1e-10 per step; the oracle's
