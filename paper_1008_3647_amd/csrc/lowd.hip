@@ -20,8 +20,8 @@ using namespace hopc;
 
 constexpr int kLowdThreads = 256;
 // slices per thread of the operator kernel (its loads are issued together):
-// four, two on 2D lattices of Nx <= 8, whose workgroups already hold 16 or
-// more slices (measured on 8^2 x 8000, 16 rhs: complex128 apply_M 72.6 ->
+// four, two on 2D lattices of Nx <= 8, where a workgroup then still covers 8
+// or more slices (measured on 8^2 x 8000, 16 rhs: complex128 apply_M 72.6 ->
 // 59.8 us, apply_Mdag 54.6 -> 49.8 us, complex64 within 4 %; two on 2D
 // Nx = 16 was 6-14 % slower). A function of the shape alone, so that the
 // reduction's partial-sum count (lowd_blocks_per_rhs) follows it.
