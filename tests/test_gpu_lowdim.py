@@ -239,3 +239,40 @@ def test_operator_at_full_size(dim, nx, ntau, nrhs, dtype):
     for k in (0, nrhs // 2, nrhs - 1):
         assert rel_err(y[k], oracle.apply_M(x[k], sigma, TAU, G)) < TOL_OP[dtype], k
         assert rel_err(yd[k], oracle.apply_Mdag(x[k], sigma, TAU, G)) < TOL_OP[dtype], k
+
+
+@pytest.mark.parametrize("dim,ntau", [(1, (1 << 20) + 37), (2, (1 << 16) + 5)])
+def test_operator_beyond_32bit_offsets(dim, ntau):
+    """Nine complex128 right-hand sides of 16^d x ntau (2.4 GB): the last one
+    starts beyond 2^31 bytes. Rhs 0 and 8 carry Gaussian vectors, the others
+    zeros; sampled output slices of both (first, wrap-around, middle, last)
+    against the oracle's slice formula (Sec. 1, Eq. MatrixM)."""
+    require_gpu()
+    from paper_1008_3647_amd import Lattice
+    nx, nrhs = 16, 9
+    say(f"lowdim 32-bit offsets dim={dim} ntau={ntau} nrhs={nrhs}")
+    sigma = sigma_field(nx, ntau, 1300, dim)
+    x0 = gaussian_rhs(nx, ntau, [1301], dim)[0]
+    x8 = gaussian_rhs(nx, ntau, [1308], dim)[0]
+    assert 8 * x8.nbytes >= (1 << 31)
+    L = Lattice(nx, ntau, TAU, G, torch.complex128, dim=dim)
+    L.set_aux_field(to_dev(sigma))
+    xd = torch.zeros((nrhs,) + L.shape, dtype=torch.complex128, device="cuda")
+    xd[0] = to_dev(x0)
+    xd[8] = to_dev(x8)
+    y = L.apply_M(xd)
+    yd = L.apply_Mdag(xd)
+    A = oracle.coupling_A(TAU, G)
+    for r, x in ((0, x0), (8, x8)):
+        for t in (0, 1, ntau // 2, ntau - 2, ntau - 1):
+            tp, tn = (t - 1) % ntau, (t + 1) % ntau
+            sp = 1.0 if tp == ntau - 1 else -1.0
+            ref = x[t] + sp * op.apply_expK(oracle.field_b(sigma[tp], A) * x[tp], TAU, "free", dim)
+            assert rel_err(to_host(y[r, t]), ref) < TOL_OP[torch.complex128], (r, t)
+            st = 1.0 if t == ntau - 1 else -1.0
+            refd = x[t] + st * oracle.field_b(sigma[t], A) * op.apply_expK(x[tn], TAU, "free", dim)
+            assert rel_err(to_host(yd[r, t]), refd) < TOL_OP[torch.complex128], (r, t)
+    assert float(y[4].abs().max()) == 0.0
+    del xd, y, yd
+    L.close()
+    torch.cuda.empty_cache()
