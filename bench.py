@@ -942,9 +942,11 @@ def main():
     # Check interval of the unpreconditioned solve: a check point costs an
     # iteration in the unmerged form plus the gated reliable-update launches
     # (~0.1 ms at this size), while the loop stops at most two intervals late
-    # on launches that do nothing; 40 measured fastest of 10, 20, 40. The
-    # preconditioned solve (~80 iterations per step) keeps the default 10.
-    check_every = 40 if pc is None else 10
+    # on launches that do nothing; 40 measured fastest of 10, 20, 40, then 60
+    # 0.5 % faster than 40 at the same iteration counts (80 and 120 within
+    # 0.1 % of 60, 120 with 30 more iterations). The preconditioned solve
+    # (~80 iterations per step) keeps the default 10.
+    check_every = 60 if pc is None else 10
 
     def solve(mixed):
         return L.solve_bicgstab(b, "two_step", precond=pc, tol=tol, mixed=mixed, maxit=20000,
