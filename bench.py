@@ -945,7 +945,8 @@ def main():
     # on launches that do nothing; 40 measured fastest of 10, 20, 40, then 60
     # 0.5 % faster than 40 at the same iteration counts (80 and 120 within
     # 0.1 % of 60, 120 with 30 more iterations). The preconditioned solve
-    # (~80 iterations per step) keeps the default 10.
+    # (~80 iterations per step) keeps the default 10 (5 and 20 measured 0.6 %
+    # slower).
     check_every = 60 if pc is None else 10
 
     def solve(mixed):
