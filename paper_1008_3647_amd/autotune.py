@@ -84,14 +84,18 @@ def _time_solve(L, b, op, precond, mixed, iters, reps):
 
 def tune(L: Lattice, b: torch.Tensor, mixed=False, op="M", iters=16, reps=2,
          vec_blocks=(0, 32, 64, 128, 256, 512), orders=ORDERS,
-         cache: str | None = DEFAULT_CACHE, force=False, verbose=False, precond=None):
+         cache: str | None = DEFAULT_CACHE, force=False, verbose=False, precond=None,
+         finalists=3, refine_iters=100, refine_reps=2):
     """Pick the launch shape for solves of `b` on `L` (with `precond`, whose
     basis-change launches follow the same slab choice): slices per slab and
     workgroup numbering of the streaming kernels first (vector kernels at their
     default), then the workgroups per rhs of the vector kernels for that
-    choice. Returns a dict with the choice and the timings of every candidate."""
+    choice; the `finalists` fastest of all are timed again over
+    `refine_iters` iterations, `refine_reps` rounds in turn (the short runs
+    cannot separate shapes a few tenths of a per cent apart). Returns a dict
+    with the choice and the timings of every candidate."""
     nrhs = b.shape[0]
-    key = "v2|" + _key(L, nrhs, mixed, precond)
+    key = "v3|" + _key(L, nrhs, mixed, precond)
     data = _load(cache) if cache else {}
     if not force and key in data:
         best = data[key]
@@ -117,11 +121,31 @@ def tune(L: Lattice, b: torch.Tensor, mixed=False, op="M", iters=16, reps=2,
     for vb in vec_blocks:
         if vb != 0:
             run(first["slab"], vb, first["xcd_group"], first["rhs_inner"])
-    best = min(results, key=lambda d: d["seconds"])
+    final = sorted(results, key=lambda d: d["seconds"])[:max(1, finalists)]
+    if len(final) > 1 and refine_reps > 0:
+        for d in final:
+            d["refined"] = float("inf")
+        for _ in range(refine_reps):
+            for d in final:
+                L.tune(d["slab"], d["vec_blocks"], xcd_group=d["xcd_group"],
+                       rhs_inner=d["rhs_inner"])
+                d["refined"] = min(d["refined"], _time_solve(L, b, op, precond, mixed,
+                                                             refine_iters, 1))
+        if verbose:
+            for d in final:
+                print(f"tune refine slab={d['slab']} vec_blocks={d['vec_blocks']} "
+                      f"group={d['xcd_group']} rhs_inner={d['rhs_inner']}: "
+                      f"{d['refined'] * 1e3:.2f} ms", flush=True)
+        best = min(final, key=lambda d: d["refined"])
+    else:
+        best = final[0]
     L.tune(best["slab"], best["vec_blocks"], xcd_group=best["xcd_group"],
            rhs_inner=best["rhs_inner"])
     choice = {k: best[k] for k in ("slab", "vec_blocks", "xcd_group", "rhs_inner", "seconds")}
     choice["iters"] = iters
+    if "refined" in best:
+        choice["refined_seconds"] = best["refined"]
+        choice["refine_iters"] = refine_iters
     if cache:
         data[key] = choice
         _store(cache, data)

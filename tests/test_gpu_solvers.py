@@ -351,3 +351,34 @@ def test_solve_log_json_lines(tmp_path):
     assert recs[1]["relres"][0] == s2["relres"][0] and "sca" in recs[1]["precond"]
     assert recs[0]["lattice"] == dict(nx=nx, ntau=ntau, dim=3, dtype="complex128",
                                       dispersion="free", tau=TAU, g=G)
+
+
+def test_tune_picks_a_candidate_and_the_solve_converges():
+    """autotune.tune on an 8^3 x 40 lattice (FP32-refined, 2 rhs; no cache):
+    the short sweep over slab sizes, workgroup orders and vector workgroups,
+    then the finalists over longer runs; the choice is one of the candidates,
+    stays applied, and the two-step solve with it meets tol against the
+    oracle's residual."""
+    require_gpu()
+    from paper_1008_3647_amd import Lattice
+    from paper_1008_3647_amd.autotune import tune
+    nx, ntau = 8, 40
+    sigma = sigma_field(nx, ntau, 1400)
+    b = gaussian_rhs(nx, ntau, [1401, 1402])
+    L = Lattice(nx, ntau, TAU, G, torch.complex128)
+    L.set_aux_field(to_dev(sigma))
+    bd = to_dev(b)
+    ch = tune(L, bd, mixed=True, cache=None, vec_blocks=(0, 64), finalists=2,
+              refine_iters=20, refine_reps=2)
+    say(f"tune choice {ch['slab']} {ch['vec_blocks']} {ch['xcd_group']} {ch['rhs_inner']} "
+        f"refined {ch.get('refined_seconds')}")
+    shapes = [(c["slab"], c["vec_blocks"], c["xcd_group"], c["rhs_inner"])
+              for c in ch["candidates"]]
+    assert (ch["slab"], ch["vec_blocks"], ch["xcd_group"], ch["rhs_inner"]) in shapes
+    assert ch["refine_iters"] == 20 and ch["refined_seconds"] > 0
+    x, st = L.solve_bicgstab(bd, "two_step", tol=1e-10, mixed=True)
+    assert st["status"] == 0 and max(st["relres"]) <= 1e-10
+    xh = to_host(x)
+    for k in range(2):
+        r = b[k] - oracle.apply_Q(xh[k], sigma, TAU, G)
+        assert np.linalg.norm(r) / np.linalg.norm(b[k]) < 1e-7
